@@ -1,0 +1,156 @@
+/*
+ * ci.h -- C ABI of libci: construction of the sparse M-scheme many-body
+ * Hamiltonian of a Configuration Interaction / No-Core Shell Model calculation
+ * with a two-body interaction, on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the construction stage
+ * (Potter et al., "Accelerating Ab Initio Nuclear Physics Calculations with
+ * GPUs"):
+ *   - Sec. 2: the indexing systems of the many-body basis are set up first
+ *     (ci_basis_build); the symmetric matrix is generated and only half of it
+ *     is stored; each element is a linear combination of one-body (kinetic /
+ *     single-particle) and two-body interaction terms;
+ *   - Sec. 4.1: the matrix is split into chunks of similar quantum numbers; the
+ *     nonzeros are located twice, once to count them so that the arrays can be
+ *     allocated (ci_hamiltonian_count) and once to calculate and store them
+ *     (ci_hamiltonian_fill), in compressed-row (CSR) form;
+ *   - Sec. 5.2: all index tables are built contiguously on the host and moved
+ *     to the device in one allocation and one copy.
+ * ci_hamiltonian_vjp is the adjoint of the fill with respect to the two-body
+ * table (not in the paper).
+ *
+ * Conventions (the paper does not fix them; these are the textbook readings):
+ *   orbits   harmonic-oscillator m-states of shells 0..S, S = max(Ntop(Z),
+ *            Ntop(N)) + Nmax, ordered by N, l, 2j, 2m (ascending), the same
+ *            set for both species.  Single-particle energy (N + 3/2) hw.
+ *            Combined index: proton orbit k -> k, neutron orbit k -> n_sps + k.
+ *   basis    proton and neutron Slater determinants as n_words 64-bit words
+ *            (orbit k -> word k/64, bit k%64); a state is kept if its total
+ *            oscillator quanta Nq <= N0 + Nmax, (-1)^Nq = parity, and
+ *            sum 2m = two_m.  Species keys (Nq, 2M) ascending; blocks are the
+ *            compatible (proton key, neutron key) pairs in that order; inside a
+ *            key determinants ascend as unsigned integers (word n_words-1 most
+ *            significant); row = block offset + ip * |neutron key| + in.
+ *   two-body table (tbme): antisymmetrized V_{ab,cd}, a<b, c<d, one FP32 value
+ *            per unordered {(ab),(cd)}.  Sectors by class (pp, pn, nn), then
+ *            pair 2M, then pair parity; pairs lexicographic inside a sector and
+ *            kept only if N_a + N_b <= N0(Z,N) - N0(Z-z, N-n) + Nmax; entries are
+ *            the upper triangle, row-major.  ci_tbme_keys lists the keys.
+ *   CSR      upper triangle including the diagonal; (i, j) is stored iff
+ *            j >= i and the states differ in at most two nucleons, even when
+ *            the value is zero; columns ascend inside a row.  row_ptr int64,
+ *            col int32 (row index inside the basis), val FP32.  Diagonal and
+ *            one-nucleon-difference sums are accumulated in FP64.
+ *
+ * Batches: n_probs > 1 builds independent bases side by side.  Basis b owns
+ *   row_ptr[R_b .. R_b + D_b] with R_b = sum_{c<b} (D_c + 1); its values are
+ *   positions in the concatenated col/val arrays (so row_ptr[R_b] is the
+ *   number of entries of the bases before b).  tbme / grad_tbme of basis b
+ *   start at T_b = sum_{c<b} n_tbme_c.
+ *
+ * Memory: every array argument marked "device" is caller-owned device memory
+ * (for example a torch tensor on the GPU).  ci_basis_build allocates the index
+ * tables on the current device and keeps them in the handle until
+ * ci_basis_free.  No call keeps a pointer to a caller array after it returns.
+ * All launches go to the given stream (hipStream_t; NULL = the null stream).
+ *
+ * Errors: every call returns CI_OK (0) or a negative CI_E* code; the message
+ * of the last failure on the calling thread is ci_last_error().  Validation
+ * errors are reported before any device call.
+ */
+#ifndef CI_H
+#define CI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CI_OK 0
+#define CI_EINVAL (-1)       /* null pointer, bad problem, bad index          */
+#define CI_EUNSUPPORTED (-2) /* n_sps > 256 (more than 4 words), D >= 2^31,   */
+                             /* a two-body sector too large for the index     */
+#define CI_ESPACE (-3)       /* work buffer too small; sizes are in the info  */
+#define CI_EHIP (-4)         /* HIP runtime error (message in ci_last_error)  */
+
+typedef void* ci_stream; /* hipStream_t */
+
+/* One problem: Z protons, N neutrons, Nmax excitation quanta above the lowest
+ * filling, total 2M (two_m + Z + N must be even), parity +1 / -1, hw in MeV. */
+typedef struct {
+    int32_t Z, N, nmax, two_m, parity;
+    int32_t reserved;
+    double hw_mev;
+} ci_problem;
+
+/* Sizes of one basis (filled by ci_basis_plan / ci_basis_build). */
+typedef struct {
+    int32_t shell_max, n_sps, n_words, n0; /* S, orbits per species, words, N0 */
+    int32_t n_pkeys, n_nkeys, n_blocks, n_sectors;
+    int64_t n_psd, n_nsd; /* proton / neutron determinants */
+    int64_t dim;          /* D */
+    int64_t n_tbme;       /* two-body table length */
+    int64_t row_ptr_offset; /* R_b */
+    int64_t tbme_offset;    /* T_b */
+    int64_t index_bytes;    /* device bytes of this basis' index tables */
+    int64_t n_tasks;        /* row tiles of this basis */
+} ci_basis_info;
+
+typedef struct ci_basis ci_basis; /* opaque */
+
+/* Thread-local text of the last error. */
+const char* ci_last_error(void);
+
+/* Host only, no device call: validates the problems and fills info[n_probs]
+ * (the sizes that ci_basis_build will produce).  Sec. 2 (basis indexing). */
+int ci_basis_plan(const ci_problem* probs, int32_t n_probs, ci_basis_info* info);
+
+/* Host only: the two-body keys (a, b, c, d) of one problem in table order,
+ * abcd [n_tbme][4] int32 host memory with room for cap rows. */
+int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap);
+
+/* Builds the basis indexing (Sec. 2) of n_probs problems: enumerates the
+ * determinants, blocks, one- and two-nucleon partner lists and the two-body
+ * pair index on the host, then makes ONE device allocation and ONE copy
+ * (Sec. 5.2).  info[n_probs] is filled; *out receives the handle. */
+int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info,
+                   ci_basis** out, ci_stream stream);
+
+/* Frees the handle and its device tables (NULL is allowed). */
+void ci_basis_free(ci_basis* b);
+
+/* Count pass (Sec. 4.1): row_ptr (device, int64, sum_b (D_b + 1)) receives
+ * the CSR row offsets of every basis; nnz (host, int64[n_probs]) the number
+ * of stored entries per basis.  Synchronizes the stream (nnz is read back). */
+int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
+
+/* Fill pass (Sec. 2, Sec. 4.1): writes col (device int32) and val (device
+ * FP32) of every stored entry at the positions given by row_ptr (from
+ * ci_hamiltonian_count).  tbme: device FP32, concatenated tables.  Asynchronous. */
+int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row_ptr,
+                        int32_t* col, float* val, ci_stream stream);
+
+/* Adjoint of the fill with respect to the two-body table: for L = sum_e
+ * grad_val[e] * val[e], writes grad_tbme = dL/dtbme (device FP32, overwritten).
+ * The pair / phase structure is recomputed, not stored.  work: device scratch
+ * of at least ci_vjp_work_bytes(b) bytes (FP64 accumulators).  Asynchronous. */
+int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val,
+                       float* grad_tbme, void* work, size_t work_bytes, ci_stream stream);
+
+/* Bytes of work needed by ci_hamiltonian_vjp for this handle. */
+size_t ci_vjp_work_bytes(const ci_basis* b);
+
+/* Number of problems in the handle; info of problem `prob`. */
+int32_t ci_basis_count(const ci_basis* b);
+int ci_basis_get_info(const ci_basis* b, int32_t prob, ci_basis_info* info);
+
+/* Copies the basis states of problem `prob` to bits (device uint64
+ * [D][2 * n_words], proton words then neutron words).  Asynchronous. */
+int ci_basis_states(const ci_basis* b, int32_t prob, uint64_t* bits, ci_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CI_H */

@@ -1,0 +1,291 @@
+"""MI355X construction of M-scheme CI / No-Core Shell Model Hamiltonians.
+
+Thin Python binding of ``libci.so`` (C ABI in ``include/ci.h``).  Python only
+marshals arguments: device memory comes from torch tensors and every step of
+the construction runs in the library's HIP kernels.  There is no CPU fallback:
+if the library is missing or no GPU is visible, the calls raise.
+
+Entry points (same names as the C ABI):
+  ci_basis_plan(problems)                      sizes, host only
+  ci_tbme_keys(problem)                        two-body keys in table order, host only
+  ci_basis_build(problems) -> Basis            basis indexing (paper Sec. 2)
+  ci_hamiltonian_count(basis) -> (row_ptr, nnz)            count pass (Sec. 4.1)
+  ci_hamiltonian_fill(basis, tbme, row_ptr) -> (col, val)  fill pass (Sec. 2, 4.1)
+  ci_hamiltonian_vjp(basis, row_ptr, grad_val) -> grad_tbme  adjoint
+  CIHamiltonian.apply(tbme, basis, row_ptr, col) -> val      autograd wrapper
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libci.so")
+
+CI_OK, CI_EINVAL, CI_EUNSUPPORTED, CI_ESPACE, CI_EHIP = 0, -1, -2, -3, -4
+_ERRNAMES = {CI_EINVAL: "CI_EINVAL", CI_EUNSUPPORTED: "CI_EUNSUPPORTED", CI_ESPACE: "CI_ESPACE",
+             CI_EHIP: "CI_EHIP"}
+
+HW_MEV = 15.0
+
+
+class CIError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_ERRNAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class ci_problem(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_int32), ("N", ctypes.c_int32), ("nmax", ctypes.c_int32),
+                ("two_m", ctypes.c_int32), ("parity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hw_mev", ctypes.c_double)]
+
+
+class ci_basis_info(ctypes.Structure):
+    _fields_ = [("shell_max", ctypes.c_int32), ("n_sps", ctypes.c_int32), ("n_words", ctypes.c_int32),
+                ("n0", ctypes.c_int32), ("n_pkeys", ctypes.c_int32), ("n_nkeys", ctypes.c_int32),
+                ("n_blocks", ctypes.c_int32), ("n_sectors", ctypes.c_int32),
+                ("n_psd", ctypes.c_int64), ("n_nsd", ctypes.c_int64), ("dim", ctypes.c_int64),
+                ("n_tbme", ctypes.c_int64), ("row_ptr_offset", ctypes.c_int64),
+                ("tbme_offset", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
+                ("n_tasks", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# every symbol include/ci.h declares
+EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
+           "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
+           "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
+
+_lib = None
+
+
+def load_library():
+    """Load libci.so (built by ``paper_1412_5989_amd.build``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libci.so is not built (run `python -m paper_1412_5989_amd.build`)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.ci_last_error.restype = ctypes.c_char_p
+    L.ci_basis_plan.argtypes = [P(ci_problem), i32, P(ci_basis_info)]
+    L.ci_tbme_keys.argtypes = [P(ci_problem), vp, i64]
+    L.ci_basis_build.argtypes = [P(ci_problem), i32, P(ci_basis_info), P(vp), vp]
+    L.ci_basis_free.argtypes = [vp]
+    L.ci_basis_free.restype = None
+    L.ci_hamiltonian_count.argtypes = [vp, vp, vp, vp]
+    L.ci_hamiltonian_fill.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.ci_hamiltonian_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.ci_vjp_work_bytes.argtypes = [vp]
+    L.ci_vjp_work_bytes.restype = sz
+    L.ci_basis_count.argtypes = [vp]
+    L.ci_basis_count.restype = i32
+    L.ci_basis_get_info.argtypes = [vp, i32, P(ci_basis_info)]
+    L.ci_basis_states.argtypes = [vp, i32, vp, vp]
+    for name in EXPORTS:
+        if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != CI_OK:
+        raise CIError(rc, load_library().ci_last_error().decode())
+
+
+def _problems(problems) -> Tuple[ctypes.Array, int]:
+    if isinstance(problems, tuple) and problems and isinstance(problems[0], (int, np.integer)):
+        problems = [problems]
+    ps = list(problems)
+    arr = (ci_problem * len(ps))()
+    for k, p in enumerate(ps):
+        Z, N, nmax, two_m = (int(x) for x in p[:4])
+        parity = int(p[4]) if len(p) > 4 else 1
+        hw = float(p[5]) if len(p) > 5 else HW_MEV
+        arr[k] = ci_problem(Z, N, nmax, two_m, parity, 0, hw)
+    return arr, len(ps)
+
+
+def ci_basis_plan(problems) -> List[dict]:
+    """Sizes of each problem's basis (host only, no device call)."""
+    arr, n = _problems(problems)
+    info = (ci_basis_info * n)()
+    _check(load_library().ci_basis_plan(arr, n, info))
+    return [info[k].as_dict() for k in range(n)]
+
+
+def ci_tbme_keys(problem) -> np.ndarray:
+    """[n_tbme, 4] int32 two-body keys (a, b, c, d) in table order (host only)."""
+    arr, _ = _problems([problem])
+    n = ci_basis_plan([problem])[0]["n_tbme"]
+    out = np.zeros((max(n, 1), 4), np.int32)
+    _check(load_library().ci_tbme_keys(arr, out.ctypes.data_as(ctypes.c_void_p), n))
+    return out[:n]
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libci runs only on the device (no CPU fallback)")
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Basis:
+    """Handle of one or more bases built on the current device."""
+
+    def __init__(self, problems, stream=None):
+        torch = _torch()
+        arr, n = _problems(problems)
+        info = (ci_basis_info * n)()
+        h = ctypes.c_void_p()
+        _check(load_library().ci_basis_build(arr, n, info, ctypes.byref(h), _stream_ptr(stream)))
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.problems = [tuple(int(x) for x in (p.Z, p.N, p.nmax, p.two_m, p.parity)) for p in arr]
+        self.info = [info[k].as_dict() for k in range(n)]
+        self.n_probs = n
+        self.n_rowptr = sum(i["dim"] + 1 for i in self.info)
+        self.n_tbme = sum(i["n_tbme"] for i in self.info)
+        self.nnz = None  # per basis, after count
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ci_basis_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def vjp_work_bytes(self) -> int:
+        return int(load_library().ci_vjp_work_bytes(self._h))
+
+    def states(self, prob: int = 0):
+        torch = _torch()
+        i = self.info[prob]
+        out = torch.empty((i["dim"], 2 * i["n_words"]), dtype=torch.int64, device=self.device)
+        _check(load_library().ci_basis_states(self._h, prob, _ptr(out), _stream_ptr()))
+        return out
+
+    def row_ptr_slice(self, row_ptr, prob: int):
+        """row_ptr of one basis (values are positions in the concatenated arrays)."""
+        i = self.info[prob]
+        return row_ptr[i["row_ptr_offset"]: i["row_ptr_offset"] + i["dim"] + 1]
+
+
+def ci_basis_build(problems, stream=None) -> Basis:
+    return Basis(problems, stream)
+
+
+def ci_hamiltonian_count(basis: Basis, stream=None):
+    """Count pass: (row_ptr int64 device tensor, nnz list per basis)."""
+    torch = _torch()
+    row_ptr = torch.empty(basis.n_rowptr, dtype=torch.int64, device=basis.device)
+    nnz = np.zeros(basis.n_probs, np.int64)
+    _check(load_library().ci_hamiltonian_count(basis.handle, _ptr(row_ptr),
+                                               nnz.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+    basis.nnz = [int(x) for x in nnz]
+    return row_ptr, basis.nnz
+
+
+def _check_tensor(t, dtype, n, name):
+    torch = _torch()
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous %s CUDA tensor of %d elements" % (name, dtype, n))
+
+
+def ci_hamiltonian_fill(basis: Basis, tbme, row_ptr, col=None, val=None, stream=None):
+    """Fill pass: (col int32, val float32) device tensors of all stored entries."""
+    torch = _torch()
+    if basis.nnz is None:
+        raise RuntimeError("call ci_hamiltonian_count first")
+    tot = sum(basis.nnz)
+    _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    if col is None:
+        col = torch.empty(tot, dtype=torch.int32, device=basis.device)
+    if val is None:
+        val = torch.empty(tot, dtype=torch.float32, device=basis.device)
+    _check_tensor(col, torch.int32, tot, "col")
+    _check_tensor(val, torch.float32, tot, "val")
+    _check(load_library().ci_hamiltonian_fill(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                              _stream_ptr(stream)))
+    return col, val
+
+
+def ci_hamiltonian_vjp(basis: Basis, row_ptr, grad_val, grad_tbme=None, work=None, stream=None):
+    """Adjoint: grad_tbme (float32 device) = d(sum grad_val * val)/d tbme."""
+    torch = _torch()
+    tot = sum(basis.nnz)
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    _check_tensor(grad_val, torch.float32, tot, "grad_val")
+    if grad_tbme is None:
+        grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
+    nwork = basis.vjp_work_bytes()
+    if work is None:
+        work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
+    _check(load_library().ci_hamiltonian_vjp(basis.handle, _ptr(row_ptr), _ptr(grad_val), _ptr(grad_tbme),
+                                             _ptr(work), work.numel() * work.element_size(),
+                                             _stream_ptr(stream)))
+    return grad_tbme
+
+
+def _make_autograd():
+    import torch
+
+    class CIHamiltonian(torch.autograd.Function):
+        """val = H(tbme) on a fixed structure; backward runs the adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, tbme, basis, row_ptr, col=None):
+            _, val = ci_hamiltonian_fill(basis, tbme.detach().contiguous(), row_ptr, col=col)
+            ctx.basis = basis
+            ctx.save_for_backward(row_ptr)
+            return val
+
+        @staticmethod
+        def backward(ctx, gval):
+            (row_ptr,) = ctx.saved_tensors
+            g = ci_hamiltonian_vjp(ctx.basis, row_ptr, gval.contiguous().to(torch.float32))
+            return g, None, None, None
+
+    return CIHamiltonian
+
+
+class _Lazy:
+    def __init__(self):
+        self._cls = None
+
+    def __getattr__(self, k):
+        if self._cls is None:
+            self._cls = _make_autograd()
+        return getattr(self._cls, k)
+
+
+CIHamiltonian = _Lazy()

@@ -1,0 +1,419 @@
+// C ABI of libci (declared in include/ci.h): validation, the basis handle,
+// the single device allocation of the index tables, and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ci_internal.h"
+
+namespace ci {
+hipError_t launch_count(const BasisDev* bases, const Task* tasks, int64_t ntasks, int64_t* row_ptr,
+                        int64_t nrp, const int64_t* seg_first, int nseg, int64_t* scan_tmp,
+                        hipStream_t s);
+hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_t* last, int64_t* nnz,
+                      int n, hipStream_t s);
+hipError_t launch_fill(const BasisDev* bases, const Task* tasks, int64_t ntasks, const float* tbme,
+                       const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, hipStream_t s);
+hipError_t launch_vjp(const BasisDev* bases, const Task* tasks, int64_t ntasks, const int64_t* row_ptr,
+                      int64_t nrp, const float* gval, float* gtbme, double* gacc, int64_t ntbme,
+                      hipStream_t s);
+}  // namespace ci
+
+using namespace ci;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* where)
+{
+    return fail(CI_EHIP, std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+struct ci_basis {
+    int device = 0;
+    std::vector<ci_basis_info> info;
+    std::vector<std::shared_ptr<HostBasis>> host;  // per problem (shared for equal problems)
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    BasisDev* d_bases = nullptr;
+    Task* d_tasks = nullptr;
+    int64_t ntasks = 0;
+    int64_t* d_seg_first = nullptr;  // R_b
+    int64_t* d_seg_last = nullptr;   // R_b + D_b
+    int64_t* d_scan_tmp = nullptr;
+    int64_t* d_nnz = nullptr;
+    int64_t n_rowptr = 0;
+    int64_t n_tbme = 0;
+};
+
+namespace {
+
+// Bump layout of the arena (256-byte aligned pieces); the same walk computes
+// the size (base == nullptr) and fills a host mirror.
+struct Layout {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        size_t o = off;
+        off += count * sizeof(T);
+        return o;
+    }
+};
+
+using Key = std::tuple<int, int, int, int, int, double>;
+
+Key key_of(const ci_problem& p) { return Key(p.Z, p.N, p.nmax, p.two_m, p.parity, p.hw_mev); }
+
+void fill_info(const HostBasis& hb, ci_basis_info& in)
+{
+    std::memset(&in, 0, sizeof in);
+    in.shell_max = hb.S;
+    in.n_sps = hb.nsps;
+    in.n_words = hb.W;
+    in.n0 = hb.N0;
+    in.n_pkeys = hb.sp[0].nk();
+    in.n_nkeys = hb.sp[1].nk();
+    in.n_blocks = hb.nblk();
+    in.n_sectors = (int32_t)hb.sec_n.size();
+    in.n_psd = hb.sp[0].nsd();
+    in.n_nsd = hb.sp[1].nsd();
+    in.dim = hb.dim;
+    in.n_tbme = hb.n_tbme;
+    in.n_tasks = (int64_t)hb.tasks.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ci_last_error(void) { return g_err.c_str(); }
+
+int ci_basis_plan(const ci_problem* probs, int32_t n_probs, ci_basis_info* info)
+{
+    if (!probs || !info || n_probs <= 0) return fail(CI_EINVAL, "null pointer or n_probs <= 0");
+    std::string err;
+    int64_t R = 0, T = 0;
+    for (int32_t b = 0; b < n_probs; b++) {
+        HostBasis hb;
+        int rc = plan_basis(probs[b], hb, err);
+        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
+        fill_info(hb, info[b]);
+        info[b].row_ptr_offset = R;
+        info[b].tbme_offset = T;
+        info[b].index_bytes = -1;  // known after the partner lists are built
+        R += hb.dim + 1;
+        T += hb.n_tbme;
+    }
+    return CI_OK;
+}
+
+int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap)
+{
+    if (!prob || (!abcd && cap > 0)) return fail(CI_EINVAL, "null pointer");
+    std::string err;
+    HostBasis hb;
+    int rc = plan_basis(*prob, hb, err);
+    if (rc != CI_OK) return fail(rc, err);
+    if (cap < hb.n_tbme) return fail(CI_ESPACE, "need room for " + std::to_string(hb.n_tbme) + " keys");
+    std::vector<int32_t> k;
+    tbme_keys(hb, k);
+    std::memcpy(abcd, k.data(), k.size() * sizeof(int32_t));
+    return CI_OK;
+}
+
+int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info, ci_basis** out,
+                   ci_stream stream)
+{
+    if (!probs || !info || !out || n_probs <= 0) return fail(CI_EINVAL, "null pointer or n_probs <= 0");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<ci_basis> h(new ci_basis());
+    std::string err;
+    // host construction; equal problems share one set of index tables
+    std::map<Key, int> uniq;
+    std::vector<int> which(n_probs);
+    std::vector<std::shared_ptr<HostBasis>> ub;
+    for (int32_t b = 0; b < n_probs; b++) {
+        int rc = validate_problem(probs[b], err);
+        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
+        auto it = uniq.find(key_of(probs[b]));
+        if (it != uniq.end()) {
+            which[b] = it->second;
+            continue;
+        }
+        auto hb = std::make_shared<HostBasis>();
+        rc = build_basis(probs[b], *hb, err);
+        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
+        which[b] = (int)ub.size();
+        uniq[key_of(probs[b])] = which[b];
+        ub.push_back(hb);
+    }
+
+    // arena layout: per unique basis its tables, then per problem a BasisDev,
+    // then the tasks and the small count-pass buffers
+    Layout L;
+    struct SpOff { size_t sd, key_off, l1_ptr, l12_ptr, l1, l12, seg1, seg12, self12; };
+    struct UOff { SpOff sp[2]; size_t blk_kp, blk_kn, blk_off, pair, sec_off, sec_n, orb_n; size_t bytes; };
+    std::vector<UOff> uo(ub.size());
+    for (size_t u = 0; u < ub.size(); u++) {
+        const HostBasis& hb = *ub[u];
+        size_t start = L.off;
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const HostSpecies& sp = hb.sp[sidx];
+            SpOff& o = uo[u].sp[sidx];
+            o.sd = L.take<uint64_t>(sp.sd.size());
+            o.key_off = L.take<int32_t>(sp.key_off.size());
+            o.l1_ptr = L.take<int64_t>(sp.l1_ptr.size());
+            o.l12_ptr = L.take<int64_t>(sp.l12_ptr.size());
+            o.l1 = L.take<uint64_t>(sp.l1.size());
+            o.l12 = L.take<uint64_t>(sp.l12.size());
+            o.seg1 = L.take<int32_t>(sp.seg1.size());
+            o.seg12 = L.take<int32_t>(sp.seg12.size());
+            o.self12 = L.take<int32_t>(sp.self12.size());
+        }
+        uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
+        uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
+        uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
+        uo[u].pair = L.take<uint32_t>(hb.pair.size());
+        uo[u].sec_off = L.take<int64_t>(hb.sec_off.size());
+        uo[u].sec_n = L.take<int32_t>(hb.sec_n.size());
+        uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
+        uo[u].bytes = L.off - start;
+    }
+    int64_t ntasks = 0, R = 0, T = 0;
+    for (int32_t b = 0; b < n_probs; b++) {
+        const HostBasis& hb = *ub[which[b]];
+        ntasks += (int64_t)hb.tasks.size();
+        R += hb.dim + 1;
+        T += hb.n_tbme;
+    }
+    const int64_t nb_scan = (R + 4095) / 4096 + 1;
+    const size_t o_bases = L.take<BasisDev>(n_probs);
+    const size_t o_tasks = L.take<Task>(std::max<int64_t>(ntasks, 1));
+    const size_t o_first = L.take<int64_t>(n_probs);
+    const size_t o_last = L.take<int64_t>(n_probs);
+    const size_t o_scan = L.take<int64_t>(nb_scan);
+    const size_t o_nnz = L.take<int64_t>(n_probs);
+    const size_t bytes = (L.off + 255) & ~size_t(255);
+
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipMalloc(&h->arena, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(index arena)");
+    h->arena_bytes = bytes;
+    char* dev = (char*)h->arena;
+
+    // host mirror of the arena; device pointers are the arena base plus the
+    // offsets of the layout (the tables are relocated once, then copied once)
+    std::vector<char> mirror(bytes, 0);
+    auto put = [&](size_t off, const void* src, size_t n) {
+        if (n) std::memcpy(mirror.data() + off, src, n);
+    };
+    std::vector<BasisDev> ud(ub.size());
+    for (size_t u = 0; u < ub.size(); u++) {
+        const HostBasis& hb = *ub[u];
+        BasisDev& d = ud[u];
+        std::memset(&d, 0, sizeof d);
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const HostSpecies& sp = hb.sp[sidx];
+            const SpOff& o = uo[u].sp[sidx];
+            put(o.sd, sp.sd.data(), sp.sd.size() * 8);
+            put(o.key_off, sp.key_off.data(), sp.key_off.size() * 4);
+            put(o.l1_ptr, sp.l1_ptr.data(), sp.l1_ptr.size() * 8);
+            put(o.l12_ptr, sp.l12_ptr.data(), sp.l12_ptr.size() * 8);
+            put(o.l1, sp.l1.data(), sp.l1.size() * 8);
+            put(o.l12, sp.l12.data(), sp.l12.size() * 8);
+            put(o.seg1, sp.seg1.data(), sp.seg1.size() * 4);
+            put(o.seg12, sp.seg12.data(), sp.seg12.size() * 4);
+            put(o.self12, sp.self12.data(), sp.self12.size() * 4);
+            SpeciesDev& sd = d.sp[sidx];
+            sd.sd = (const uint64_t*)(dev + o.sd);
+            sd.key_off = (const int32_t*)(dev + o.key_off);
+            sd.l1_ptr = (const int64_t*)(dev + o.l1_ptr);
+            sd.l12_ptr = (const int64_t*)(dev + o.l12_ptr);
+            sd.l1 = (const uint64_t*)(dev + o.l1);
+            sd.l12 = (const uint64_t*)(dev + o.l12);
+            sd.seg1 = (const int32_t*)(dev + o.seg1);
+            sd.seg12 = (const int32_t*)(dev + o.seg12);
+            sd.self12 = (const int32_t*)(dev + o.self12);
+            sd.nsd = (int32_t)sp.nsd();
+            sd.nk = sp.nk();
+        }
+        put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
+        put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
+        put(uo[u].blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
+        put(uo[u].pair, hb.pair.data(), hb.pair.size() * 4);
+        put(uo[u].sec_off, hb.sec_off.data(), hb.sec_off.size() * 8);
+        put(uo[u].sec_n, hb.sec_n.data(), hb.sec_n.size() * 4);
+        put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
+        d.blk_kp = (const int32_t*)(dev + uo[u].blk_kp);
+        d.blk_kn = (const int32_t*)(dev + uo[u].blk_kn);
+        d.blk_off = (const int64_t*)(dev + uo[u].blk_off);
+        d.pair = (const uint32_t*)(dev + uo[u].pair);
+        d.sec_off = (const int64_t*)(dev + uo[u].sec_off);
+        d.sec_n = (const int32_t*)(dev + uo[u].sec_n);
+        d.orb_n = (const int32_t*)(dev + uo[u].orb_n);
+        d.dim = hb.dim;
+        d.W = hb.W;
+        d.nsps = hb.nsps;
+        d.nblk = hb.nblk();
+        d.nsec = (int32_t)hb.sec_n.size();
+        d.Z = hb.prob.Z;
+        d.NN = hb.prob.N;
+        d.hw = hb.prob.hw_mev;
+    }
+    std::vector<BasisDev> bd(n_probs);
+    std::vector<Task> tasks;
+    tasks.reserve(ntasks);
+    std::vector<int64_t> first(n_probs), last(n_probs);
+    R = 0;
+    T = 0;
+    h->info.resize(n_probs);
+    for (int32_t b = 0; b < n_probs; b++) {
+        const HostBasis& hb = *ub[which[b]];
+        bd[b] = ud[which[b]];
+        bd[b].row0 = R;
+        bd[b].tbme0 = T;
+        for (Task t : hb.tasks) {
+            t.basis = b;
+            tasks.push_back(t);
+        }
+        fill_info(hb, info[b]);
+        info[b].row_ptr_offset = R;
+        info[b].tbme_offset = T;
+        info[b].index_bytes = (int64_t)uo[which[b]].bytes;
+        h->info[b] = info[b];
+        first[b] = R;
+        last[b] = R + hb.dim;
+        R += hb.dim + 1;
+        T += hb.n_tbme;
+        h->host.push_back(ub[which[b]]);
+    }
+    put(o_bases, bd.data(), bd.size() * sizeof(BasisDev));
+    put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
+    put(o_first, first.data(), first.size() * 8);
+    put(o_last, last.data(), last.size() * 8);
+    h->d_bases = (BasisDev*)(dev + o_bases);
+    h->d_tasks = (Task*)(dev + o_tasks);
+    h->d_seg_first = (int64_t*)(dev + o_first);
+    h->d_seg_last = (int64_t*)(dev + o_last);
+    h->d_scan_tmp = (int64_t*)(dev + o_scan);
+    h->d_nnz = (int64_t*)(dev + o_nnz);
+    h->ntasks = ntasks;
+    h->n_rowptr = R;
+    h->n_tbme = T;
+
+    e = hipMemcpyAsync(h->arena, mirror.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index arena)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    // the partner lists are on the device now; keep only what the host needs
+    for (auto& hb : ub)
+        for (int sidx = 0; sidx < 2; sidx++) {
+            HostSpecies& sp = hb->sp[sidx];
+            std::vector<uint64_t>().swap(sp.l1);
+            std::vector<uint64_t>().swap(sp.l12);
+            std::vector<int32_t>().swap(sp.seg1);
+            std::vector<int32_t>().swap(sp.seg12);
+        }
+    *out = h.release();
+    return CI_OK;
+}
+
+void ci_basis_free(ci_basis* b)
+{
+    if (!b) return;
+    if (b->arena) hipFree(b->arena);
+    delete b;
+}
+
+int32_t ci_basis_count(const ci_basis* b) { return b ? (int32_t)b->info.size() : 0; }
+
+int ci_basis_get_info(const ci_basis* b, int32_t prob, ci_basis_info* info)
+{
+    if (!b || !info) return fail(CI_EINVAL, "null pointer");
+    if (prob < 0 || prob >= (int32_t)b->info.size()) return fail(CI_EINVAL, "problem index out of range");
+    *info = b->info[prob];
+    return CI_OK;
+}
+
+int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)b->info.size();
+    hipError_t e = launch_count(b->d_bases, b->d_tasks, b->ntasks, row_ptr, b->n_rowptr, b->d_seg_first, n,
+                                b->d_scan_tmp, s);
+    if (e != hipSuccess) return hip_fail(e, "count launch");
+    e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
+    if (e != hipSuccess) return hip_fail(e, "nnz launch");
+    e = hipMemcpyAsync(nnz, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(nnz)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(count)");
+    return CI_OK;
+}
+
+int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                        float* val, ci_stream stream)
+{
+    if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    hipError_t e = launch_fill(b->d_bases, b->d_tasks, b->ntasks, tbme, row_ptr, b->n_rowptr, col, val,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fill launch");
+    return CI_OK;
+}
+
+size_t ci_vjp_work_bytes(const ci_basis* b) { return b ? (size_t)b->n_tbme * sizeof(double) : 0; }
+
+int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
+                       void* work, size_t work_bytes, ci_stream stream)
+{
+    if (!b || !row_ptr || !grad_val) return fail(CI_EINVAL, "null pointer");
+    if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
+    if (work_bytes < ci_vjp_work_bytes(b))
+        return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
+    hipError_t e = launch_vjp(b->d_bases, b->d_tasks, b->ntasks, row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work,
+                              b->n_tbme, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "vjp launch");
+    return CI_OK;
+}
+
+int ci_basis_states(const ci_basis* b, int32_t prob, uint64_t* bits, ci_stream stream)
+{
+    if (!b || !bits) return fail(CI_EINVAL, "null pointer");
+    if (prob < 0 || prob >= (int32_t)b->info.size()) return fail(CI_EINVAL, "problem index out of range");
+    const HostBasis& hb = *b->host[prob];
+    const int W = hb.W;
+    std::vector<uint64_t> st((size_t)hb.dim * 2 * W);
+    int64_t i = 0;
+    for (int bk = 0; bk < hb.nblk(); bk++) {
+        const HostSpecies& P = hb.sp[0];
+        const HostSpecies& N = hb.sp[1];
+        for (int64_t p = P.key_off[hb.blk_kp[bk]]; p < P.key_off[hb.blk_kp[bk] + 1]; p++)
+            for (int64_t q = N.key_off[hb.blk_kn[bk]]; q < N.key_off[hb.blk_kn[bk] + 1]; q++, i++) {
+                std::memcpy(&st[(size_t)i * 2 * W], &P.sd[p * W], W * 8);
+                std::memcpy(&st[(size_t)i * 2 * W + W], &N.sd[q * W], W * 8);
+            }
+    }
+    hipError_t e = hipMemcpyAsync(bits, st.data(), st.size() * 8, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(states)");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(states)");
+    return CI_OK;
+}
+
+}  // extern "C"

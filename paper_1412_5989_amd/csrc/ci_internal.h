@@ -1,0 +1,123 @@
+// Internal definitions shared by the host index builder, the C ABI and the
+// HIP kernels of libci.  Not part of the public interface (include/ci.h).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ci.h"
+
+namespace ci {
+
+constexpr int kMaxWords = 4;   // n_sps <= 256 per species
+constexpr int kTileRows = 64;  // rows of one task = one wavefront, one lane per row
+
+// ---------------------------------------------------------------------------
+// Partner record of a species determinant x: one y with d(x, y) <= 2, where
+// d is the number of orbits occupied in x and not in y.  Row-side orbits
+// ("particles", in x not y) are p1 < p2; column-side orbits ("holes", in y not
+// x) are h1 < h2.  The sign is the species-local fermion phase of the
+// Slater-Condon element <x..|H|y..> (one- and two-nucleon moves).
+//   bits  0..23  local index of y inside its species key
+//   bits 24..31  h1    bits 32..39  p1    bits 40..47  h2    bits 48..55  p2
+//   bit  56      phase is -1
+//   bits 57..58  d (0, 1, 2)
+// ---------------------------------------------------------------------------
+constexpr uint64_t kRecLocalMask = (1ull << 24) - 1;
+
+inline uint64_t make_rec(uint32_t ylocal, int d, int h1, int p1, int h2, int p2, bool neg)
+{
+    return (uint64_t)ylocal | ((uint64_t)(h1 & 255) << 24) | ((uint64_t)(p1 & 255) << 32) |
+           ((uint64_t)(h2 & 255) << 40) | ((uint64_t)(p2 & 255) << 48) |
+           ((uint64_t)(neg ? 1 : 0) << 56) | ((uint64_t)d << 57);
+}
+
+// two-body pair index entry: (sector << 16) | position of the pair in the sector
+constexpr uint32_t kNoPair = 0xffffffffu;
+
+// ---------------------------------------------------------------------------
+// Device view of one species (all pointers into the basis arena).
+// ---------------------------------------------------------------------------
+struct SpeciesDev {
+    const uint64_t* sd;      // [nsd][W]
+    const int32_t* key_off;  // [nk + 1] first global index of each key
+    const int64_t* l1_ptr;   // [nsd + 1] start of the d<=1 list of x
+    const int64_t* l12_ptr;  // [nsd + 1] start of the d<=2 list of x
+    const uint64_t* l1;      // d<=1 partners (self included), all keys, y ascending
+    const uint64_t* l12;     // d<=2 partners in keys of the same 2M and Nq parity
+    const int32_t* seg1;     // [nsd][nk + 1] first record of each key in l1(x)
+    const int32_t* seg12;    // [nsd][nk + 1] same for l12(x)
+    const int32_t* self12;   // [nsd] position of x itself inside its own key segment of l12(x)
+    int32_t nsd, nk;
+};
+
+struct BasisDev {
+    SpeciesDev sp[2];          // 0 = protons, 1 = neutrons
+    const int32_t* blk_kp;     // [nblk]
+    const int32_t* blk_kn;     // [nblk]
+    const int64_t* blk_off;    // [nblk + 1] first row of each block
+    const uint32_t* pair;      // [3][n][n] pp, pn, nn pair index (species-local orbits)
+    const int64_t* sec_off;    // [nsec] first table entry of each sector
+    const int32_t* sec_n;      // [nsec] pairs in each sector
+    const int32_t* orb_n;      // [n] oscillator shell of each orbit
+    int64_t dim;               // D
+    int64_t row0;              // R_b: this basis' segment of row_ptr
+    int64_t tbme0;             // T_b: this basis' slice of the two-body table
+    int32_t W, nsps, nblk, nsec, Z, NN;
+    double hw;
+};
+
+// One task = one wavefront = up to 64 consecutive rows of one block: rows
+// blk_off[block] + r0 + lane for lane < nrows.  Row r of a block is the pair
+// (ip, in) = (r / |Kn|, r % |Kn|).  Tasks start on a row-group boundary (a
+// row group = the |Kn| rows of one proton determinant); a large group is cut
+// into 64-row pieces, small groups are packed whole.
+struct Task {
+    int32_t basis, block, r0, nrows;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side tables of one basis.
+// ---------------------------------------------------------------------------
+struct HostSpecies {
+    int X = 0;                      // particles
+    int budget = 0;                 // largest Nq of one determinant
+    std::vector<int32_t> key_nq, key_m2;
+    std::vector<int32_t> key_off;   // nk + 1
+    std::vector<uint64_t> sd;       // nsd * W
+    std::vector<int32_t> sd_key;    // nsd
+    std::vector<int64_t> l1_ptr, l12_ptr;
+    std::vector<uint64_t> l1, l12;
+    std::vector<int32_t> seg1, seg12, self12;
+    int nk() const { return (int)key_nq.size(); }
+    int64_t nsd() const { return (int64_t)sd_key.size(); }
+};
+
+struct HostBasis {
+    ci_problem prob{};
+    int S = 0, nsps = 0, W = 0, N0 = 0, N0p = 0, N0n = 0;
+    std::vector<int32_t> orb_n, orb_l, orb_j2, orb_m2;  // species-local orbits
+    HostSpecies sp[2];
+    std::vector<int32_t> blk_kp, blk_kn;
+    std::vector<int64_t> blk_off;
+    int64_t dim = 0;
+    std::vector<int64_t> sec_off;
+    std::vector<int32_t> sec_n;
+    std::vector<uint32_t> pair;  // 3 * n * n
+    int64_t n_tbme = 0;
+    std::vector<Task> tasks;     // basis field filled by the batch builder
+    int nblk() const { return (int)blk_kp.size(); }
+};
+
+// host_basis.cpp
+int validate_problem(const ci_problem& p, std::string& err);
+// Sizes only (no partner lists): orbits, species, keys, blocks, table sectors.
+int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err);
+// Everything, including partner lists and tasks.
+int build_basis(const ci_problem& p, HostBasis& hb, std::string& err);
+// Two-body keys (a, b, c, d) in table order.
+void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd);
+
+}  // namespace ci
