@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark: Hamiltonian nonzeros per second on one MI355X.
+
+One step is the whole construction path for one problem, starting from the
+problem description and the two-body table resident in HBM:
+    ci_basis_build  (basis indexing, one upload)
+    ci_hamiltonian_count (count + scan; one sync to read nnz)
+    ci_hamiltonian_fill  (col/val of every stored entry)
+    ci_hamiltonian_vjp   (adjoint onto the table, upstream G_e = psi_i psi_j)
+value = nnz / (seconds per step).  The default workload is 6Li, Nmax = 6,
+2M = 2, positive parity (D = 186,894, 55.5 M stored entries).
+
+The JSON line also carries per-stage times, the roofline of the dominant
+kernel (timed with HIP events on the stream it runs on), the batched mode (64
+bases, one persistent graph-captured launch) and the FP64 oracle timed on the
+host cores on a bounded sample of rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ensure_library():
+    import paper_1412_5989_amd as ci
+
+    if not os.path.exists(ci.LIB_PATH):
+        from paper_1412_5989_amd import build
+
+        build.build_library()
+    ci.load_library()
+    return ci
+
+
+class EventTimer:
+    """Accumulates HIP-event durations of one kernel family on one stream."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.pairs = torch, stream, []
+
+    def __enter__(self):
+        self.a = self.torch.cuda.Event(enable_timing=True)
+        self.b = self.torch.cuda.Event(enable_timing=True)
+        self.a.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record(self.stream)
+        self.pairs.append((self.a, self.b))
+
+    def mean_ms(self):
+        self.torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs])) if self.pairs else 0.0
+
+
+def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=12.0):
+    """The FP64 oracle on sampled rows: forward rows + their gradient."""
+    import oracle
+    import seeded_inputs as si
+
+    o = oracle.Oracle(oracle.Problem(*problem))
+    o.set_tbme(si.tbme_f32(tbme_seed, o.n_tbme).astype(np.float64))
+    ps = si.psi(psi_seed, o.dim)
+
+    def run(nrows, seed):
+        rows = si.sample_rows(o.dim, nrows, seed)
+        t0 = time.perf_counter()
+        counts, cols, _ = o.rows(rows)
+        G = si.upstream_grad(ps, np.repeat(rows, counts), cols).astype(np.float64)
+        o.grad_rows(rows, G)
+        return int(counts.sum()), time.perf_counter() - t0, len(rows)
+
+    n, t, _ = run(64, 1)
+    nrows = int(min(o.dim, max(64, 64 * budget_s / max(t, 1e-3))))
+    n, t, nr = run(nrows, 2)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": n / t,
+        "unit": "nonzeros/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d sampled rows of the same workload (%d stored entries), row scan + values on %d "
+                  "OpenMP threads, gradient of those rows on 1 thread, %.1f s" % (nr, n, threads, t),
+    }
+
+
+def run_batched(ci, torch, steps, warmup):
+    """64 bases in one handle; fill + vjp captured in one HIP graph."""
+    import seeded_inputs as si
+
+    probs, tseeds, pseeds = si.batch_problems()
+    t0 = time.perf_counter()
+    b = ci.ci_basis_build(probs)
+    rp, nnz = ci.ci_hamiltonian_count(b)
+    t_setup = time.perf_counter() - t0
+    tb = torch.from_numpy(np.concatenate([si.tbme_f32(s, i["n_tbme"]) for s, i in zip(tseeds, b.info)])).cuda()
+    tot = int(sum(nnz))
+    col = torch.empty(tot, dtype=torch.int32, device="cuda")
+    val = torch.empty(tot, dtype=torch.float32, device="cuda")
+    G = torch.empty(tot, dtype=torch.float32, device="cuda")
+    ci.ci_hamiltonian_fill(b, tb, rp, col, val)
+    # upstream psi_i psi_j per basis, built on the device from the structure
+    rpc = rp.cpu().numpy()
+    for k, i in enumerate(b.info):
+        seg = rpc[i["row_ptr_offset"]: i["row_ptr_offset"] + i["dim"] + 1]
+        ps = torch.from_numpy(si.psi(pseeds[k], i["dim"])).cuda()
+        rows = torch.repeat_interleave(torch.arange(i["dim"], device="cuda"),
+                                       torch.from_numpy(np.diff(seg)).cuda())
+        G[seg[0]: seg[-1]] = (ps[rows] * ps[col[seg[0]: seg[-1]].long()]).float()
+    gt = torch.empty(b.n_tbme, dtype=torch.float32, device="cuda")
+    work = torch.empty(b.vjp_work_bytes(), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            ci.ci_hamiltonian_fill(b, tb, rp, col, val)
+            ci.ci_hamiltonian_vjp(b, rp, G, gt, work)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ci.ci_hamiltonian_fill(b, tb, rp, col, val)
+        ci.ci_hamiltonian_vjp(b, rp, G, gt, work)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        g.replay()
+    e.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / steps
+    out = {"bases": len(probs), "dim_total": int(sum(i["dim"] for i in b.info)), "nnz_total": tot,
+           "ms_per_replay": ms, "nnz_per_s": tot / (ms * 1e-3), "setup_s": t_setup,
+           "graph": "fill + vjp of all bases, one capture"}
+    b.free()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="li6_nmax6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the construction path here runs on a single "
+              "MI355X (multi-GPU sharding is described in the design notes, not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import seeded_inputs as si
+
+    ci = ensure_library()
+    w = si.WORKLOADS[args.workload]
+    prob = w["problem"]
+    stream = torch.cuda.current_stream()
+
+    # inputs resident in HBM before the timed region: the two-body table and
+    # the upstream gradient (which needs the structure, so one setup pass)
+    log("setup", args.workload, prob)
+    b = ci.ci_basis_build([prob])
+    rp, nnz = ci.ci_hamiltonian_count(b)
+    nnz = nnz[0]
+    D = b.info[0]["dim"]
+    n_tbme = b.n_tbme
+    tbme = torch.from_numpy(si.tbme_f32(w["tbme_seed"], n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian_fill(b, tbme, rp)
+    rows = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp))
+    ps = torch.from_numpy(si.psi(si.PSI_SEED.get(args.workload, 0), D)).cuda()
+    G = (ps[rows] * ps[col.long()]).float()
+    del rows
+    b.free()
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    gt = torch.empty(n_tbme, dtype=torch.float32, device="cuda")
+    work = torch.empty(8 * n_tbme, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    t_basis, t_count = [], []
+    ev_fill, ev_vjp = EventTimer(torch, stream), EventTimer(torch, stream)
+
+    def step(timed):
+        t0 = time.perf_counter()
+        h = ci.ci_basis_build([prob])
+        t1 = time.perf_counter()
+        r, n = ci.ci_hamiltonian_count(h)
+        t2 = time.perf_counter()
+        if timed:
+            t_basis.append(t1 - t0)
+            t_count.append(t2 - t1)
+            with ev_fill:
+                ci.ci_hamiltonian_fill(h, tbme, r, col, val)
+            with ev_vjp:
+                ci.ci_hamiltonian_vjp(h, r, G, gt, work)
+        else:
+            ci.ci_hamiltonian_fill(h, tbme, r, col, val)
+            ci.ci_hamiltonian_vjp(h, r, G, gt, work)
+        torch.cuda.synchronize()
+        h.free()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+
+    fill_ms = ev_fill.mean_ms()
+    vjp_ms = ev_vjp.mean_ms()
+    # dominant kernel: the fill writes 8 B per stored entry (int32 col + FP32
+    # val) and reads 8 B per row of row_ptr; that is its algorithmic traffic
+    dom, dom_ms = ("fill", fill_ms) if fill_ms >= vjp_ms else ("vjp", vjp_ms)
+    if dom == "fill":
+        alg_bytes = 8 * nnz + 8 * (D + 1)
+    else:  # reads 4 B of upstream gradient per entry + row_ptr, writes the table
+        alg_bytes = 4 * nnz + 8 * (D + 1) + 4 * n_tbme
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    res = {
+        "metric": "Hamiltonian nonzeros/sec (fwd, adjoint, batched) + roofline fraction, 1 MI355X",
+        "value": nnz / sec,
+        "unit": "nonzeros/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f32 (f64 accumulation)",
+        "data": "synthetic: seeded N(0,1) MeV two-body table, seeded psi for the upstream gradient",
+        "config": {"workload": args.workload, "Z": prob[0], "N": prob[1], "nmax": prob[2],
+                   "two_m": prob[3], "parity": prob[4], "dim": D, "nnz": nnz, "n_tbme": n_tbme,
+                   "step": "basis build + count/scan + fill + vjp"},
+        "stages_ms": {"basis_build": 1e3 * float(np.mean(t_basis)), "count_scan_sync": 1e3 * float(np.mean(t_count)),
+                      "fill": fill_ms, "vjp": vjp_ms},
+        "fwd_nnz_per_s": nnz / (fill_ms * 1e-3),
+        "adjoint_nnz_per_s": nnz / (vjp_ms * 1e-3),
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_batched:
+        log("batched")
+        res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(prob, w["tbme_seed"], si.PSI_SEED.get(args.workload, 0))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
