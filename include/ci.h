@@ -95,7 +95,6 @@ typedef struct {
     int64_t row_ptr_offset; /* R_b */
     int64_t tbme_offset;    /* T_b */
     int64_t index_bytes;    /* device bytes of this basis' index tables */
-    int64_t n_tasks;        /* row tiles of this basis */
 } ci_basis_info;
 
 typedef struct ci_basis ci_basis; /* opaque */

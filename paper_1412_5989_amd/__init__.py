@@ -50,8 +50,7 @@ class ci_basis_info(ctypes.Structure):
                 ("n_blocks", ctypes.c_int32), ("n_sectors", ctypes.c_int32),
                 ("n_psd", ctypes.c_int64), ("n_nsd", ctypes.c_int64), ("dim", ctypes.c_int64),
                 ("n_tbme", ctypes.c_int64), ("row_ptr_offset", ctypes.c_int64),
-                ("tbme_offset", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
-                ("n_tasks", ctypes.c_int64)]
+                ("tbme_offset", ctypes.c_int64), ("index_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -13,16 +13,17 @@
 #include "ci_internal.h"
 
 namespace ci {
-hipError_t launch_count(const BasisDev* bases, const Task* tasks, int64_t ntasks, int64_t* row_ptr,
-                        int64_t nrp, const int64_t* seg_first, int nseg, int64_t* scan_tmp,
+hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
+                        int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
                         hipStream_t s);
 hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_t* last, int64_t* nnz,
                       int n, hipStream_t s);
-hipError_t launch_fill(const BasisDev* bases, const Task* tasks, int64_t ntasks, const float* tbme,
-                       const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, hipStream_t s);
-hipError_t launch_vjp(const BasisDev* bases, const Task* tasks, int64_t ntasks, const int64_t* row_ptr,
-                      int64_t nrp, const float* gval, float* gtbme, double* gacc, int64_t ntbme,
-                      hipStream_t s);
+hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
+                       const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
+                       hipStream_t s);
+hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
+                      const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
+                      int64_t ntbme, hipStream_t s);
 }  // namespace ci
 
 using namespace ci;
@@ -47,8 +48,8 @@ struct ci_basis {
     void* arena = nullptr;
     size_t arena_bytes = 0;
     BasisDev* d_bases = nullptr;
-    Task* d_tasks = nullptr;
-    int64_t ntasks = 0;
+    int64_t* d_basis_row0 = nullptr;  // first global row of each basis, [n + 1]
+    int64_t nrows = 0;                // sum of the dimensions
     int64_t* d_seg_first = nullptr;  // R_b
     int64_t* d_seg_last = nullptr;   // R_b + D_b
     int64_t* d_scan_tmp = nullptr;
@@ -92,7 +93,6 @@ void fill_info(const HostBasis& hb, ci_basis_info& in)
     in.n_nsd = hb.sp[1].nsd();
     in.dim = hb.dim;
     in.n_tbme = hb.n_tbme;
-    in.n_tasks = (int64_t)hb.tasks.size();
 }
 
 }  // namespace
@@ -163,7 +163,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     }
 
     // arena layout: per unique basis its tables, then per problem a BasisDev,
-    // then the tasks and the small count-pass buffers
+    // then the row table and the small count-pass buffers
     Layout L;
     struct SpOff { size_t sd, key_off, l1_ptr, l12_ptr, l1, l12, seg1, seg12, self12; };
     struct UOff { SpOff sp[2]; size_t blk_kp, blk_kn, blk_off, pair, sec_off, sec_n, orb_n; size_t bytes; };
@@ -193,16 +193,15 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
         uo[u].bytes = L.off - start;
     }
-    int64_t ntasks = 0, R = 0, T = 0;
+    int64_t R = 0, T = 0;
     for (int32_t b = 0; b < n_probs; b++) {
         const HostBasis& hb = *ub[which[b]];
-        ntasks += (int64_t)hb.tasks.size();
         R += hb.dim + 1;
         T += hb.n_tbme;
     }
     const int64_t nb_scan = (R + 4095) / 4096 + 1;
     const size_t o_bases = L.take<BasisDev>(n_probs);
-    const size_t o_tasks = L.take<Task>(std::max<int64_t>(ntasks, 1));
+    const size_t o_row0 = L.take<int64_t>(n_probs + 1);
     const size_t o_first = L.take<int64_t>(n_probs);
     const size_t o_last = L.take<int64_t>(n_probs);
     const size_t o_scan = L.take<int64_t>(nb_scan);
@@ -276,9 +275,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.hw = hb.prob.hw_mev;
     }
     std::vector<BasisDev> bd(n_probs);
-    std::vector<Task> tasks;
-    tasks.reserve(ntasks);
-    std::vector<int64_t> first(n_probs), last(n_probs);
+    std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
     R = 0;
     T = 0;
     h->info.resize(n_probs);
@@ -287,10 +284,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         bd[b] = ud[which[b]];
         bd[b].row0 = R;
         bd[b].tbme0 = T;
-        for (Task t : hb.tasks) {
-            t.basis = b;
-            tasks.push_back(t);
-        }
+        row0[b + 1] = row0[b] + hb.dim;
         fill_info(hb, info[b]);
         info[b].row_ptr_offset = R;
         info[b].tbme_offset = T;
@@ -303,16 +297,16 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         h->host.push_back(ub[which[b]]);
     }
     put(o_bases, bd.data(), bd.size() * sizeof(BasisDev));
-    put(o_tasks, tasks.data(), tasks.size() * sizeof(Task));
+    put(o_row0, row0.data(), row0.size() * 8);
     put(o_first, first.data(), first.size() * 8);
     put(o_last, last.data(), last.size() * 8);
     h->d_bases = (BasisDev*)(dev + o_bases);
-    h->d_tasks = (Task*)(dev + o_tasks);
+    h->d_basis_row0 = (int64_t*)(dev + o_row0);
     h->d_seg_first = (int64_t*)(dev + o_first);
     h->d_seg_last = (int64_t*)(dev + o_last);
     h->d_scan_tmp = (int64_t*)(dev + o_scan);
     h->d_nnz = (int64_t*)(dev + o_nnz);
-    h->ntasks = ntasks;
+    h->nrows = row0[n_probs];
     h->n_rowptr = R;
     h->n_tbme = T;
 
@@ -355,7 +349,7 @@ int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_s
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)b->info.size();
-    hipError_t e = launch_count(b->d_bases, b->d_tasks, b->ntasks, row_ptr, b->n_rowptr, b->d_seg_first, n,
+    hipError_t e = launch_count(b->d_bases, n, b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, b->d_seg_first,
                                 b->d_scan_tmp, s);
     if (e != hipSuccess) return hip_fail(e, "count launch");
     e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
@@ -371,8 +365,8 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
                         float* val, ci_stream stream)
 {
     if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
-    hipError_t e = launch_fill(b->d_bases, b->d_tasks, b->ntasks, tbme, row_ptr, b->n_rowptr, col, val,
-                               (hipStream_t)stream);
+    hipError_t e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr,
+                               b->n_rowptr, col, val, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     return CI_OK;
 }
@@ -386,8 +380,8 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
-    hipError_t e = launch_vjp(b->d_bases, b->d_tasks, b->ntasks, row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work,
-                              b->n_tbme, (hipStream_t)stream);
+    hipError_t e = launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr,
+                              grad_val, grad_tbme, (double*)work, b->n_tbme, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "vjp launch");
     return CI_OK;
 }

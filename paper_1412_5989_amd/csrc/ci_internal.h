@@ -12,7 +12,6 @@
 namespace ci {
 
 constexpr int kMaxWords = 4;   // n_sps <= 256 per species
-constexpr int kTileRows = 64;  // rows of one task = one wavefront, one lane per row
 
 // ---------------------------------------------------------------------------
 // Partner record of a species determinant x: one y with d(x, y) <= 2, where
@@ -69,14 +68,6 @@ struct BasisDev {
     double hw;
 };
 
-// One task = one wavefront = up to 64 consecutive rows of one block: rows
-// blk_off[block] + r0 + lane for lane < nrows.  Row r of a block is the pair
-// (ip, in) = (r / |Kn|, r % |Kn|).  Tasks start on a row-group boundary (a
-// row group = the |Kn| rows of one proton determinant); a large group is cut
-// into 64-row pieces, small groups are packed whole.
-struct Task {
-    int32_t basis, block, r0, nrows;
-};
 
 // ---------------------------------------------------------------------------
 // Host-side tables of one basis.
@@ -107,7 +98,6 @@ struct HostBasis {
     std::vector<int32_t> sec_n;
     std::vector<uint32_t> pair;  // 3 * n * n
     int64_t n_tbme = 0;
-    std::vector<Task> tasks;     // basis field filled by the batch builder
     int nblk() const { return (int)blk_kp.size(); }
 };
 
@@ -115,7 +105,7 @@ struct HostBasis {
 int validate_problem(const ci_problem& p, std::string& err);
 // Sizes only (no partner lists): orbits, species, keys, blocks, table sectors.
 int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err);
-// Everything, including partner lists and tasks.
+// Everything, including the partner lists.
 int build_basis(const ci_problem& p, HostBasis& hb, std::string& err);
 // Two-body keys (a, b, c, d) in table order.
 void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd);

@@ -7,7 +7,7 @@
 // by (Nq, 2M) key; the compatible key blocks and row offsets; for every
 // species determinant its one- and two-nucleon partner lists with the moved
 // orbits and the fermion phase; the sector / pair index of the two-body table;
-// and the row tiles handed to the kernels.
+// all flat, for a single upload.
 #include <algorithm>
 #include <array>
 #include <cstring>
@@ -449,20 +449,6 @@ int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
     if (rc != CI_OK) return rc;
     rc = make_tbme_index(hb, err);
     if (rc != CI_OK) return rc;
-    hb.tasks.clear();
-    for (int b = 0; b < hb.nblk(); b++) {
-        const int np = hb.sp[0].key_off[hb.blk_kp[b] + 1] - hb.sp[0].key_off[hb.blk_kp[b]];
-        const int nn = hb.sp[1].key_off[hb.blk_kn[b] + 1] - hb.sp[1].key_off[hb.blk_kn[b]];
-        if (nn >= kTileRows / 2) {
-            for (int ip = 0; ip < np; ip++)
-                for (int in0 = 0; in0 < nn; in0 += kTileRows)
-                    hb.tasks.push_back({0, b, ip * nn + in0, std::min(kTileRows, nn - in0)});
-        } else {
-            const int per = kTileRows / nn;  // whole row groups per task
-            for (int ip = 0; ip < np; ip += per)
-                hb.tasks.push_back({0, b, ip * nn, std::min(per, np - ip) * nn});
-        }
-    }
     return CI_OK;
 }
 
