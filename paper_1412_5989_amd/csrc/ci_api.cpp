@@ -1,5 +1,5 @@
 // C ABI of libci (declared in include/ci.h): validation, the basis handle,
-// the single device allocation of the index tables, and the launches.
+// the device index tables, and the launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +24,10 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
 hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                       const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
                       int64_t ntbme, hipStream_t s);
+hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
+hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
+hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
+hipError_t launch_partner_fill(const PartnerArgs& a, hipStream_t s);
 }  // namespace ci
 
 using namespace ci;
@@ -45,23 +49,28 @@ struct ci_basis {
     int device = 0;
     std::vector<ci_basis_info> info;
     std::vector<std::shared_ptr<HostBasis>> host;  // per problem (shared for equal problems)
-    void* arena = nullptr;
-    size_t arena_bytes = 0;
+    void* arena = nullptr;                         // index tables
+    void* lists = nullptr;                         // partner lists
+    size_t arena_bytes = 0, list_bytes = 0;
     BasisDev* d_bases = nullptr;
     int64_t* d_basis_row0 = nullptr;  // first global row of each basis, [n + 1]
     int64_t nrows = 0;                // sum of the dimensions
-    int64_t* d_seg_first = nullptr;  // R_b
-    int64_t* d_seg_last = nullptr;   // R_b + D_b
+    int64_t* d_seg_first = nullptr;   // R_b
+    int64_t* d_seg_last = nullptr;    // R_b + D_b
     int64_t* d_scan_tmp = nullptr;
     int64_t* d_nnz = nullptr;
     int64_t n_rowptr = 0;
     int64_t n_tbme = 0;
+    ~ci_basis()
+    {
+        if (arena) hipFree(arena);
+        if (lists) hipFree(lists);
+    }
 };
 
 namespace {
 
-// Bump layout of the arena (256-byte aligned pieces); the same walk computes
-// the size (base == nullptr) and fills a host mirror.
+// Bump layout (256-byte aligned pieces) of one device allocation.
 struct Layout {
     size_t off = 0;
     template <typename T>
@@ -72,6 +81,7 @@ struct Layout {
         off += count * sizeof(T);
         return o;
     }
+    size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
 using Key = std::tuple<int, int, int, int, int, double>;
@@ -94,6 +104,16 @@ void fill_info(const HostBasis& hb, ci_basis_info& in)
     in.dim = hb.dim;
     in.n_tbme = hb.n_tbme;
 }
+
+// offsets of one species' tables in the arena
+struct SpOff {
+    size_t sd, sd_key, key_off, key_nq, key_m2, l1_ptr, l12_ptr, seg1, seg12, self12;
+};
+struct UOff {
+    SpOff sp[2];
+    size_t blk_kp, blk_kn, blk_off, pair, sec_off, sec_n, orb_n, totals;
+    size_t bytes;
+};
 
 }  // namespace
 
@@ -142,7 +162,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     hipStream_t s = (hipStream_t)stream;
     std::unique_ptr<ci_basis> h(new ci_basis());
     std::string err;
-    // host construction; equal problems share one set of index tables
+    // host tables; equal problems share one set of device tables
     std::map<Key, int> uniq;
     std::vector<int> which(n_probs);
     std::vector<std::shared_ptr<HostBasis>> ub;
@@ -155,34 +175,35 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             continue;
         }
         auto hb = std::make_shared<HostBasis>();
-        rc = build_basis(probs[b], *hb, err);
+        rc = plan_basis(probs[b], *hb, err);
         if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
         which[b] = (int)ub.size();
         uniq[key_of(probs[b])] = which[b];
         ub.push_back(hb);
     }
 
-    // arena layout: per unique basis its tables, then per problem a BasisDev,
-    // then the row table and the small count-pass buffers
+    // ---- allocation 1: index tables, per-problem descriptors, small buffers
     Layout L;
-    struct SpOff { size_t sd, key_off, l1_ptr, l12_ptr, l1, l12, seg1, seg12, self12; };
-    struct UOff { SpOff sp[2]; size_t blk_kp, blk_kn, blk_off, pair, sec_off, sec_n, orb_n; size_t bytes; };
     std::vector<UOff> uo(ub.size());
+    int64_t max_scan = 1;
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
         size_t start = L.off;
         for (int sidx = 0; sidx < 2; sidx++) {
             const HostSpecies& sp = hb.sp[sidx];
             SpOff& o = uo[u].sp[sidx];
+            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
             o.sd = L.take<uint64_t>(sp.sd.size());
-            o.key_off = L.take<int32_t>(sp.key_off.size());
-            o.l1_ptr = L.take<int64_t>(sp.l1_ptr.size());
-            o.l12_ptr = L.take<int64_t>(sp.l12_ptr.size());
-            o.l1 = L.take<uint64_t>(sp.l1.size());
-            o.l12 = L.take<uint64_t>(sp.l12.size());
-            o.seg1 = L.take<int32_t>(sp.seg1.size());
-            o.seg12 = L.take<int32_t>(sp.seg12.size());
-            o.self12 = L.take<int32_t>(sp.self12.size());
+            o.sd_key = L.take<int32_t>(nsd);
+            o.key_off = L.take<int32_t>(nk + 1);
+            o.key_nq = L.take<int32_t>(nk);
+            o.key_m2 = L.take<int32_t>(nk);
+            o.l1_ptr = L.take<int64_t>(nsd + 1);
+            o.l12_ptr = L.take<int64_t>(nsd + 1);
+            o.seg1 = L.take<int32_t>(nsd * (nk + 1));
+            o.seg12 = L.take<int32_t>(nsd * (nk + 1));
+            o.self12 = L.take<int32_t>(nsd);
+            max_scan = std::max<int64_t>(max_scan, (int64_t)nsd + 1);
         }
         uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
         uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
@@ -191,65 +212,46 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].sec_off = L.take<int64_t>(hb.sec_off.size());
         uo[u].sec_n = L.take<int32_t>(hb.sec_n.size());
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
+        uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
         uo[u].bytes = L.off - start;
     }
     int64_t R = 0, T = 0;
     for (int32_t b = 0; b < n_probs; b++) {
-        const HostBasis& hb = *ub[which[b]];
-        R += hb.dim + 1;
-        T += hb.n_tbme;
+        R += ub[which[b]]->dim + 1;
+        T += ub[which[b]]->n_tbme;
     }
-    const int64_t nb_scan = (R + 4095) / 4096 + 1;
+    max_scan = std::max(max_scan, R);
     const size_t o_bases = L.take<BasisDev>(n_probs);
     const size_t o_row0 = L.take<int64_t>(n_probs + 1);
     const size_t o_first = L.take<int64_t>(n_probs);
     const size_t o_last = L.take<int64_t>(n_probs);
-    const size_t o_scan = L.take<int64_t>(nb_scan);
+    const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
     const size_t o_nnz = L.take<int64_t>(n_probs);
-    const size_t bytes = (L.off + 255) & ~size_t(255);
+    const size_t bytes = L.bytes();
 
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     e = hipMalloc(&h->arena, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(index arena)");
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(index tables)");
     h->arena_bytes = bytes;
     char* dev = (char*)h->arena;
+    auto D = [&](size_t off) { return (void*)(dev + off); };
 
-    // host mirror of the arena; device pointers are the arena base plus the
-    // offsets of the layout (the tables are relocated once, then copied once)
+    // host mirror; device pointers are the arena base plus the layout offsets
     std::vector<char> mirror(bytes, 0);
     auto put = [&](size_t off, const void* src, size_t n) {
         if (n) std::memcpy(mirror.data() + off, src, n);
     };
-    std::vector<BasisDev> ud(ub.size());
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
-        BasisDev& d = ud[u];
-        std::memset(&d, 0, sizeof d);
         for (int sidx = 0; sidx < 2; sidx++) {
             const HostSpecies& sp = hb.sp[sidx];
             const SpOff& o = uo[u].sp[sidx];
             put(o.sd, sp.sd.data(), sp.sd.size() * 8);
+            put(o.sd_key, sp.sd_key.data(), sp.sd_key.size() * 4);
             put(o.key_off, sp.key_off.data(), sp.key_off.size() * 4);
-            put(o.l1_ptr, sp.l1_ptr.data(), sp.l1_ptr.size() * 8);
-            put(o.l12_ptr, sp.l12_ptr.data(), sp.l12_ptr.size() * 8);
-            put(o.l1, sp.l1.data(), sp.l1.size() * 8);
-            put(o.l12, sp.l12.data(), sp.l12.size() * 8);
-            put(o.seg1, sp.seg1.data(), sp.seg1.size() * 4);
-            put(o.seg12, sp.seg12.data(), sp.seg12.size() * 4);
-            put(o.self12, sp.self12.data(), sp.self12.size() * 4);
-            SpeciesDev& sd = d.sp[sidx];
-            sd.sd = (const uint64_t*)(dev + o.sd);
-            sd.key_off = (const int32_t*)(dev + o.key_off);
-            sd.l1_ptr = (const int64_t*)(dev + o.l1_ptr);
-            sd.l12_ptr = (const int64_t*)(dev + o.l12_ptr);
-            sd.l1 = (const uint64_t*)(dev + o.l1);
-            sd.l12 = (const uint64_t*)(dev + o.l12);
-            sd.seg1 = (const int32_t*)(dev + o.seg1);
-            sd.seg12 = (const int32_t*)(dev + o.seg12);
-            sd.self12 = (const int32_t*)(dev + o.self12);
-            sd.nsd = (int32_t)sp.nsd();
-            sd.nk = sp.nk();
+            put(o.key_nq, sp.key_nq.data(), sp.key_nq.size() * 4);
+            put(o.key_m2, sp.key_m2.data(), sp.key_m2.size() * 4);
         }
         put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
         put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
@@ -258,14 +260,119 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         put(uo[u].sec_off, hb.sec_off.data(), hb.sec_off.size() * 8);
         put(uo[u].sec_n, hb.sec_n.data(), hb.sec_n.size() * 4);
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
-        d.blk_kp = (const int32_t*)(dev + uo[u].blk_kp);
-        d.blk_kn = (const int32_t*)(dev + uo[u].blk_kn);
-        d.blk_off = (const int64_t*)(dev + uo[u].blk_off);
-        d.pair = (const uint32_t*)(dev + uo[u].pair);
-        d.sec_off = (const int64_t*)(dev + uo[u].sec_off);
-        d.sec_n = (const int32_t*)(dev + uo[u].sec_n);
-        d.orb_n = (const int32_t*)(dev + uo[u].orb_n);
+    }
+    std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
+    R = 0;
+    for (int32_t b = 0; b < n_probs; b++) {
+        const HostBasis& hb = *ub[which[b]];
+        first[b] = R;
+        last[b] = R + hb.dim;
+        row0[b + 1] = row0[b] + hb.dim;
+        R += hb.dim + 1;
+    }
+    put(o_row0, row0.data(), row0.size() * 8);
+    put(o_first, first.data(), first.size() * 8);
+    put(o_last, last.data(), last.size() * 8);
+    e = hipMemcpyAsync(h->arena, mirror.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index tables)");
+
+    // ---- partner lists on the device: count, scan, read the lengths back
+    auto args = [&](size_t u, int sidx) {
+        const HostSpecies& sp = ub[u]->sp[sidx];
+        const SpOff& o = uo[u].sp[sidx];
+        PartnerArgs a{};
+        a.sd = (const uint64_t*)D(o.sd);
+        a.sd_key = (const int32_t*)D(o.sd_key);
+        a.key_off = (const int32_t*)D(o.key_off);
+        a.key_nq = (const int32_t*)D(o.key_nq);
+        a.key_m2 = (const int32_t*)D(o.key_m2);
+        a.l1_ptr = (int64_t*)D(o.l1_ptr);
+        a.l12_ptr = (int64_t*)D(o.l12_ptr);
+        a.seg1 = (int32_t*)D(o.seg1);
+        a.seg12 = (int32_t*)D(o.seg12);
+        a.self12 = (int32_t*)D(o.self12);
+        a.nsd = (int32_t)sp.nsd();
+        a.nk = sp.nk();
+        a.W = ub[u]->W;
+        return a;
+    };
+    int64_t* scan_tmp = (int64_t*)D(o_scan);
+    for (size_t u = 0; u < ub.size(); u++)
+        for (int sidx = 0; sidx < 2; sidx++) {
+            PartnerArgs a = args(u, sidx);
+            if ((e = launch_partner_count(a, s)) != hipSuccess) return hip_fail(e, "partner count");
+            // l*_ptr[0] is 0 from the mirror; the inclusive scan gives offsets
+            if ((e = launch_inclusive_scan(a.l1_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess ||
+                (e = launch_inclusive_scan(a.l12_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess)
+                return hip_fail(e, "partner scan");
+            int64_t* tot = (int64_t*)D(uo[u].totals);
+            if ((e = launch_copy_i64(a.l1_ptr + a.nsd, tot + 2 * sidx, s)) != hipSuccess ||
+                (e = launch_copy_i64(a.l12_ptr + a.nsd, tot + 2 * sidx + 1, s)) != hipSuccess)
+                return hip_fail(e, "partner totals");
+        }
+    std::vector<int64_t> totals(4 * ub.size());
+    for (size_t u = 0; u < ub.size(); u++) {
+        e = hipMemcpyAsync(&totals[4 * u], D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(list lengths)");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(partner count)");
+
+    // ---- allocation 2: the partner lists; fill them
+    Layout LL;
+    std::vector<size_t> lo1(2 * ub.size()), lo12(2 * ub.size());
+    for (size_t u = 0; u < ub.size(); u++)
+        for (int sidx = 0; sidx < 2; sidx++) {
+            lo1[2 * u + sidx] = LL.take<uint64_t>(std::max<int64_t>(totals[4 * u + 2 * sidx], 1));
+            lo12[2 * u + sidx] = LL.take<uint64_t>(std::max<int64_t>(totals[4 * u + 2 * sidx + 1], 1));
+        }
+    e = hipMalloc(&h->lists, LL.bytes());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(partner lists)");
+    h->list_bytes = LL.bytes();
+    char* ldev = (char*)h->lists;
+    for (size_t u = 0; u < ub.size(); u++)
+        for (int sidx = 0; sidx < 2; sidx++) {
+            PartnerArgs a = args(u, sidx);
+            a.l1 = (uint64_t*)(ldev + lo1[2 * u + sidx]);
+            a.l12 = (uint64_t*)(ldev + lo12[2 * u + sidx]);
+            if ((e = launch_partner_fill(a, s)) != hipSuccess) return hip_fail(e, "partner fill");
+        }
+
+    // ---- per-problem descriptors
+    std::vector<BasisDev> bd(n_probs);
+    R = 0;
+    T = 0;
+    h->info.resize(n_probs);
+    for (int32_t b = 0; b < n_probs; b++) {
+        const size_t u = (size_t)which[b];
+        const HostBasis& hb = *ub[u];
+        BasisDev& d = bd[b];
+        std::memset(&d, 0, sizeof d);
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const SpOff& o = uo[u].sp[sidx];
+            SpeciesDev& sd = d.sp[sidx];
+            sd.sd = (const uint64_t*)D(o.sd);
+            sd.key_off = (const int32_t*)D(o.key_off);
+            sd.l1_ptr = (const int64_t*)D(o.l1_ptr);
+            sd.l12_ptr = (const int64_t*)D(o.l12_ptr);
+            sd.l1 = (const uint64_t*)(ldev + lo1[2 * u + sidx]);
+            sd.l12 = (const uint64_t*)(ldev + lo12[2 * u + sidx]);
+            sd.seg1 = (const int32_t*)D(o.seg1);
+            sd.seg12 = (const int32_t*)D(o.seg12);
+            sd.self12 = (const int32_t*)D(o.self12);
+            sd.nsd = (int32_t)hb.sp[sidx].nsd();
+            sd.nk = hb.sp[sidx].nk();
+        }
+        d.blk_kp = (const int32_t*)D(uo[u].blk_kp);
+        d.blk_kn = (const int32_t*)D(uo[u].blk_kn);
+        d.blk_off = (const int64_t*)D(uo[u].blk_off);
+        d.pair = (const uint32_t*)D(uo[u].pair);
+        d.sec_off = (const int64_t*)D(uo[u].sec_off);
+        d.sec_n = (const int32_t*)D(uo[u].sec_n);
+        d.orb_n = (const int32_t*)D(uo[u].orb_n);
         d.dim = hb.dim;
+        d.row0 = R;
+        d.tbme0 = T;
         d.W = hb.W;
         d.nsps = hb.nsps;
         d.nblk = hb.nblk();
@@ -273,66 +380,37 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.Z = hb.prob.Z;
         d.NN = hb.prob.N;
         d.hw = hb.prob.hw_mev;
-    }
-    std::vector<BasisDev> bd(n_probs);
-    std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
-    R = 0;
-    T = 0;
-    h->info.resize(n_probs);
-    for (int32_t b = 0; b < n_probs; b++) {
-        const HostBasis& hb = *ub[which[b]];
-        bd[b] = ud[which[b]];
-        bd[b].row0 = R;
-        bd[b].tbme0 = T;
-        row0[b + 1] = row0[b] + hb.dim;
         fill_info(hb, info[b]);
         info[b].row_ptr_offset = R;
         info[b].tbme_offset = T;
-        info[b].index_bytes = (int64_t)uo[which[b]].bytes;
+        int64_t lb = 0;
+        for (int sidx = 0; sidx < 2; sidx++)
+            lb += 8 * (totals[4 * u + 2 * sidx] + totals[4 * u + 2 * sidx + 1]);
+        info[b].index_bytes = (int64_t)uo[u].bytes + lb;
         h->info[b] = info[b];
-        first[b] = R;
-        last[b] = R + hb.dim;
+        h->host.push_back(ub[u]);
         R += hb.dim + 1;
         T += hb.n_tbme;
-        h->host.push_back(ub[which[b]]);
     }
-    put(o_bases, bd.data(), bd.size() * sizeof(BasisDev));
-    put(o_row0, row0.data(), row0.size() * 8);
-    put(o_first, first.data(), first.size() * 8);
-    put(o_last, last.data(), last.size() * 8);
-    h->d_bases = (BasisDev*)(dev + o_bases);
-    h->d_basis_row0 = (int64_t*)(dev + o_row0);
-    h->d_seg_first = (int64_t*)(dev + o_first);
-    h->d_seg_last = (int64_t*)(dev + o_last);
-    h->d_scan_tmp = (int64_t*)(dev + o_scan);
-    h->d_nnz = (int64_t*)(dev + o_nnz);
+    e = hipMemcpyAsync(D(o_bases), bd.data(), bd.size() * sizeof(BasisDev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
+    h->d_bases = (BasisDev*)D(o_bases);
+    h->d_basis_row0 = (int64_t*)D(o_row0);
+    h->d_seg_first = (int64_t*)D(o_first);
+    h->d_seg_last = (int64_t*)D(o_last);
+    h->d_scan_tmp = scan_tmp;
+    h->d_nnz = (int64_t*)D(o_nnz);
     h->nrows = row0[n_probs];
     h->n_rowptr = R;
     h->n_tbme = T;
-
-    e = hipMemcpyAsync(h->arena, mirror.data(), bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index arena)");
+    // the host buffers of the copies go out of scope at return
     e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    // the partner lists are on the device now; keep only what the host needs
-    for (auto& hb : ub)
-        for (int sidx = 0; sidx < 2; sidx++) {
-            HostSpecies& sp = hb->sp[sidx];
-            std::vector<uint64_t>().swap(sp.l1);
-            std::vector<uint64_t>().swap(sp.l12);
-            std::vector<int32_t>().swap(sp.seg1);
-            std::vector<int32_t>().swap(sp.seg12);
-        }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(basis build)");
     *out = h.release();
     return CI_OK;
 }
 
-void ci_basis_free(ci_basis* b)
-{
-    if (!b) return;
-    if (b->arena) hipFree(b->arena);
-    delete b;
-}
+void ci_basis_free(ci_basis* b) { delete b; }
 
 int32_t ci_basis_count(const ci_basis* b) { return b ? (int32_t)b->info.size() : 0; }
 

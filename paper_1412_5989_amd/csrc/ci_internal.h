@@ -9,6 +9,12 @@
 
 #include "ci.h"
 
+#ifdef __HIPCC__
+#define CI_HD __host__ __device__
+#else
+#define CI_HD
+#endif
+
 namespace ci {
 
 constexpr int kMaxWords = 4;   // n_sps <= 256 per species
@@ -26,7 +32,7 @@ constexpr int kMaxWords = 4;   // n_sps <= 256 per species
 // ---------------------------------------------------------------------------
 constexpr uint64_t kRecLocalMask = (1ull << 24) - 1;
 
-inline uint64_t make_rec(uint32_t ylocal, int d, int h1, int p1, int h2, int p2, bool neg)
+CI_HD inline uint64_t make_rec(uint32_t ylocal, int d, int h1, int p1, int h2, int p2, bool neg)
 {
     return (uint64_t)ylocal | ((uint64_t)(h1 & 255) << 24) | ((uint64_t)(p1 & 255) << 32) |
            ((uint64_t)(h2 & 255) << 40) | ((uint64_t)(p2 & 255) << 48) |
@@ -79,9 +85,6 @@ struct HostSpecies {
     std::vector<int32_t> key_off;   // nk + 1
     std::vector<uint64_t> sd;       // nsd * W
     std::vector<int32_t> sd_key;    // nsd
-    std::vector<int64_t> l1_ptr, l12_ptr;
-    std::vector<uint64_t> l1, l12;
-    std::vector<int32_t> seg1, seg12, self12;
     int nk() const { return (int)key_nq.size(); }
     int64_t nsd() const { return (int64_t)sd_key.size(); }
 };
@@ -101,12 +104,28 @@ struct HostBasis {
     int nblk() const { return (int)blk_kp.size(); }
 };
 
+// Arguments of the device partner-list kernels (basis_kernels.hip), one species.
+struct PartnerArgs {
+    const uint64_t* sd;      // [nsd][W]
+    const int32_t* sd_key;   // [nsd]
+    const int32_t* key_off;  // [nk + 1]
+    const int32_t* key_nq;   // [nk]
+    const int32_t* key_m2;   // [nk]
+    int64_t* l1_ptr;         // count pass: counts at [x + 1]; fill pass: offsets
+    int64_t* l12_ptr;
+    uint64_t* l1;
+    uint64_t* l12;
+    int32_t* seg1;  // [nsd][nk + 1]
+    int32_t* seg12;
+    int32_t* self12;
+    int32_t nsd, nk, W;
+};
+
 // host_basis.cpp
 int validate_problem(const ci_problem& p, std::string& err);
-// Sizes only (no partner lists): orbits, species, keys, blocks, table sectors.
+// Host tables: orbits, species determinants, keys, blocks, table sectors and
+// pair index (the partner lists are built on the device).
 int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err);
-// Everything, including the partner lists.
-int build_basis(const ci_problem& p, HostBasis& hb, std::string& err);
 // Two-body keys (a, b, c, d) in table order.
 void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd);
 

@@ -4,17 +4,14 @@
 // moved to the device with one allocation and one copy).
 //
 // Builds: the oscillator orbits; the proton and neutron determinants grouped
-// by (Nq, 2M) key; the compatible key blocks and row offsets; for every
-// species determinant its one- and two-nucleon partner lists with the moved
-// orbits and the fermion phase; the sector / pair index of the two-body table;
-// all flat, for a single upload.
+// by (Nq, 2M) key; the compatible key blocks and row offsets; the sector /
+// pair index of the two-body table; all flat, for a single upload.  The
+// partner lists of the determinants are built on the device.
 #include <algorithm>
 #include <array>
 #include <cstring>
 #include <functional>
 #include <map>
-#include <thread>
-#include <unordered_map>
 
 #include "ci_internal.h"
 
@@ -47,31 +44,7 @@ int lowest_quanta(int X)
 
 using Bits = std::array<uint64_t, kMaxWords>;
 
-struct BitsHash {
-    size_t operator()(const Bits& b) const
-    {
-        uint64_t h = 0x9e3779b97f4a7c15ull;
-        for (uint64_t w : b) {
-            uint64_t z = w + h;
-            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-            h = z ^ (z >> 31);
-        }
-        return (size_t)h;
-    }
-};
-
-inline bool test_bit(const Bits& b, int k) { return (b[k >> 6] >> (k & 63)) & 1; }
 inline void flip_bit(Bits& b, int k) { b[k >> 6] ^= 1ull << (k & 63); }
-
-// number of set bits of b strictly below orbit k
-inline int count_below(const Bits& b, int k)
-{
-    int c = 0;
-    for (int w = 0; w < (k >> 6); w++) c += __builtin_popcountll(b[w]);
-    if (k & 63) c += __builtin_popcountll(b[k >> 6] & ((1ull << (k & 63)) - 1));
-    return c;
-}
 
 struct RawSD {
     Bits bits;
@@ -220,13 +193,12 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
     return CI_OK;
 }
 
-// Sectors and pair index of the two-body table.
+// Sectors and pair index of the two-body table: sectors ordered by class
+// (pp, pn, nn), pair 2M, pair parity; pairs lexicographic inside a sector.
 int make_tbme_index(HostBasis& hb, std::string& err)
 {
     const int n = hb.nsps;
     const ci_problem& p = hb.prob;
-    int maxm = 0;
-    for (int m : hb.orb_m2) maxm = std::max(maxm, m);
     hb.pair.assign((size_t)3 * n * n, kNoPair);
     hb.sec_off.clear();
     hb.sec_n.clear();
@@ -235,179 +207,31 @@ int make_tbme_index(HostBasis& hb, std::string& err)
         const int z = 2 - cls;            // protons in the pair
         if (p.Z - z < 0 || p.N - (2 - z) < 0) continue;
         const int n2max = hb.N0 - (lowest_quanta(p.Z - z) + lowest_quanta(p.N - (2 - z))) + p.nmax;
-        for (int M = -2 * maxm; M <= 2 * maxm; M += 2)
-            for (int par = 0; par < 2; par++) {
-                int32_t cnt = 0;
-                const int sec = (int)hb.sec_n.size();
-                for (int a = 0; a < n; a++)
-                    for (int b = (cls == 1 ? 0 : a + 1); b < n; b++) {
-                        if (hb.orb_m2[a] + hb.orb_m2[b] != M) continue;
-                        const int q = hb.orb_n[a] + hb.orb_n[b];
-                        if ((q & 1) != par || q > n2max) continue;
-                        if (sec >= 65536 || cnt >= 65536) {
-                            err = "two-body sector too large for the pair index";
-                            return CI_EUNSUPPORTED;
-                        }
-                        hb.pair[(size_t)cls * n * n + (size_t)a * n + b] =
-                            ((uint32_t)sec << 16) | (uint32_t)cnt;
-                        cnt++;
-                    }
-                if (cnt == 0) continue;
-                hb.sec_n.push_back(cnt);
-                hb.sec_off.push_back(total);
-                total += (int64_t)cnt * (cnt + 1) / 2;
+        // pairs of this class grouped by (2M, parity), each group lexicographic
+        std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> groups;
+        for (int a = 0; a < n; a++)
+            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++) {
+                const int q = hb.orb_n[a] + hb.orb_n[b];
+                if (q > n2max) continue;
+                groups[{hb.orb_m2[a] + hb.orb_m2[b], q & 1}].push_back({a, b});
             }
+        for (auto& kv : groups) {
+            const int sec = (int)hb.sec_n.size();
+            const int32_t cnt = (int32_t)kv.second.size();
+            if (sec >= 65536 || cnt > 65536) {
+                err = "two-body sector too large for the pair index";
+                return CI_EUNSUPPORTED;
+            }
+            for (int32_t t = 0; t < cnt; t++)
+                hb.pair[(size_t)cls * n * n + (size_t)kv.second[t].first * n + kv.second[t].second] =
+                    ((uint32_t)sec << 16) | (uint32_t)t;
+            hb.sec_n.push_back(cnt);
+            hb.sec_off.push_back(total);
+            total += (int64_t)cnt * (cnt + 1) / 2;
+        }
     }
     hb.n_tbme = total;
     return CI_OK;
-}
-
-// One- and two-nucleon partner lists of every determinant of species s.
-void make_partners(HostBasis& hb, int s)
-{
-    HostSpecies& sp = hb.sp[s];
-    const int n = hb.nsps, W = hb.W, nk = sp.nk();
-    const int64_t nsd = sp.nsd();
-    std::unordered_map<Bits, int32_t, BitsHash> index;
-    index.reserve((size_t)nsd * 2);
-    for (int64_t g = 0; g < nsd; g++) {
-        Bits b{};
-        std::memcpy(b.data(), &sp.sd[g * W], W * sizeof(uint64_t));
-        index.emplace(b, (int32_t)g);
-    }
-    // orbit pairs (h1 < h2) grouped by (pair 2M, parity), ascending quanta
-    std::map<std::pair<int, int>, std::vector<std::pair<int16_t, int16_t>>> groups;
-    for (int a = 0; a < n; a++)
-        for (int b = a + 1; b < n; b++)
-            groups[{hb.orb_m2[a] + hb.orb_m2[b], (hb.orb_n[a] + hb.orb_n[b]) & 1}].push_back(
-                {(int16_t)a, (int16_t)b});
-    for (auto& kv : groups)
-        std::stable_sort(kv.second.begin(), kv.second.end(), [&](auto x, auto y) {
-            return hb.orb_n[x.first] + hb.orb_n[x.second] < hb.orb_n[y.first] + hb.orb_n[y.second];
-        });
-
-    sp.seg1.assign((size_t)nsd * (nk + 1), 0);
-    sp.seg12.assign((size_t)nsd * (nk + 1), 0);
-    sp.self12.assign((size_t)nsd, 0);
-    std::vector<int32_t> key_nq(sp.key_nq), key_m2(sp.key_m2);
-    std::vector<int32_t> nq_of(nsd);
-    for (int64_t g = 0; g < nsd; g++) nq_of[g] = key_nq[sp.sd_key[g]];
-
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (nsd < 256) nth = 1;
-    std::vector<std::vector<uint64_t>> t1(nth), t12(nth);
-    std::vector<std::vector<int64_t>> c1(nth), c12(nth);
-    auto work = [&](unsigned t) {
-        int64_t x0 = nsd * t / nth, x1 = nsd * (t + 1) / nth;
-        std::vector<std::pair<int32_t, uint64_t>> L1, L12;
-        std::vector<int> occ, unocc;
-        for (int64_t x = x0; x < x1; x++) {
-            Bits bx{};
-            std::memcpy(bx.data(), &sp.sd[x * W], W * sizeof(uint64_t));
-            const int kx = sp.sd_key[x];
-            const int nqx = nq_of[x];
-            occ.clear();
-            unocc.clear();
-            for (int k = 0; k < n; k++) (test_bit(bx, k) ? occ : unocc).push_back(k);
-            L1.clear();
-            L12.clear();
-            auto same_mp = [&](int g) {
-                int ky = sp.sd_key[g];
-                return key_m2[ky] == key_m2[kx] && ((key_nq[ky] - key_nq[kx]) & 1) == 0;
-            };
-            auto local = [&](int g) { return (uint32_t)(g - sp.key_off[sp.sd_key[g]]); };
-            // itself
-            uint64_t self = make_rec(local((int)x), 0, 0, 0, 0, 0, false);
-            L1.push_back({(int32_t)x, self});
-            L12.push_back({(int32_t)x, self});
-            // one nucleon: particle p (in x) -> hole h (in y)
-            for (int pp : occ)
-                for (int h : unocc) {
-                    if (nqx - hb.orb_n[pp] + hb.orb_n[h] > sp.budget) continue;
-                    Bits by = bx;
-                    flip_bit(by, pp);
-                    flip_bit(by, h);
-                    auto it = index.find(by);
-                    if (it == index.end()) continue;
-                    const int g = it->second;
-                    int lo = std::min(pp, h), hi = std::max(pp, h);
-                    int between = count_below(bx, hi) - count_below(bx, lo + 1);
-                    uint64_t r = make_rec(local(g), 1, h, pp, 0, 0, between & 1);
-                    L1.push_back({g, r});
-                    if (same_mp(g)) L12.push_back({g, r});
-                }
-            // two nucleons, same pair 2M and parity (so the key keeps its 2M
-            // and the parity of its Nq)
-            for (size_t u = 0; u < occ.size(); u++)
-                for (size_t v = u + 1; v < occ.size(); v++) {
-                    const int p1 = occ[u], p2 = occ[v];
-                    auto it = groups.find({hb.orb_m2[p1] + hb.orb_m2[p2],
-                                           (hb.orb_n[p1] + hb.orb_n[p2]) & 1});
-                    if (it == groups.end()) continue;
-                    const int room = sp.budget - nqx + hb.orb_n[p1] + hb.orb_n[p2];
-                    for (auto hh : it->second) {
-                        const int h1 = hh.first, h2 = hh.second;
-                        if (hb.orb_n[h1] + hb.orb_n[h2] > room) break;
-                        if (test_bit(bx, h1) || test_bit(bx, h2)) continue;
-                        Bits by = bx;
-                        flip_bit(by, p1);
-                        flip_bit(by, p2);
-                        flip_bit(by, h1);
-                        flip_bit(by, h2);
-                        auto jt = index.find(by);
-                        if (jt == index.end()) continue;
-                        const int g = jt->second;
-                        Bits T = by;  // y without the holes = x without the particles
-                        flip_bit(T, h1);
-                        flip_bit(T, h2);
-                        int e = count_below(by, h1) + count_below(by, h2) - 1 + count_below(T, p1) +
-                                count_below(T, p2);
-                        L12.push_back({g, make_rec(local(g), 2, h1, p1, h2, p2, e & 1)});
-                    }
-                }
-            std::sort(L1.begin(), L1.end(), [](auto& a, auto& b) { return a.first < b.first; });
-            std::sort(L12.begin(), L12.end(), [](auto& a, auto& b) { return a.first < b.first; });
-            // segment starts per key
-            int32_t* s1 = &sp.seg1[(size_t)x * (nk + 1)];
-            int32_t* s12 = &sp.seg12[(size_t)x * (nk + 1)];
-            size_t q1 = 0, q12 = 0;
-            for (int k = 0; k <= nk; k++) {
-                while (q1 < L1.size() && sp.sd_key[L1[q1].first] < k) q1++;
-                while (q12 < L12.size() && sp.sd_key[L12[q12].first] < k) q12++;
-                s1[k] = (int32_t)q1;
-                s12[k] = (int32_t)q12;
-            }
-            s1[nk] = (int32_t)L1.size();
-            s12[nk] = (int32_t)L12.size();
-            for (size_t q = 0; q < L12.size(); q++)
-                if (L12[q].first == (int32_t)x) sp.self12[x] = (int32_t)q - s12[kx];
-            for (auto& e : L1) t1[t].push_back(e.second);
-            for (auto& e : L12) t12[t].push_back(e.second);
-            c1[t].push_back((int64_t)L1.size());
-            c12[t].push_back((int64_t)L12.size());
-        }
-    };
-    std::vector<std::thread> pool;
-    for (unsigned t = 1; t < nth; t++) pool.emplace_back(work, t);
-    work(0);
-    for (auto& th : pool) th.join();
-
-    sp.l1_ptr.assign(nsd + 1, 0);
-    sp.l12_ptr.assign(nsd + 1, 0);
-    int64_t x = 0;
-    for (unsigned t = 0; t < nth; t++)
-        for (size_t k = 0; k < c1[t].size(); k++, x++) {
-            sp.l1_ptr[x + 1] = sp.l1_ptr[x] + c1[t][k];
-            sp.l12_ptr[x + 1] = sp.l12_ptr[x] + c12[t][k];
-        }
-    sp.l1.clear();
-    sp.l12.clear();
-    sp.l1.reserve(sp.l1_ptr[nsd]);
-    sp.l12.reserve(sp.l12_ptr[nsd]);
-    for (unsigned t = 0; t < nth; t++) {
-        sp.l1.insert(sp.l1.end(), t1[t].begin(), t1[t].end());
-        sp.l12.insert(sp.l12.end(), t12[t].begin(), t12[t].end());
-    }
 }
 
 }  // namespace
@@ -449,14 +273,6 @@ int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
     if (rc != CI_OK) return rc;
     rc = make_tbme_index(hb, err);
     if (rc != CI_OK) return rc;
-    return CI_OK;
-}
-
-int build_basis(const ci_problem& p, HostBasis& hb, std::string& err)
-{
-    int rc = plan_basis(p, hb, err);
-    if (rc != CI_OK) return rc;
-    for (int s = 0; s < 2; s++) make_partners(hb, s);
     return CI_OK;
 }
 

@@ -584,6 +584,24 @@ __global__ void nnz_of_bases(const int64_t* __restrict__ row_ptr, const int64_t*
 
 static inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nbk = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nbk), dim3(kScanThreads), 0, s, x, n, tmp);
+    hipLaunchKernelGGL(scan_sums_exclusive, dim3(1), dim3(kScanThreads), 0, s, tmp, nbk);
+    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nbk), dim3(kScanThreads), 0, s, x, n, tmp);
+    return hipGetLastError();
+}
+
+__global__ void copy_i64(const int64_t* __restrict__ src, int64_t* __restrict__ dst) { *dst = *src; }
+
+hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_i64, dim3(1), dim3(1), 0, s, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
                         hipStream_t s)
@@ -595,12 +613,7 @@ hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0
     // the first slot of each basis' segment holds 0 before the scan, so the
     // inclusive scan leaves there the number of entries of the bases before it
     hipLaunchKernelGGL(zero_i64_at, dim3(grid_for(nb, 256)), dim3(256), 0, s, row_ptr, seg_first, nb);
-    const int64_t nbk = (nrp + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nbk), dim3(kScanThreads), 0, s, row_ptr, nrp,
-                       scan_tmp);
-    hipLaunchKernelGGL(scan_sums_exclusive, dim3(1), dim3(kScanThreads), 0, s, scan_tmp, nbk);
-    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nbk), dim3(kScanThreads), 0, s, row_ptr, nrp, scan_tmp);
-    return hipGetLastError();
+    return launch_inclusive_scan(row_ptr, nrp, scan_tmp, s);
 }
 
 hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_t* last, int64_t* nnz,
