@@ -20,6 +20,18 @@ namespace {
 
 constexpr int kPartnerWaves = 4;
 
+// descriptor pointers are generic; use them through the global address space
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* glb(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glbw(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // number of set bits of the W-word string strictly below orbit k
 __device__ __forceinline__ int bits_below(const uint64_t* w, int W, int k)
 {
@@ -79,21 +91,24 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs
     if (x >= A.nsd) return;
     const int W = A.W;
     uint64_t xw[kMaxWords];
-    for (int t = 0; t < kMaxWords; t++) xw[t] = t < W ? A.sd[(int64_t)x * W + t] : 0;
-    const int kx = A.sd_key[x];
-    const int mx = A.key_m2[kx], qx = A.key_nq[kx];
+    const auto sd = glb(A.sd);
+    const auto key_off = glb(A.key_off), key_nq = glb(A.key_nq), key_m2 = glb(A.key_m2);
+    for (int t = 0; t < kMaxWords; t++) xw[t] = t < W ? sd[(int64_t)x * W + t] : 0;
+    const int kx = glb(A.sd_key)[x];
+    const int mx = key_m2[kx], qx = key_nq[kx];
     int c1 = 0, c12 = 0;
-    const int64_t o1 = FILL ? A.l1_ptr[x] : 0, o12 = FILL ? A.l12_ptr[x] : 0;
-    int32_t* s1 = A.seg1 + (int64_t)x * (A.nk + 1);
-    int32_t* s12 = A.seg12 + (int64_t)x * (A.nk + 1);
+    const int64_t o1 = FILL ? glb(A.l1_ptr)[x] : 0, o12 = FILL ? glb(A.l12_ptr)[x] : 0;
+    const auto s1 = glbw(A.seg1 + (int64_t)x * (A.nk + 1));
+    const auto s12 = glbw(A.seg12 + (int64_t)x * (A.nk + 1));
+    const auto l1 = glbw(A.l1), l12 = glbw(A.l12);
     for (int k = 0; k < A.nk; k++) {
         if (FILL && lane == 0) {
             s1[k] = c1;
             s12[k] = c12;
         }
-        const bool same = A.key_m2[k] == mx && ((A.key_nq[k] - qx) & 1) == 0;
+        const bool same = key_m2[k] == mx && ((key_nq[k] - qx) & 1) == 0;
         const int c12k = c12;  // first l12 record of key k
-        const int y0 = A.key_off[k], y1 = A.key_off[k + 1];
+        const int y0 = key_off[k], y1 = key_off[k + 1];
         for (int yb = y0; yb < y1; yb += 64) {
             const int y = yb + lane;
             int pc = 64;
@@ -101,7 +116,7 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs
             if (y < y1) {
                 pc = 0;
                 for (int t = 0; t < W; t++) {
-                    yw[t] = A.sd[(int64_t)y * W + t];
+                    yw[t] = sd[(int64_t)y * W + t];
                     pc += __popcll(xw[t] ^ yw[t]);
                 }
             }
@@ -113,13 +128,13 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs
                 if (in1) {
                     const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0));
-                    A.l1[o1 + c1 + r] = rec;
+                    l1[o1 + c1 + r] = rec;
                 }
                 if (in12) {
                     const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m12 >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m12, 0));
-                    A.l12[o12 + c12 + r] = rec;
-                    if (y == x) A.self12[x] = c12 - c12k + r;
+                    l12[o12 + c12 + r] = rec;
+                    if (y == x) glbw(A.self12)[x] = c12 - c12k + r;
                 }
             }
             c1 += __popcll(m1);
@@ -131,8 +146,8 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs
             s1[A.nk] = c1;
             s12[A.nk] = c12;
         } else {
-            A.l1_ptr[x + 1] = c1;
-            A.l12_ptr[x + 1] = c12;
+            glbw(A.l1_ptr)[x + 1] = c1;
+            glbw(A.l12_ptr)[x + 1] = c12;
         }
     }
 }

@@ -111,7 +111,7 @@ struct SpOff {
 };
 struct UOff {
     SpOff sp[2];
-    size_t blk_kp, blk_kn, blk_off, pair, sec_off, sec_n, orb_n, totals;
+    size_t blk_kp, blk_kn, blk_off, pair, orb_n, totals;
     size_t bytes;
 };
 
@@ -208,9 +208,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
         uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
         uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
-        uo[u].pair = L.take<uint32_t>(hb.pair.size());
-        uo[u].sec_off = L.take<int64_t>(hb.sec_off.size());
-        uo[u].sec_n = L.take<int32_t>(hb.sec_n.size());
+        uo[u].pair = L.take<uint64_t>(hb.pair64.size());
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
         uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
         uo[u].bytes = L.off - start;
@@ -256,9 +254,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
         put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
         put(uo[u].blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
-        put(uo[u].pair, hb.pair.data(), hb.pair.size() * 4);
-        put(uo[u].sec_off, hb.sec_off.data(), hb.sec_off.size() * 8);
-        put(uo[u].sec_n, hb.sec_n.data(), hb.sec_n.size() * 4);
+        put(uo[u].pair, hb.pair64.data(), hb.pair64.size() * 8);
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
     }
     std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
@@ -366,9 +362,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.blk_kp = (const int32_t*)D(uo[u].blk_kp);
         d.blk_kn = (const int32_t*)D(uo[u].blk_kn);
         d.blk_off = (const int64_t*)D(uo[u].blk_off);
-        d.pair = (const uint32_t*)D(uo[u].pair);
-        d.sec_off = (const int64_t*)D(uo[u].sec_off);
-        d.sec_n = (const int32_t*)D(uo[u].sec_n);
+        d.pair = (const uint64_t*)D(uo[u].pair);
         d.orb_n = (const int32_t*)D(uo[u].orb_n);
         d.dim = hb.dim;
         d.row0 = R;

@@ -39,8 +39,12 @@ CI_HD inline uint64_t make_rec(uint32_t ylocal, int d, int h1, int p1, int h2, i
            ((uint64_t)(neg ? 1 : 0) << 56) | ((uint64_t)d << 57);
 }
 
-// two-body pair index entry: (sector << 16) | position of the pair in the sector
+// two-body pair index entry (host): (sector << 16) | position of the pair in the sector
 constexpr uint32_t kNoPair = 0xffffffffu;
+// device pair entry: bits 0..15 position r of the pair in its sector, bits
+// 16..31 sector, bits 32..63 base(r) = sector offset + r (2 n_s - r + 1) / 2 - r,
+// so that V_{r,q} (r <= q) sits at base(r) + q
+constexpr uint64_t kNoPair64 = ~0ull;
 
 // ---------------------------------------------------------------------------
 // Device view of one species (all pointers into the basis arena).
@@ -63,9 +67,7 @@ struct BasisDev {
     const int32_t* blk_kp;     // [nblk]
     const int32_t* blk_kn;     // [nblk]
     const int64_t* blk_off;    // [nblk + 1] first row of each block
-    const uint32_t* pair;      // [3][n][n] pp, pn, nn pair index (species-local orbits)
-    const int64_t* sec_off;    // [nsec] first table entry of each sector
-    const int32_t* sec_n;      // [nsec] pairs in each sector
+    const uint64_t* pair;      // [3][n][n] pp, pn, nn pair entries (species-local orbits)
     const int32_t* orb_n;      // [n] oscillator shell of each orbit
     int64_t dim;               // D
     int64_t row0;              // R_b: this basis' segment of row_ptr
@@ -99,7 +101,8 @@ struct HostBasis {
     int64_t dim = 0;
     std::vector<int64_t> sec_off;
     std::vector<int32_t> sec_n;
-    std::vector<uint32_t> pair;  // 3 * n * n
+    std::vector<uint32_t> pair;    // 3 * n * n
+    std::vector<uint64_t> pair64;  // 3 * n * n, device form
     int64_t n_tbme = 0;
     int nblk() const { return (int)blk_kp.size(); }
 };

@@ -231,6 +231,19 @@ int make_tbme_index(HostBasis& hb, std::string& err)
         }
     }
     hb.n_tbme = total;
+    if (total >= ((int64_t)1 << 31)) {
+        err = "two-body table of " + std::to_string(total) + " entries does not fit int32 indices";
+        return CI_EUNSUPPORTED;
+    }
+    // device form: the entry also carries the row base of the pair
+    hb.pair64.assign(hb.pair.size(), kNoPair64);
+    for (size_t t = 0; t < hb.pair.size(); t++) {
+        const uint32_t e = hb.pair[t];
+        if (e == kNoPair) continue;
+        const int64_t sec = e >> 16, r = e & 0xffff, ns = hb.sec_n[sec];
+        const int64_t base = hb.sec_off[sec] + r * (2 * ns - r + 1) / 2 - r;
+        hb.pair64[t] = ((uint64_t)(uint32_t)base << 32) | e;
+    }
     return CI_OK;
 }
 

@@ -35,7 +35,7 @@ namespace ci {
 enum { kCount = 0, kFill = 1, kAdjoint = 2 };
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kQueue = 128;  // queued multi-term entries per wave
+constexpr int kQueue = 96;  // queued multi-term entries per wave
 
 __device__ __forceinline__ int rec_d(uint64_t r) { return (int)((r >> 57) & 3); }
 __device__ __forceinline__ int rec_local(uint64_t r) { return (int)(r & kRecLocalMask); }
@@ -46,6 +46,29 @@ __device__ __forceinline__ int rec_p2(uint64_t r) { return (int)((r >> 48) & 255
 __device__ __forceinline__ double rec_sign(uint64_t r) { return ((r >> 56) & 1) ? -1.0 : 1.0; }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pointers read from the descriptors are generic; accessing them through the
+// global address space gives global_load instead of flat_load (a flat load
+// also counts against the LDS wait counter and would stall every LDS access).
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(const T* p)
+{
+    return (gptr<T>)p;
+}
+template <typename T>
+using gmut = __attribute__((address_space(1))) T*;
+// relaxed device-scope FP64 add in L2 (hardware atomic with -munsafe-fp-atomics)
+__device__ __forceinline__ void atomic_add_f64(gmut<double> p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ gmut<T> glbw(T* p)
+{
+    return (gmut<T>)p;
+}
 __device__ __forceinline__ int64_t uniform64(int64_t v)
 {
     const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -61,14 +84,29 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic).
 __device__ __forceinline__ int wave_incl_scan(int v)
 {
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
     return v;
+}
+
+__device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+
+// largest t in [0, 64) with a[t] <= x, for a[0] <= x < a[64], a non-decreasing
+__device__ __forceinline__ int seg_search64(const int32_t* a, int x)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (a[lo + step] <= x) lo += step;
+    return lo;
 }
 
 // largest t in [0, n) with a[t] <= x, for a[0] <= x < a[n], a non-decreasing
@@ -84,40 +122,53 @@ __device__ __forceinline__ int seg_search(const int32_t* a, int n, int x)
 }
 
 // Table position of V_{ab,cd} of class cls (0 pp, 1 pn, 2 nn) with
-// species-local orbits (for pn: a, c protons; b, d neutrons).  Returns -1 if
-// either pair is outside the stored table; *sg receives the antisymmetry sign.
-__device__ __forceinline__ int64_t tb_index(const BasisDev& B, int cls, int a, int b, int c, int d,
-                                            double* sg)
+// species-local orbits, for ordered pairs (a < b and c < d for pp and nn; a,
+// c protons and b, d neutrons for pn).  -1 if a pair is outside the table.
+__device__ __forceinline__ int tb_pos(const BasisDev& B, int cls, int a, int b, int c, int d)
 {
-    double s = 1.0;
-    if (cls != 1) {
-        if (a > b) { int t = a; a = b; b = t; s = -s; }
-        if (c > d) { int t = c; c = d; d = t; s = -s; }
-    }
     const int n = B.nsps;
-    const uint32_t* P = B.pair + (size_t)cls * n * n;
-    const uint32_t e1 = P[a * n + b], e2 = P[c * n + d];
-    *sg = s;
-    if (e1 == kNoPair || e2 == kNoPair || (e1 >> 16) != (e2 >> 16)) return -1;
-    const int sec = (int)(e1 >> 16);
-    int64_t r = e1 & 0xffff, q = e2 & 0xffff;
-    if (r > q) { int64_t t = r; r = q; q = t; }
-    const int64_t ns = B.sec_n[sec];
-    return B.sec_off[sec] + r * (2 * ns - r + 1) / 2 + (q - r);
+    const gptr<uint64_t> P = glb(B.pair) + cls * n * n;
+    const uint64_t e1 = P[a * n + b], e2 = P[c * n + d];
+    const uint32_t l1 = (uint32_t)e1, l2 = (uint32_t)e2;
+    if (e1 == kNoPair64 || e2 == kNoPair64 || (l1 >> 16) != (l2 >> 16)) return -1;
+    const bool first = (l1 & 0xffff) <= (l2 & 0xffff);
+    return (int)((first ? (uint32_t)(e1 >> 32) : (uint32_t)(e2 >> 32)) + (first ? (l2 & 0xffff) : (l1 & 0xffff)));
 }
+
+// Same for pairs in any order: each swap inside a pp or nn pair flips the sign.
+__device__ __forceinline__ int tb_pos_any(const BasisDev& B, int cls, int a, int b, int c, int d, bool* neg)
+{
+    bool ng = false;
+    if (cls != 1) {
+        if (a > b) { const int t = a; a = b; b = t; ng = !ng; }
+        if (c > d) { const int t = c; c = d; d = t; ng = !ng; }
+    }
+    *neg = ng;
+    return tb_pos(B, cls, a, b, c, d);
+}
+
+__device__ __forceinline__ bool rec_neg(uint64_t r) { return (r >> 56) & 1; }
 
 // Per-wavefront LDS.
 struct WaveLds {
-    int32_t bstart[65];        // first segment of each target block of the window
-    int32_t eoff[65];          // first entry of each segment of the chunk
-    uint64_t spr[64];          // proton partner record of each segment
-    const uint64_t* slp[64];   // first neutron partner record of each segment
-    int64_t scol[64];          // column of local neutron index 0 of each segment
-    int32_t qpos[kQueue];      // queued entry: offset from the row's first entry
-    uint64_t qpr[kQueue];      //   proton record (self record for no proton move)
-    uint64_t qnr[kQueue];      //   neutron record
-    int32_t toff[kQueue + 1];  //   first term of each queued entry
-    int32_t occ[2 * 64];       // occupied orbits of the row: protons, then neutrons
+    int32_t bstart[65];  // first segment of each target block of the window
+    int32_t eoff[65];    // first entry of each segment of the chunk
+    // per target block of the window
+    int32_t bp[64];    // first proton partner in the block: index into l12 (bit 31 set) or l1
+    int32_t bcol[64];  // first row of the block
+    int32_t bstr[64];  // rows per proton determinant (|Kn'|)
+    int32_t bn1[64], bl1[64];    // the row's neutron d<=1 partners in Kn': first, count
+    int32_t bn12[64], bl12[64];  // the row's neutron d<=2 partners in Kn' (N' >= N in the row's block)
+    // per segment (target block, proton partner) of the chunk
+    uint64_t spr[64];  // proton partner record
+    int32_t soff[64];  // first neutron partner: index into l12 (bit 31 set) or l1
+    int32_t scol[64];  // column of neutron local index 0
+    // queued multi-term entries
+    int32_t qpos[kQueue];  // offset from the row's first entry
+    uint64_t qpr[kQueue];  // proton record (the self record when no proton moved)
+    uint64_t qnr[kQueue];  // neutron record
+    int32_t toff[kQueue + 1];
+    uint8_t occ[128];  // occupied orbits of the row: protons, then neutrons
 };
 
 struct RowView {
@@ -140,45 +191,45 @@ __device__ __forceinline__ int queued_terms(const RowView& R, uint64_t pr, uint6
     return (rec_d(pr) == 0 && rec_d(nr) == 0) ? A * (A - 1) / 2 : A - 1;
 }
 
-// The u-th two-body term of a queued entry: coefficient and table position.
-__device__ __forceinline__ int64_t queued_term(const RowView& R, const WaveLds& L, uint64_t pr, uint64_t nr,
-                                               int u, double* coef)
+// The u-th two-body term of a queued entry: table position and sign.
+__device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, uint64_t pr, uint64_t nr, int u,
+                                           bool* neg)
 {
     const BasisDev& B = *R.B;
     const int Z = R.Z, NN = R.NN;
-    const int32_t* oP = L.occ;
-    const int32_t* oN = L.occ + Z;
-    double s;
-    int64_t k;
+    const uint8_t* oP = L.occ;
+    const uint8_t* oN = L.occ + Z;
+    bool s;
+    int k;
     if (rec_d(pr) == 1) {  // one proton moved: p (row) -> h (column)
         const int h = rec_h1(pr), p = rec_p1(pr);
         if (u < Z - 1) {  // the u-th proton spectator (the row's protons without p)
             const int kk = (oP[u] >= p) ? oP[u + 1] : oP[u];
-            k = tb_index(B, 0, p, kk, h, kk, &s);
+            k = tb_pos_any(B, 0, p, kk, h, kk, &s);
         } else {
             const int b = oN[u - (Z - 1)];
-            k = tb_index(B, 1, p, b, h, b, &s);
+            k = tb_pos_any(B, 1, p, b, h, b, &s);
         }
-        *coef = rec_sign(pr) * s;
+        *neg = s ^ rec_neg(pr);
         return k;
     }
     if (rec_d(nr) == 1) {  // one neutron moved
         const int h = rec_h1(nr), p = rec_p1(nr);
         if (u < NN - 1) {
             const int kk = (oN[u] >= p) ? oN[u + 1] : oN[u];
-            k = tb_index(B, 2, p, kk, h, kk, &s);
+            k = tb_pos_any(B, 2, p, kk, h, kk, &s);
         } else {
             const int a = oP[u - (NN - 1)];
-            k = tb_index(B, 1, a, p, a, h, &s);
+            k = tb_pos_any(B, 1, a, p, a, h, &s);
         }
-        *coef = rec_sign(nr) * s;
+        *neg = s ^ rec_neg(nr);
         return k;
     }
-    // diagonal: every occupied pair, pp then nn then pn
+    // diagonal: every occupied pair, pp then nn then pn (all ordered)
     const int npp = Z * (Z - 1) / 2, nnn = NN * (NN - 1) / 2;
     int cls, a, b;
     if (u < npp + nnn) {
-        const int32_t* o = (u < npp) ? oP : oN;
+        const uint8_t* o = (u < npp) ? oP : oN;
         const int X = (u < npp) ? Z : NN;
         int t = (u < npp) ? u : u - npp;
         int x = 0;
@@ -195,9 +246,8 @@ __device__ __forceinline__ int64_t queued_term(const RowView& R, const WaveLds& 
         b = oN[t % NN];
         cls = 1;
     }
-    k = tb_index(B, cls, a, b, a, b, &s);
-    *coef = s;
-    return k;
+    *neg = false;
+    return tb_pos(B, cls, a, b, a, b);
 }
 
 // Evaluate (fill) or scatter (adjoint) the queued multi-term entries.
@@ -206,15 +256,15 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
 {
     const int lane = threadIdx.x & 63;
     if (qn == 0) return;
-    // first term of each queued entry (up to 128 entries: two per lane)
+    // first term of each queued entry
     int tot = 0;
     for (int base = 0; base < qn; base += 64) {
         const int q = base + lane;
         const int t = q < qn ? queued_terms(R, L.qpr[q], L.qnr[q]) : 0;
         const int incl = wave_incl_scan(t);
-        L.toff[q + 1] = tot + incl;  // q < kQueue
+        if (q < kQueue) L.toff[q + 1] = tot + incl;
         if (lane == 0 && base == 0) L.toff[0] = 0;
-        tot += __shfl(incl, 63, 64);
+        tot += lane63(incl);
     }
     wave_sync();
     double carry = 0.0;
@@ -226,15 +276,18 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
         double v = 0.0;
         if (act) {
             q = seg_search(L.toff, qn, t);
-            const int u = t - L.toff[q];
-            double coef;
-            const int64_t k = queued_term(R, L, L.qpr[q], L.qnr[q], u, &coef);
+            bool neg;
+            const int k = queued_term(R, L, L.qpr[q], L.qnr[q], t - L.toff[q], &neg);
             if (k >= 0) {
                 if (MODE == kFill) {
-                    v = coef * (double)R.tbme[k];
+                    const double x = (double)glb(R.tbme)[k];
+                    v = neg ? -x : x;
                 } else {
                     const int64_t p = R.pos0 + L.qpos[q];
-                    if (p < R.cap) atomicAdd(&R.gacc[k], coef * (double)R.gval[p]);
+                    if (p < R.cap) {
+                        const double g = (double)glb(R.gval)[p];
+                        atomic_add_f64(glbw(R.gacc) + k, neg ? -g : g);
+                    }
                 }
             }
         }
@@ -253,7 +306,7 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
                 const int64_t p = R.pos0 + L.qpos[q];
                 double x = v;
                 if (rec_d(L.qpr[q]) == 0 && rec_d(L.qnr[q]) == 0) x += R.spe_sum;
-                if (p < R.cap) R.val[p] = (float)x;
+                if (p < R.cap) glbw(R.val)[p] = (float)x;
             }
             // an entry cut by the end of the round continues in the next one
             carry = __shfl(v, 63, 64);
@@ -265,26 +318,29 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
 
 // One row: count (returns the number of entries), fill or adjoint.
 template <int MODE>
-__device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int64_t r, RowView& R)
+__device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView& R)
 {
     const int lane = threadIdx.x & 63;
     const SpeciesDev& SP = B.sp[0];
     const SpeciesDev& SN = B.sp[1];
-    const int kp = B.blk_kp[bi], kn = B.blk_kn[bi];
-    const int nKn = SN.key_off[kn + 1] - SN.key_off[kn];
-    const int ip = (int)(r / nKn), in = (int)(r - (int64_t)ip * nKn);
-    const int64_t gP = SP.key_off[kp] + ip;
-    const int64_t gN = SN.key_off[kn] + in;
+    const gptr<int32_t> blk_kp = glb(B.blk_kp), blk_kn = glb(B.blk_kn);
+    const gptr<int64_t> blk_off = glb(B.blk_off);
+    const gptr<int32_t> pkoff = glb(SP.key_off), nkoff = glb(SN.key_off);
+    const int kp = blk_kp[bi], kn = blk_kn[bi];
+    const int nKn = nkoff[kn + 1] - nkoff[kn];
+    const int ip = r / nKn, in = r - ip * nKn;
+    const int gP = pkoff[kp] + ip;
+    const int gN = nkoff[kn] + in;
     const int nkp = SP.nk, nkn = SN.nk;
-    const uint64_t* P1 = SP.l1 + SP.l1_ptr[gP];
-    const uint64_t* P12 = SP.l12 + SP.l12_ptr[gP];
-    const int32_t* sP1 = SP.seg1 + gP * (nkp + 1);
-    const int32_t* sP12 = SP.seg12 + gP * (nkp + 1);
-    const uint64_t* N1 = SN.l1 + SN.l1_ptr[gN];
-    const uint64_t* N12 = SN.l12 + SN.l12_ptr[gN];
-    const int32_t* sN1 = SN.seg1 + gN * (nkn + 1);
-    const int32_t* sN12 = SN.seg12 + gN * (nkn + 1);
-    const int self12 = SN.self12[gN];
+    const gptr<uint64_t> P1 = glb(SP.l1 + glb(SP.l1_ptr)[gP]);
+    const gptr<uint64_t> P12 = glb(SP.l12 + glb(SP.l12_ptr)[gP]);
+    const gptr<int32_t> sP1 = glb(SP.seg1 + (int64_t)gP * (nkp + 1));
+    const gptr<int32_t> sP12 = glb(SP.seg12 + (int64_t)gP * (nkp + 1));
+    const gptr<uint64_t> N1 = glb(SN.l1 + glb(SN.l1_ptr)[gN]);
+    const gptr<uint64_t> N12 = glb(SN.l12 + glb(SN.l12_ptr)[gN]);
+    const gptr<int32_t> sN1 = glb(SN.seg1 + (int64_t)gN * (nkn + 1));
+    const gptr<int32_t> sN12 = glb(SN.seg12 + (int64_t)gN * (nkn + 1));
+    const int self12 = glb(SN.self12)[gN];
 
     if (MODE != kCount) {
         // occupied orbits of the row (for the multi-term entries)
@@ -292,14 +348,14 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int64_t r, RowV
         if (lane == 0) {
             int t = 0;
             for (int s = 0; s < 2; s++) {
-                const uint64_t* w = (s == 0 ? SP.sd + gP * B.W : SN.sd + gN * B.W);
+                const gptr<uint64_t> w = glb(s == 0 ? SP.sd + (int64_t)gP * B.W : SN.sd + (int64_t)gN * B.W);
                 for (int k = 0; k < B.W; k++) {
                     uint64_t x = w[k];
                     while (x) {
                         const int o = k * 64 + __ffsll((long long)x) - 1;
                         x &= x - 1;
-                        L.occ[t++] = o;
-                        e += (B.orb_n[o] + 1.5) * B.hw;
+                        L.occ[t++] = (uint8_t)o;
+                        e += (glb(B.orb_n)[o] + 1.5) * B.hw;
                     }
                 }
             }
@@ -311,49 +367,61 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int64_t r, RowV
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
     for (int w0 = bi; w0 < B.nblk; w0 += 64) {
-        // 1. proton partners of P in each target block of the window
+        // 1. per target block of the window: proton partners of P, neutron
+        //    partners of N, column base
         const int b2 = w0 + lane;
         int np = 0;
         if (b2 < B.nblk) {
-            const int kp2 = B.blk_kp[b2];
-            np = (B.blk_kn[b2] == kn) ? sP12[kp2 + 1] - sP12[kp2] : sP1[kp2 + 1] - sP1[kp2];
+            const int kp2 = blk_kp[b2], kn2 = blk_kn[b2];
+            const bool same_n = (kn2 == kn);
+            const int ps = same_n ? sP12[kp2] : sP1[kp2];
+            np = (same_n ? sP12[kp2 + 1] : sP1[kp2 + 1]) - ps;
+            L.bp[lane] = ps | (same_n ? (int)0x80000000 : 0);
+            L.bcol[lane] = (int)blk_off[b2];
+            L.bstr[lane] = nkoff[kn2 + 1] - nkoff[kn2];
+            const int s1 = sN1[kn2], s12 = sN12[kn2] + (b2 == bi ? self12 : 0);  // diagonal block: N' >= N
+            const int l1 = sN1[kn2 + 1] - s1, l12 = sN12[kn2 + 1] - s12;
+            L.bn1[lane] = s1;
+            L.bl1[lane] = l1;
+            L.bn12[lane] = s12;
+            L.bl12[lane] = l12;
+            // a block with another neutron key needs a neutron partner of N in it
+            // (d <= 1 for a moved proton, d <= 2 for P' = P): otherwise every
+            // segment of the block is empty
+            if (!same_n && l1 == 0 && (kp2 != kp || l12 == 0)) np = 0;
         }
         const int bincl = wave_incl_scan(np);
         L.bstart[lane + 1] = bincl;
         if (lane == 0) L.bstart[0] = 0;
-        const int S = __shfl(bincl, 63, 64);
+        const int S = lane63(bincl);
         wave_sync();
         for (int s0 = 0; s0 < S; s0 += 64) {
             // 2. entries of each segment (target block, P')
             const int s = s0 + lane;
             int len = 0;
             uint64_t pr = 0;
-            const uint64_t* lp = nullptr;
-            int64_t cb = 0;
+            int so = 0, sc = 0;
             if (s < S) {
-                const int t = seg_search(L.bstart, 64, s);
-                const int bb = w0 + t;
-                const int kp2 = B.blk_kp[bb], kn2 = B.blk_kn[bb];
-                const bool same_n = (kn2 == kn);
-                const int q = s - L.bstart[t];
-                pr = same_n ? P12[sP12[kp2] + q] : P1[sP1[kp2] + q];
+                const int t = seg_search64(L.bstart, s);
+                const int bp = L.bp[t];
+                const int q = (bp & 0x7fffffff) + s - L.bstart[t];
+                pr = bp < 0 ? P12[q] : P1[q];
                 const int dp = rec_d(pr), ipp = rec_local(pr);
-                cb = B.blk_off[bb] + (int64_t)ipp * (SN.key_off[kn2 + 1] - SN.key_off[kn2]);
-                if (bb == bi && ipp < ip) {
+                sc = L.bcol[t] + ipp * L.bstr[t];
+                if (w0 + t == bi && ipp < ip) {
                     len = 0;  // lower triangle
                 } else if (dp == 2) {
                     len = 1;  // two protons moved: N' = N
                 } else if (dp == 1) {
-                    lp = N1 + sN1[kn2];
-                    len = sN1[kn2 + 1] - sN1[kn2];
+                    so = L.bn1[t];
+                    len = L.bl1[t];
                 } else {
-                    const int k0 = (bb == bi) ? self12 : 0;  // diagonal block: N' >= N
-                    lp = N12 + sN12[kn2] + k0;
-                    len = sN12[kn2 + 1] - sN12[kn2] - k0;
+                    so = L.bn12[t] | (int)0x80000000;
+                    len = L.bl12[t];
                 }
             }
             const int eincl = wave_incl_scan(len);
-            const int T = __shfl(eincl, 63, 64);
+            const int T = lane63(eincl);
             if (MODE == kCount) {
                 pos += T;
                 continue;
@@ -361,49 +429,45 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int64_t r, RowV
             L.eoff[lane + 1] = eincl;
             if (lane == 0) L.eoff[0] = 0;
             L.spr[lane] = pr;
-            L.slp[lane] = lp;
-            L.scol[lane] = cb;
+            L.soff[lane] = so;
+            L.scol[lane] = sc;
             wave_sync();
             // 3. the entries of the chunk, 64 consecutive ones per round
             for (int e0 = 0; e0 < T; e0 += 64) {
                 const int e = e0 + lane;
                 bool special = false;
-                uint64_t qp = 0, qnrec = 0;
+                uint64_t prj = 0, nr = 0;
                 if (e < T) {
-                    const int j = seg_search(L.eoff, 64, e);
+                    const int j = seg_search64(L.eoff, e);
                     const int k = e - L.eoff[j];
-                    const uint64_t prj = L.spr[j];
+                    prj = L.spr[j];
                     const int dp = rec_d(prj);
-                    const int64_t p = R.pos0 + pos + e;
-                    int64_t c;
-                    int64_t key = -1;
-                    double coef = 0.0;
-                    if (dp == 2) {  // two protons moved
-                        c = L.scol[j] + in;
-                        key = tb_index(B, 0, rec_p1(prj), rec_p2(prj), rec_h1(prj), rec_h2(prj), &coef);
-                        coef *= rec_sign(prj);
-                    } else {
-                        const uint64_t nr = L.slp[j][k];
-                        c = L.scol[j] + rec_local(nr);
-                        const int dn = rec_d(nr);
-                        if (dp + dn == 2) {  // one proton and one neutron, or two neutrons, moved
-                            if (dp == 1)
-                                key = tb_index(B, 1, rec_p1(prj), rec_p1(nr), rec_h1(prj), rec_h1(nr), &coef);
-                            else
-                                key = tb_index(B, 2, rec_p1(nr), rec_p2(nr), rec_h1(nr), rec_h2(nr), &coef);
-                            coef *= rec_sign(prj) * rec_sign(nr);
-                        } else {  // diagonal or one nucleon moved: queue
-                            special = true;
-                            qp = prj;
-                            qnrec = nr;
-                        }
+                    if (dp != 2) {
+                        const int so2 = L.soff[j];
+                        const int idx = (so2 & 0x7fffffff) + k;
+                        nr = so2 < 0 ? N12[idx] : N1[idx];
                     }
+                    const int dn = rec_d(nr);
+                    special = (dp != 2) && (dp + dn != 2);
+                    // two nucleons moved: pp (proton record), pn (both), nn (neutron record)
+                    const int cls = dp == 2 ? 0 : (dp == 1 ? 1 : 2);
+                    const int a = dp == 0 ? rec_p1(nr) : rec_p1(prj);
+                    const int b = dp == 2 ? rec_p2(prj) : (dp == 1 ? rec_p1(nr) : rec_p2(nr));
+                    const int c = dp == 0 ? rec_h1(nr) : rec_h1(prj);
+                    const int d = dp == 2 ? rec_h2(prj) : (dp == 1 ? rec_h1(nr) : rec_h2(nr));
+                    const bool neg = rec_neg(prj) ^ rec_neg(nr);
+                    const int64_t p = R.pos0 + pos + e;
+                    const int key = special ? -1 : tb_pos(B, cls, a, b, c, d);
                     if (p < R.cap) {
                         if (MODE == kFill) {
-                            R.col[p] = (int32_t)c;
-                            if (!special) R.val[p] = key >= 0 ? (float)(coef * (double)R.tbme[key]) : 0.0f;
-                        } else if (!special && key >= 0) {
-                            atomicAdd(&R.gacc[key], coef * (double)R.gval[p]);
+                            glbw(R.col)[p] = L.scol[j] + (dp == 2 ? in : rec_local(nr));
+                            if (!special) {
+                                const float x = key >= 0 ? glb(R.tbme)[key] : 0.0f;
+                                glbw(R.val)[p] = neg ? -x : x;
+                            }
+                        } else if (key >= 0) {
+                            const double g = (double)glb(R.gval)[p];
+                            atomic_add_f64(glbw(R.gacc) + key, neg ? -g : g);
                         }
                     }
                 }
@@ -413,8 +477,8 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int64_t r, RowV
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
                     if (special) {
                         L.qpos[qn + rank] = (int32_t)(pos + e);
-                        L.qpr[qn + rank] = qp;
-                        L.qnr[qn + rank] = qnrec;
+                        L.qpr[qn + rank] = prj;
+                        L.qnr[qn + rank] = nr;
                     }
                     qn += __popcll(m);
                     wave_sync();
@@ -449,12 +513,13 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
     while (b + 1 < nb && basis_row0[b + 1] <= grow) b++;
     b = uniform(b);
     const BasisDev& B = bases[b];
-    const int64_t i = grow - basis_row0[b];
+    const int i = (int)(grow - basis_row0[b]);
     // block of the row
+    const gptr<int64_t> blk_off = glb(B.blk_off);
     int lo = 0, hi = B.nblk;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (B.blk_off[mid] <= i) lo = mid;
+        if (blk_off[mid] <= i) lo = mid;
         else hi = mid;
     }
     const int bi = uniform(lo);
@@ -468,15 +533,16 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
     R.Z = B.Z;
     R.NN = B.NN;
     R.spe_sum = 0.0;
+    const int r = i - (int)blk_off[bi];
     if (MODE == kCount) {
         R.pos0 = 0;
         R.cap = 0;
-        const int64_t n = do_row<kCount>(B, lds[wid], bi, i - B.blk_off[bi], R);
-        if ((threadIdx.x & 63) == 0) row_ptr[B.row0 + i + 1] = n;
+        const int64_t n = do_row<kCount>(B, lds[wid], bi, r, R);
+        if ((threadIdx.x & 63) == 0) glbw(row_ptr)[B.row0 + i + 1] = n;
     } else {
         R.pos0 = uniform64(row_ptr[B.row0 + i]);
         R.cap = uniform64(row_ptr[nrp - 1]);  // the entries of all bases end here
-        do_row<MODE>(B, lds[wid], bi, i - B.blk_off[bi], R);
+        do_row<MODE>(B, lds[wid], bi, r, R);
     }
 }
 
