@@ -10,7 +10,6 @@
 #include <algorithm>
 #include <array>
 #include <cstring>
-#include <functional>
 #include <map>
 
 #include "ci_internal.h"
@@ -51,34 +50,34 @@ struct RawSD {
     int nq, m2;
 };
 
-void enumerate_species(const HostBasis& hb, int X, int budget, std::vector<RawSD>& out)
+// All X-orbit determinants with Nq <= budget, in colex order (as unsigned
+// W-word integers, word W-1 most significant): the highest orbit is chosen
+// first, in ascending order, and the rest recursively below it.  low[j] is
+// the fewest quanta j nucleons can have.
+void colex_choose(const HostBasis& hb, int left, int limit, int nq, int m2, int budget, const int* low,
+                  RawSD& cur, std::vector<RawSD>& out)
 {
-    const int n = hb.nsps;
-    RawSD cur{};
-    // depth-first choice of X orbits in ascending order
-    std::function<void(int, int, int, int)> rec = [&](int start, int left, int nq, int m2) {
-        if (left == 0) {
-            cur.nq = nq;
-            cur.m2 = m2;
-            out.push_back(cur);
-            return;
-        }
-        for (int k = start; k <= n - left; k++) {
-            // orbits ascend in N, so the remaining picks cost at least left * N_k
-            if (nq + left * hb.orb_n[k] > budget) break;
-            flip_bit(cur.bits, k);
-            rec(k + 1, left - 1, nq + hb.orb_n[k], m2 + hb.orb_m2[k]);
-            flip_bit(cur.bits, k);
-        }
-    };
-    rec(0, X, 0, 0);
+    if (left == 0) {
+        cur.nq = nq;
+        cur.m2 = m2;
+        out.push_back(cur);
+        return;
+    }
+    for (int k = left - 1; k < limit; k++) {
+        // orbits ascend in N: a larger top orbit never costs less
+        if (nq + hb.orb_n[k] + low[left - 1] > budget) break;
+        flip_bit(cur.bits, k);
+        colex_choose(hb, left - 1, k, nq + hb.orb_n[k], m2 + hb.orb_m2[k], budget, low, cur, out);
+        flip_bit(cur.bits, k);
+    }
 }
 
-bool colex_less(const uint64_t* a, const uint64_t* b, int W)
+void enumerate_species(const HostBasis& hb, int X, int budget, std::vector<RawSD>& out)
 {
-    for (int w = W - 1; w >= 0; w--)
-        if (a[w] != b[w]) return a[w] < b[w];
-    return false;
+    std::vector<int> low(X + 1);
+    for (int j = 0; j <= X; j++) low[j] = lowest_quanta(j);
+    RawSD cur{};
+    colex_choose(hb, X, hb.nsps, 0, 0, budget, low.data(), cur, out);
 }
 
 bool block_ok(const HostBasis& hb, int nqp, int m2p, int nqn, int m2n)
@@ -126,48 +125,57 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
         hb.sp[s].budget = top - other0[s];
         enumerate_species(hb, X[s], hb.sp[s].budget, raw[s]);
     }
-    // distinct keys of each species, then the keys that form a block
-    std::vector<std::pair<int, int>> keys[2];
+    // keys (Nq, 2M) of each species on a dense grid; keep those in a block
+    int maxm = 0;
+    for (int m : hb.orb_m2) maxm = std::max(maxm, m);
+    const int mtot = std::max(1, std::max(p.Z, p.N)) * maxm;  // |2M| bound of one species
+    const int nqs = top + 1, nms = 2 * mtot + 1;
+    auto cell = [&](int nq, int m2) { return nq * nms + (m2 + mtot); };
+    std::vector<int32_t> present[2];
     for (int s = 0; s < 2; s++) {
-        for (const RawSD& r : raw[s]) keys[s].push_back({r.nq, r.m2});
-        std::sort(keys[s].begin(), keys[s].end());
-        keys[s].erase(std::unique(keys[s].begin(), keys[s].end()), keys[s].end());
+        present[s].assign((size_t)nqs * nms, 0);
+        for (const RawSD& r : raw[s]) present[s][cell(r.nq, r.m2)]++;
     }
-    std::vector<char> usep(keys[0].size(), 0), usen(keys[1].size(), 0);
-    for (size_t a = 0; a < keys[0].size(); a++)
-        for (size_t b = 0; b < keys[1].size(); b++)
-            if (block_ok(hb, keys[0][a].first, keys[0][a].second, keys[1][b].first,
-                         keys[1][b].second))
-                usep[a] = usen[b] = 1;
+    std::vector<char> use[2];
+    use[0].assign((size_t)nqs * nms, 0);
+    use[1].assign((size_t)nqs * nms, 0);
+    for (int qa = 0; qa < nqs; qa++)
+        for (int ma = -mtot; ma <= mtot; ma++) {
+            if (!present[0][cell(qa, ma)]) continue;
+            const int mb = p.two_m - ma;
+            if (mb < -mtot || mb > mtot) continue;
+            for (int qb = 0; qb < nqs; qb++)
+                if (present[1][cell(qb, mb)] && block_ok(hb, qa, ma, qb, mb))
+                    use[0][cell(qa, ma)] = use[1][cell(qb, mb)] = 1;
+        }
     for (int s = 0; s < 2; s++) {
         HostSpecies& sp = hb.sp[s];
-        const std::vector<char>& use = s == 0 ? usep : usen;
-        std::map<std::pair<int, int>, int> kid;
-        for (size_t k = 0; k < keys[s].size(); k++)
-            if (use[k]) {
-                kid[keys[s][k]] = (int)sp.key_nq.size();
-                sp.key_nq.push_back(keys[s][k].first);
-                sp.key_m2.push_back(keys[s][k].second);
-            }
+        // key ids in (Nq, 2M) order
+        std::vector<int32_t> kid((size_t)nqs * nms, -1);
+        for (int q = 0; q < nqs; q++)
+            for (int m = -mtot; m <= mtot; m++)
+                if (use[s][cell(q, m)]) {
+                    kid[cell(q, m)] = (int32_t)sp.key_nq.size();
+                    sp.key_nq.push_back(q);
+                    sp.key_m2.push_back(m);
+                }
         const int nk = sp.nk();
-        std::vector<std::vector<int64_t>> members(nk);
-        for (size_t r = 0; r < raw[s].size(); r++) {
-            auto it = kid.find({raw[s][r].nq, raw[s][r].m2});
-            if (it != kid.end()) members[it->second].push_back((int64_t)r);
-        }
         sp.key_off.assign(nk + 1, 0);
-        for (int k = 0; k < nk; k++) sp.key_off[k + 1] = sp.key_off[k] + (int32_t)members[k].size();
+        for (int k = 0; k < nk; k++)
+            sp.key_off[k + 1] = sp.key_off[k] + present[s][cell(sp.key_nq[k], sp.key_m2[k])];
+        std::vector<int64_t> order(sp.key_off[nk]);
+        std::vector<int32_t> fillp(sp.key_off.begin(), sp.key_off.end() - 1);
+        for (size_t r = 0; r < raw[s].size(); r++) {
+            const int k = kid[cell(raw[s][r].nq, raw[s][r].m2)];
+            if (k >= 0) order[fillp[k]++] = (int64_t)r;
+        }
         const int W = hb.W;
         sp.sd.assign((size_t)sp.key_off[nk] * W, 0);
         sp.sd_key.assign(sp.key_off[nk], 0);
+        // the enumeration is in colex order, so each key's bucket already is
         for (int k = 0; k < nk; k++) {
-            std::vector<int64_t>& m = members[k];
-            std::sort(m.begin(), m.end(), [&](int64_t a, int64_t b) {
-                return colex_less(raw[s][a].bits.data(), raw[s][b].bits.data(), W);
-            });
-            for (size_t t = 0; t < m.size(); t++) {
-                int64_t g = sp.key_off[k] + (int64_t)t;
-                std::memcpy(&sp.sd[g * W], raw[s][m[t]].bits.data(), W * sizeof(uint64_t));
+            for (int64_t g = sp.key_off[k]; g < sp.key_off[k + 1]; g++) {
+                std::memcpy(&sp.sd[g * W], raw[s][order[g]].bits.data(), W * sizeof(uint64_t));
                 sp.sd_key[g] = k;
             }
         }
@@ -199,6 +207,8 @@ int make_tbme_index(HostBasis& hb, std::string& err)
 {
     const int n = hb.nsps;
     const ci_problem& p = hb.prob;
+    int maxm = 0;
+    for (int m : hb.orb_m2) maxm = std::max(maxm, m);
     hb.pair.assign((size_t)3 * n * n, kNoPair);
     hb.sec_off.clear();
     hb.sec_n.clear();
@@ -207,28 +217,36 @@ int make_tbme_index(HostBasis& hb, std::string& err)
         const int z = 2 - cls;            // protons in the pair
         if (p.Z - z < 0 || p.N - (2 - z) < 0) continue;
         const int n2max = hb.N0 - (lowest_quanta(p.Z - z) + lowest_quanta(p.N - (2 - z))) + p.nmax;
-        // pairs of this class grouped by (2M, parity), each group lexicographic
-        std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> groups;
+        // sectors of this class on a dense (2M, parity) grid: count, number in
+        // (2M, parity) order, then give each pair its lexicographic position
+        const int nm = 4 * maxm + 1;
+        std::vector<int32_t> cnt(2 * nm, 0), sid(2 * nm, -1);
+        auto valid = [&](int a, int b) { return hb.orb_n[a] + hb.orb_n[b] <= n2max; };
+        auto slot = [&](int a, int b) {
+            return (hb.orb_m2[a] + hb.orb_m2[b] + 2 * maxm) * 2 + ((hb.orb_n[a] + hb.orb_n[b]) & 1);
+        };
         for (int a = 0; a < n; a++)
-            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++) {
-                const int q = hb.orb_n[a] + hb.orb_n[b];
-                if (q > n2max) continue;
-                groups[{hb.orb_m2[a] + hb.orb_m2[b], q & 1}].push_back({a, b});
-            }
-        for (auto& kv : groups) {
+            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++)
+                if (valid(a, b)) cnt[slot(a, b)]++;
+        for (int t = 0; t < 2 * nm; t++) {
+            if (!cnt[t]) continue;
             const int sec = (int)hb.sec_n.size();
-            const int32_t cnt = (int32_t)kv.second.size();
-            if (sec >= 65536 || cnt > 65536) {
+            if (sec >= 65536 || cnt[t] > 65536) {
                 err = "two-body sector too large for the pair index";
                 return CI_EUNSUPPORTED;
             }
-            for (int32_t t = 0; t < cnt; t++)
-                hb.pair[(size_t)cls * n * n + (size_t)kv.second[t].first * n + kv.second[t].second] =
-                    ((uint32_t)sec << 16) | (uint32_t)t;
-            hb.sec_n.push_back(cnt);
+            sid[t] = sec;
+            hb.sec_n.push_back(cnt[t]);
             hb.sec_off.push_back(total);
-            total += (int64_t)cnt * (cnt + 1) / 2;
+            total += (int64_t)cnt[t] * (cnt[t] + 1) / 2;
+            cnt[t] = 0;  // reused as the running position
         }
+        for (int a = 0; a < n; a++)
+            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++)
+                if (valid(a, b)) {
+                    const int t = slot(a, b);
+                    hb.pair[(size_t)cls * n * n + (size_t)a * n + b] = ((uint32_t)sid[t] << 16) | (uint32_t)cnt[t]++;
+                }
     }
     hb.n_tbme = total;
     if (total >= ((int64_t)1 << 31)) {
