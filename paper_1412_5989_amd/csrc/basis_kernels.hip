@@ -8,7 +8,7 @@
 // For each kept y the moved orbits are decoded with __ffsll (particles in x
 // and not in y, holes in y and not in x) and the fermion phase is taken from
 // masked popcounts.  Ballot compaction keeps the records in ascending y, so
-// every key is one contiguous segment.  Two passes: count, then fill.
+// every key is one contiguous segment.  Passes: count (per key), offsets, fill.
 #include <hip/hip_runtime.h>
 
 #include "ci_internal.h"
@@ -83,90 +83,211 @@ __device__ uint64_t partner_record(const uint64_t* x, const uint64_t* y, int W, 
     return make_rec(yl, 2, h1, p1, h2, p2, e & 1);
 }
 
-template <bool FILL>
+// Work item = (determinant x, key group g): the keys are cut into kGroups
+// groups by the position of their first determinant, and one wavefront scans
+// the candidates of one group for one x.  The count pass writes the number of
+// partners of x in each key; a per-x scan turns those into segment offsets;
+// the fill pass writes each key's records at its offset.
+constexpr int kGroups = 8;
+
+// keys [k0, k1) of group g: those whose first determinant lies in the g-th slice
+__device__ __forceinline__ void key_group(const __attribute__((address_space(1))) int32_t* key_off, int nk,
+                                          int nsd, int g, int* k0, int* k1)
+{
+    const int lo = (int)((int64_t)nsd * g / kGroups), hi = (int)((int64_t)nsd * (g + 1) / kGroups);
+    int a = 0, b = 0;
+    while (a < nk && key_off[a] < lo) a++;
+    b = a;
+    while (b < nk && key_off[b] < hi) b++;
+    *k0 = a;
+    *k1 = b;
+}
+
+// sum over the 64 lanes (DPP row shifts, row broadcasts), result in every lane
+__device__ __forceinline__ int wave_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+template <int W, bool FILL>
 __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs A)
 {
     const int lane = threadIdx.x & 63;
-    const int x = (int)blockIdx.x * kPartnerWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = (int)blockIdx.x * kPartnerWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x = item / kGroups, g = item - x * kGroups;
     if (x >= A.nsd) return;
-    const int W = A.W;
-    uint64_t xw[kMaxWords];
+    const int nsd = A.nsd;
     const auto sd = glb(A.sd);
     const auto key_off = glb(A.key_off), key_nq = glb(A.key_nq), key_m2 = glb(A.key_m2);
-    for (int t = 0; t < kMaxWords; t++) xw[t] = t < W ? sd[(int64_t)x * W + t] : 0;
+    int k0, k1;
+    key_group(key_off, A.nk, nsd, g, &k0, &k1);
+    if (k0 >= k1) return;
+    uint64_t xw[W];
+    const __attribute__((address_space(1))) uint64_t* col[W];  // word t of every determinant
+#pragma unroll
+    for (int t = 0; t < W; t++) {
+        xw[t] = sd[(int64_t)x * W + t];
+        col[t] = glb(A.sdT) + (int64_t)t * nsd;
+    }
     const int kx = glb(A.sd_key)[x];
     const int mx = key_m2[kx], qx = key_nq[kx];
-    int c1 = 0, c12 = 0;
-    const int64_t o1 = FILL ? glb(A.l1_ptr)[x] : 0, o12 = FILL ? glb(A.l12_ptr)[x] : 0;
     const auto s1 = glbw(A.seg1 + (int64_t)x * (A.nk + 1));
     const auto s12 = glbw(A.seg12 + (int64_t)x * (A.nk + 1));
+    const int64_t o1 = FILL ? glb(A.l1_ptr)[x] : 0, o12 = FILL ? glb(A.l12_ptr)[x] : 0;
     const auto l1 = glbw(A.l1), l12 = glbw(A.l12);
-    for (int k = 0; k < A.nk; k++) {
-        if (FILL && lane == 0) {
-            s1[k] = c1;
-            s12[k] = c12;
-        }
+    for (int k = k0; k < k1; k++) {
         const bool same = key_m2[k] == mx && ((key_nq[k] - qx) & 1) == 0;
-        const int c12k = c12;  // first l12 record of key k
         const int y0 = key_off[k], y1 = key_off[k + 1];
+        if (!FILL) {
+            // count only: per-lane counters, one reduction per key
+            int n1 = 0, n12 = 0;
+            for (int yb = y0; yb < y1; yb += 64) {
+                const int y = yb + lane;
+                const int yc = y < y1 ? y : y1 - 1;
+                int pc = 0;
+#pragma unroll
+                for (int t = 0; t < W; t++) pc += __popcll(xw[t] ^ col[t][yc]);
+                const bool ok = y < y1;
+                n1 += (ok && pc <= 2) ? 1 : 0;
+                n12 += (ok && same && pc <= 4) ? 1 : 0;
+            }
+            n1 = wave_sum(n1);
+            n12 = wave_sum(n12);
+            if (lane == 0) {
+                s1[k] = n1;
+                s12[k] = n12;
+            }
+            continue;
+        }
+        int c1 = s1[k], c12 = s12[k];
         for (int yb = y0; yb < y1; yb += 64) {
             const int y = yb + lane;
-            int pc = 64;
-            uint64_t yw[kMaxWords] = {0, 0, 0, 0};
-            if (y < y1) {
-                pc = 0;
-                for (int t = 0; t < W; t++) {
-                    yw[t] = sd[(int64_t)y * W + t];
-                    pc += __popcll(xw[t] ^ yw[t]);
-                }
-            }
-            const bool in1 = pc <= 2;
-            const bool in12 = same && pc <= 4;
+            const int yc = y < y1 ? y : y1 - 1;
+            int pc = 0;
+#pragma unroll
+            for (int t = 0; t < W; t++) pc += __popcll(xw[t] ^ col[t][yc]);
+            const bool in1 = y < y1 && pc <= 2;
+            const bool in12 = y < y1 && same && pc <= 4;
             const uint64_t m1 = __ballot(in1), m12 = __ballot(in12);
-            if (FILL && (in1 || in12)) {
-                const uint64_t rec = partner_record(xw, yw, W, pc, (uint32_t)(y - y0));
-                if (in1) {
-                    const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0));
-                    l1[o1 + c1 + r] = rec;
-                }
-                if (in12) {
-                    const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m12 >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m12, 0));
-                    l12[o12 + c12 + r] = rec;
-                    if (y == x) glbw(A.self12)[x] = c12 - c12k + r;
-                }
+            // placeholder (x, y); decoded into a partner record afterwards
+            const uint64_t ph = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+            if (in1) {
+                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0));
+                l1[o1 + c1 + r] = ph;
+            }
+            if (in12) {
+                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m12 >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m12, 0));
+                l12[o12 + c12 + r] = ph;
             }
             c1 += __popcll(m1);
             c12 += __popcll(m12);
         }
     }
-    if (lane == 0) {
-        if (FILL) {
-            s1[A.nk] = c1;
-            s12[A.nk] = c12;
-        } else {
-            glbw(A.l1_ptr)[x + 1] = c1;
-            glbw(A.l12_ptr)[x + 1] = c12;
+}
+
+// One lane per partner: the placeholder (x, y) becomes the partner record
+// (local index of y, moved orbits, phase, d).  For l12 also records the
+// position of x itself inside its own key segment.
+__global__ void __launch_bounds__(256) partner_decode(PartnerArgs A, uint64_t* list, int64_t n, bool is12)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const auto lst = glbw(list);
+    const uint64_t ph = lst[t];
+    const int x = (int)(ph >> 32), y = (int)(uint32_t)ph;
+    const int W = A.W;
+    const auto sd = glb(A.sd);
+    uint64_t xw[kMaxWords], yw[kMaxWords];
+    int pc = 0;
+    for (int w = 0; w < kMaxWords; w++) {
+        xw[w] = w < W ? sd[(int64_t)x * W + w] : 0;
+        yw[w] = w < W ? sd[(int64_t)y * W + w] : 0;
+        pc += __popcll(xw[w] ^ yw[w]);
+    }
+    const int ky = glb(A.sd_key)[y];
+    lst[t] = partner_record(xw, yw, W, pc, (uint32_t)(y - glb(A.key_off)[ky]));
+    if (is12 && x == y)
+        glbw(A.self12)[x] = (int)(t - glb(A.l12_ptr)[x] - glb(A.seg12)[(int64_t)x * (A.nk + 1) + ky]);
+}
+
+// Per determinant x: segment counts -> segment offsets (exclusive scan over
+// the keys), list lengths into l*_ptr[x + 1].
+__global__ void __launch_bounds__(64 * kPartnerWaves) partner_offsets(PartnerArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int x = (int)blockIdx.x * kPartnerWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (x >= A.nsd) return;
+    const auto s1 = glbw(A.seg1 + (int64_t)x * (A.nk + 1));
+    const auto s12 = glbw(A.seg12 + (int64_t)x * (A.nk + 1));
+    int run1 = 0, run12 = 0;
+    for (int k0 = 0; k0 < A.nk; k0 += 64) {
+        const int k = k0 + lane;
+        const int a = k < A.nk ? s1[k] : 0, b = k < A.nk ? s12[k] : 0;
+        int ia = a, ib = b;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ua = __shfl_up(ia, o, 64), ub = __shfl_up(ib, o, 64);
+            if (lane >= o) {
+                ia += ua;
+                ib += ub;
+            }
         }
+        if (k < A.nk) {
+            s1[k] = run1 + ia - a;
+            s12[k] = run12 + ib - b;
+        }
+        run1 += __shfl(ia, 63, 64);
+        run12 += __shfl(ib, 63, 64);
+    }
+    if (lane == 0) {
+        s1[A.nk] = run1;
+        s12[A.nk] = run12;
+        glbw(A.l1_ptr)[x + 1] = run1;
+        glbw(A.l12_ptr)[x + 1] = run12;
     }
 }
 
 }  // namespace
 
+static inline unsigned grid_of(int64_t items) { return (unsigned)((items + kPartnerWaves - 1) / kPartnerWaves); }
+
+template <bool FILL>
+static void launch_scan(const PartnerArgs& a, hipStream_t s)
+{
+    const dim3 g(grid_of((int64_t)a.nsd * kGroups)), b(64 * kPartnerWaves);
+    switch (a.W) {
+        case 1: hipLaunchKernelGGL((partner_kernel<1, FILL>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((partner_kernel<2, FILL>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((partner_kernel<3, FILL>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((partner_kernel<4, FILL>), g, b, 0, s, a); break;
+    }
+}
+
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s)
 {
-    if (a.nsd > 0)
-        hipLaunchKernelGGL(partner_kernel<false>, dim3((a.nsd + kPartnerWaves - 1) / kPartnerWaves),
-                           dim3(64 * kPartnerWaves), 0, s, a);
+    if (a.nsd > 0) {
+        launch_scan<false>(a, s);
+        hipLaunchKernelGGL(partner_offsets, dim3(grid_of(a.nsd)), dim3(64 * kPartnerWaves), 0, s, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_partner_fill(const PartnerArgs& a, hipStream_t s)
+hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hipStream_t s)
 {
-    if (a.nsd > 0)
-        hipLaunchKernelGGL(partner_kernel<true>, dim3((a.nsd + kPartnerWaves - 1) / kPartnerWaves),
-                           dim3(64 * kPartnerWaves), 0, s, a);
+    if (a.nsd > 0) {
+        launch_scan<true>(a, s);
+        if (n1 > 0)
+            hipLaunchKernelGGL(partner_decode, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, a, a.l1, n1, false);
+        if (n12 > 0)
+            hipLaunchKernelGGL(partner_decode, dim3((unsigned)((n12 + 255) / 256)), dim3(256), 0, s, a, a.l12, n12, true);
+    }
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, 
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
-hipError_t launch_partner_fill(const PartnerArgs& a, hipStream_t s);
+hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hipStream_t s);
 }  // namespace ci
 
 using namespace ci;
@@ -107,7 +107,7 @@ void fill_info(const HostBasis& hb, ci_basis_info& in)
 
 // offsets of one species' tables in the arena
 struct SpOff {
-    size_t sd, sd_key, key_off, key_nq, key_m2, l1_ptr, l12_ptr, seg1, seg12, self12;
+    size_t sd, sdT, sd_key, key_off, key_nq, key_m2, l1_ptr, l12_ptr, seg1, seg12, self12;
 };
 struct UOff {
     SpOff sp[2];
@@ -194,6 +194,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             SpOff& o = uo[u].sp[sidx];
             const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
             o.sd = L.take<uint64_t>(sp.sd.size());
+            o.sdT = L.take<uint64_t>(sp.sd.size());
             o.sd_key = L.take<int32_t>(nsd);
             o.key_off = L.take<int32_t>(nk + 1);
             o.key_nq = L.take<int32_t>(nk);
@@ -246,6 +247,12 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             const HostSpecies& sp = hb.sp[sidx];
             const SpOff& o = uo[u].sp[sidx];
             put(o.sd, sp.sd.data(), sp.sd.size() * 8);
+            {
+                const int64_t nsd = sp.nsd();
+                uint64_t* T = (uint64_t*)(mirror.data() + o.sdT);
+                for (int64_t x = 0; x < nsd; x++)
+                    for (int w = 0; w < hb.W; w++) T[(int64_t)w * nsd + x] = sp.sd[x * hb.W + w];
+            }
             put(o.sd_key, sp.sd_key.data(), sp.sd_key.size() * 4);
             put(o.key_off, sp.key_off.data(), sp.key_off.size() * 4);
             put(o.key_nq, sp.key_nq.data(), sp.key_nq.size() * 4);
@@ -278,6 +285,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         const SpOff& o = uo[u].sp[sidx];
         PartnerArgs a{};
         a.sd = (const uint64_t*)D(o.sd);
+        a.sdT = (const uint64_t*)D(o.sdT);
         a.sd_key = (const int32_t*)D(o.sd_key);
         a.key_off = (const int32_t*)D(o.key_off);
         a.key_nq = (const int32_t*)D(o.key_nq);
@@ -331,7 +339,8 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             PartnerArgs a = args(u, sidx);
             a.l1 = (uint64_t*)(ldev + lo1[2 * u + sidx]);
             a.l12 = (uint64_t*)(ldev + lo12[2 * u + sidx]);
-            if ((e = launch_partner_fill(a, s)) != hipSuccess) return hip_fail(e, "partner fill");
+            if ((e = launch_partner_fill(a, totals[4 * u + 2 * sidx], totals[4 * u + 2 * sidx + 1], s)) != hipSuccess)
+                return hip_fail(e, "partner fill");
         }
 
     // ---- per-problem descriptors

@@ -110,6 +110,7 @@ struct HostBasis {
 // Arguments of the device partner-list kernels (basis_kernels.hip), one species.
 struct PartnerArgs {
     const uint64_t* sd;      // [nsd][W]
+    const uint64_t* sdT;     // [W][nsd] (word-major copy for coalesced candidate loads)
     const int32_t* sd_key;   // [nsd]
     const int32_t* key_off;  // [nk + 1]
     const int32_t* key_nq;   // [nk]
