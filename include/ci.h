@@ -99,6 +99,21 @@ typedef struct {
 
 typedef struct ci_basis ci_basis; /* opaque */
 
+/* Launch shapes of the row passes (count, fill) and of the adjoint, kept in
+ * the handle.  Every shape computes the same result; only the time differs.
+ * The row passes take one row per wavefront: either a grid that covers every
+ * row once (row_grab = 0), or a persistent grid (as many workgroups as the
+ * device holds at once) whose wavefronts take row_grab consecutive rows at a
+ * time from a work counter until none are left.  The adjoint gives each
+ * workgroup groups of adj_rows consecutive rows whose contributions are summed
+ * in one shared-memory table before they reach the FP64 accumulators. */
+typedef struct {
+    int32_t row_waves;      /* wavefronts per workgroup of count and fill: 4 or 8 */
+    int32_t row_grab;       /* 0: one grid over all rows; 1..4096: persistent, rows per grab */
+    int32_t adj_rows;       /* adjoint rows per group: 1..4096 */
+    int32_t adj_persistent; /* adjoint: 0 one workgroup per group, 1 persistent workgroups */
+} ci_tuning;
+
 /* Thread-local text of the last error. */
 const char* ci_last_error(void);
 
@@ -140,6 +155,24 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
 
 /* Bytes of work needed by ci_hamiltonian_vjp for this handle. */
 size_t ci_vjp_work_bytes(const ci_basis* b);
+
+/* Autotuner (batched construction): times every candidate launch shape of
+ * the fill and of the adjoint on the caller's buffers (one warm-up and `reps`
+ * timed runs each, with HIP events on `stream`), keeps the fastest in the
+ * handle, and remembers it for handles later built from the same problem
+ * list in this process.  col, val and grad_tbme end up holding the results of
+ * a normal fill / vjp.  Synchronizes the stream; not for use inside graph
+ * capture.  CI_EINVAL for null pointers or reps < 1, CI_ESPACE for a short
+ * work buffer. */
+int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                        float* val, const float* grad_val, float* grad_tbme, void* work,
+                        size_t work_bytes, int32_t reps, ci_stream stream);
+
+/* Current launch shapes of the handle; set them by hand (CI_EINVAL when a
+ * field is out of range).  Calls on one handle share its work counter, so
+ * they must be ordered (one stream, or synchronized between streams). */
+int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t);
+int ci_basis_set_tuning(ci_basis* b, const ci_tuning* t);
 
 /* Number of problems in the handle; info of problem `prob`. */
 int32_t ci_basis_count(const ci_basis* b);

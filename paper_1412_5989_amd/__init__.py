@@ -56,9 +56,18 @@ class ci_basis_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ci_tuning(ctypes.Structure):
+    _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
+                ("adj_persistent", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
+           "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
 _lib = None
@@ -83,6 +92,9 @@ def load_library():
     L.ci_hamiltonian_count.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
+    L.ci_basis_get_tuning.argtypes = [vp, P(ci_tuning)]
+    L.ci_basis_set_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_vjp_work_bytes.argtypes = [vp]
     L.ci_vjp_work_bytes.restype = sz
     L.ci_basis_count.argtypes = [vp]
@@ -185,6 +197,21 @@ class Basis:
     def vjp_work_bytes(self) -> int:
         return int(load_library().ci_vjp_work_bytes(self._h))
 
+    @property
+    def tuning(self) -> dict:
+        """Launch shapes of the handle (see ci_tuning in include/ci.h)."""
+        t = ci_tuning()
+        _check(load_library().ci_basis_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    @tuning.setter
+    def tuning(self, d: dict):
+        t = ci_tuning()
+        _check(load_library().ci_basis_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in d.items():
+            setattr(t, k, int(v))
+        _check(load_library().ci_basis_set_tuning(self._h, ctypes.byref(t)))
+
     def states(self, prob: int = 0):
         torch = _torch()
         i = self.info[prob]
@@ -253,6 +280,30 @@ def ci_hamiltonian_vjp(basis: Basis, row_ptr, grad_val, grad_tbme=None, work=Non
                                              _ptr(work), work.numel() * work.element_size(),
                                              _stream_ptr(stream)))
     return grad_tbme
+
+
+def ci_hamiltonian_tune(basis: Basis, tbme, row_ptr, col, val, grad_val, grad_tbme=None, work=None,
+                        reps: int = 3, stream=None) -> dict:
+    """Autotuner: times the launch shapes of fill and adjoint on these buffers,
+    keeps the fastest in the handle (and for later handles of the same
+    problems); returns the chosen shapes."""
+    torch = _torch()
+    tot = sum(basis.nnz)
+    _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    _check_tensor(col, torch.int32, tot, "col")
+    _check_tensor(val, torch.float32, tot, "val")
+    _check_tensor(grad_val, torch.float32, tot, "grad_val")
+    if grad_tbme is None:
+        grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
+    nwork = basis.vjp_work_bytes()
+    if work is None:
+        work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
+    _check(load_library().ci_hamiltonian_tune(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                              _ptr(grad_val), _ptr(grad_tbme), _ptr(work),
+                                              work.numel() * work.element_size(), int(reps),
+                                              _stream_ptr(stream)))
+    return basis.tuning
 
 
 def _make_autograd():

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -15,15 +16,15 @@
 namespace ci {
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
-                        hipStream_t s);
+                        const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_t* last, int64_t* nnz,
                       int n, hipStream_t s);
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       hipStream_t s);
+                       const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                       const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
-                      int64_t ntbme, hipStream_t s);
+                      int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
@@ -59,6 +60,9 @@ struct ci_basis {
     int64_t* d_seg_last = nullptr;    // R_b + D_b
     int64_t* d_scan_tmp = nullptr;
     int64_t* d_nnz = nullptr;
+    unsigned long long* d_queue = nullptr;  // work counter of the persistent launches
+    ci_tuning tune{};
+    std::vector<ci_problem> probs;          // key of the process-wide tuning cache
     int64_t n_rowptr = 0;
     int64_t n_tbme = 0;
     ~ci_basis()
@@ -117,7 +121,56 @@ struct UOff {
 
 }  // namespace
 
+namespace {
+
+// Mean time (ms) of reps runs of f on stream s after one warm-up run.
+template <typename F>
+int time_ms(F f, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms)
+{
+    hipError_t e = f();
+    for (int r = 0; r <= reps && e == hipSuccess; r++) {
+        if (r == 1) e = hipEventRecord(e0, s);
+        if (e == hipSuccess && r > 0) e = f();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ms /= (float)reps;
+    return CI_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+// Process-wide cache of tuned launch shapes, keyed by the problem list.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::vector<std::tuple<int, int, int, int, int, double>>, ci_tuning> g_tune;
+
+std::vector<std::tuple<int, int, int, int, int, double>> tune_key(const std::vector<ci_problem>& p)
+{
+    std::vector<std::tuple<int, int, int, int, int, double>> k;
+    for (const ci_problem& q : p) k.emplace_back(q.Z, q.N, q.nmax, q.two_m, q.parity, q.hw_mev);
+    return k;
+}
+
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 0}; }
+
+ci_tuning cached_tuning(const std::vector<ci_problem>& p)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(p));
+    return it == g_tune.end() ? default_tuning() : it->second;
+}
+
+void remember_tuning(const std::vector<ci_problem>& p, const ci_tuning& t)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[tune_key(p)] = t;
+}
+}  // namespace
 
 const char* ci_last_error(void) { return g_err.c_str(); }
 
@@ -226,6 +279,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     const size_t o_last = L.take<int64_t>(n_probs);
     const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
     const size_t o_nnz = L.take<int64_t>(n_probs);
+    const size_t o_queue = L.take<unsigned long long>(1);
     const size_t bytes = L.bytes();
 
     hipError_t e = hipGetDevice(&h->device);
@@ -403,6 +457,9 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     h->d_seg_last = (int64_t*)D(o_last);
     h->d_scan_tmp = scan_tmp;
     h->d_nnz = (int64_t*)D(o_nnz);
+    h->d_queue = (unsigned long long*)D(o_queue);
+    h->probs.assign(probs, probs + n_probs);
+    h->tune = cached_tuning(h->probs);
     h->nrows = row0[n_probs];
     h->n_rowptr = R;
     h->n_tbme = T;
@@ -431,7 +488,7 @@ int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_s
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)b->info.size();
     hipError_t e = launch_count(b->d_bases, n, b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, b->d_seg_first,
-                                b->d_scan_tmp, s);
+                                b->d_scan_tmp, b->tune, b->d_queue, s);
     if (e != hipSuccess) return hip_fail(e, "count launch");
     e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
     if (e != hipSuccess) return hip_fail(e, "nnz launch");
@@ -447,7 +504,7 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
 {
     if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     hipError_t e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr,
-                               b->n_rowptr, col, val, (hipStream_t)stream);
+                               b->n_rowptr, col, val, b->tune, b->d_queue, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     return CI_OK;
 }
@@ -462,8 +519,111 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
     hipError_t e = launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr,
-                              grad_val, grad_tbme, (double*)work, b->n_tbme, (hipStream_t)stream);
+                              grad_val, grad_tbme, (double*)work, b->n_tbme, b->tune, b->d_queue,
+                              (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "vjp launch");
+    return CI_OK;
+}
+
+static bool tuning_ok(const ci_tuning& t)
+{
+    return (t.row_waves == 4 || t.row_waves == 8) && t.row_grab >= 0 && t.row_grab <= 4096 && t.adj_rows >= 1 &&
+           t.adj_rows <= 4096 && (t.adj_persistent == 0 || t.adj_persistent == 1);
+}
+
+int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
+{
+    if (!b || !t) return fail(CI_EINVAL, "null pointer");
+    *t = b->tune;
+    return CI_OK;
+}
+
+int ci_basis_set_tuning(ci_basis* b, const ci_tuning* t)
+{
+    if (!b || !t) return fail(CI_EINVAL, "null pointer");
+    if (!tuning_ok(*t)) return fail(CI_EINVAL, "launch shape out of range");
+    b->tune = *t;
+    return CI_OK;
+}
+
+
+int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
+                        const float* grad_val, float* grad_tbme, void* work, size_t work_bytes, int32_t reps,
+                        ci_stream stream)
+{
+    if (!b || !row_ptr || !grad_val || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
+    if (reps < 1) return fail(CI_EINVAL, "reps must be >= 1");
+    if (work_bytes < ci_vjp_work_bytes(b))
+        return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const ci_tuning start = b->tune;
+    ci_tuning best = start;
+    int rc = CI_OK;
+    // fill: waves per workgroup x (grid, persistent with several grab sizes)
+    float best_ms = 0.0f;
+    bool have = false;
+    for (int waves : {4, 8})
+        for (int grab : {0, 1, 4, 16}) {
+            if (rc != CI_OK) break;
+            b->tune = start;
+            b->tune.row_waves = waves;
+            b->tune.row_grab = grab;
+            float ms = 0.0f;
+            rc = time_ms([&] { return launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme,
+                                                  row_ptr, b->n_rowptr, col, val, b->tune, b->d_queue, s); },
+                         reps, s, e0, e1, &ms);
+            if (rc == CI_OK && (!have || ms < best_ms)) {
+                best_ms = ms;
+                best.row_waves = waves;
+                best.row_grab = grab;
+                have = true;
+            }
+        }
+    // adjoint: rows per shared table x (grid, persistent)
+    have = false;
+    for (int rows : {16, 32, 64})
+        for (int pers : {0, 1}) {
+            if (rc != CI_OK) break;
+            b->tune = best;
+            b->tune.adj_rows = rows;
+            b->tune.adj_persistent = pers;
+            float ms = 0.0f;
+            rc = time_ms([&] { return launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows,
+                                                 row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work,
+                                                 b->n_tbme, b->tune, b->d_queue, s); },
+                         reps, s, e0, e1, &ms);
+            if (rc == CI_OK && (!have || ms < best_ms)) {
+                best_ms = ms;
+                best.adj_rows = rows;
+                best.adj_persistent = pers;
+                have = true;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != CI_OK) {
+        b->tune = start;
+        return rc;
+    }
+    b->tune = best;
+    remember_tuning(b->probs, best);
+    // leave col / val / grad_tbme as the chosen shapes compute them
+    e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
+                    val, b->tune, b->d_queue, s);
+    if (e == hipSuccess)
+        e = launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, grad_val,
+                       grad_tbme, (double*)work, b->n_tbme, b->tune, b->d_queue, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "autotune final run");
     return CI_OK;
 }
 

@@ -28,6 +28,8 @@
 // adjoint (step 3 scatters phase * upstream value onto the table).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "ci_internal.h"
 
 namespace ci {
@@ -69,6 +71,22 @@ __device__ __forceinline__ gmut<T> glbw(T* p)
 {
     return (gmut<T>)p;
 }
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+
+// Adjoint: the rows of a workgroup scatter into a shared LDS table first
+// (open addressing on the global table position, FP32 partial sums), and each
+// occupied slot is added to the FP64 accumulator once at the end.  Table keys
+// repeat across consecutive rows (the same proton move for every row of one
+// proton determinant, and overlapping neutron moves), so the number of
+// device-scope atomics drops by that reuse factor.  A key that finds no slot
+// within kAdjProbes probes goes to the accumulator directly.
+constexpr int kAdjWaves = 8;
+constexpr int kAdjSlotBits = 12;
+constexpr int kAdjSlots = 1 << kAdjSlotBits;
+constexpr int kAdjProbes = 8;
+constexpr uint32_t kAdjEmpty = 0xffffffffu;
+
 __device__ __forceinline__ int64_t uniform64(int64_t v)
 {
     const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -175,6 +193,9 @@ struct RowView {
     const BasisDev* B;
     const float* tbme;  // this basis' table (fill)
     double* gacc;       // this basis' accumulators (adjoint)
+    int64_t tbme0;      // this basis' first table position in the batch
+    lptr<uint32_t> hkey;  // LDS accumulator table of the workgroup (adjoint), or null
+    lptr<float> hval;
     const float* gval;  // upstream values (adjoint)
     int32_t* col;
     float* val;
@@ -183,6 +204,27 @@ struct RowView {
     int Z, NN;     // particles
     double spe_sum;
 };
+
+// Adjoint contribution g to table position k of the row's basis.
+__device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
+{
+    if (R.hkey) {
+        const uint32_t gk = (uint32_t)(R.tbme0 + k);
+        uint32_t s = (gk * 2654435761u) >> (32 - kAdjSlotBits);
+        for (int t = 0; t < kAdjProbes; t++) {
+            // claim an empty slot, or learn which key holds it (one LDS round trip)
+            uint32_t cur = kAdjEmpty;
+            const bool won = __hip_atomic_compare_exchange_strong(R.hkey + s, &cur, gk, __ATOMIC_RELAXED,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (won || cur == gk) {
+                __hip_atomic_fetch_add(R.hval + s, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            s = (s + 1) & (kAdjSlots - 1);
+        }
+    }
+    atomic_add_f64(glbw(R.gacc) + k, (double)g);
+}
 
 // number of two-body terms of a queued entry
 __device__ __forceinline__ int queued_terms(const RowView& R, uint64_t pr, uint64_t nr)
@@ -285,8 +327,8 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
                 } else {
                     const int64_t p = R.pos0 + L.qpos[q];
                     if (p < R.cap) {
-                        const double g = (double)glb(R.gval)[p];
-                        atomic_add_f64(glbw(R.gacc) + k, neg ? -g : g);
+                        const float g = glb(R.gval)[p];
+                        adj_add(R, k, neg ? -g : g);
                     }
                 }
             }
@@ -457,6 +499,8 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                     const int d = dp == 2 ? rec_h2(prj) : (dp == 1 ? rec_h1(nr) : rec_h2(nr));
                     const bool neg = rec_neg(prj) ^ rec_neg(nr);
                     const int64_t p = R.pos0 + pos + e;
+                    // upstream value first: its load overlaps the table lookup
+                    const float gv = (MODE == kAdjoint && !special && p < R.cap) ? glb(R.gval)[p] : 0.0f;
                     const int key = special ? -1 : tb_pos(B, cls, a, b, c, d);
                     if (p < R.cap) {
                         if (MODE == kFill) {
@@ -466,8 +510,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                                 glbw(R.val)[p] = neg ? -x : x;
                             }
                         } else if (key >= 0) {
-                            const double g = (double)glb(R.gval)[p];
-                            atomic_add_f64(glbw(R.gacc) + key, neg ? -g : g);
+                            adj_add(R, key, neg ? -gv : gv);
                         }
                     }
                 }
@@ -496,18 +539,16 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     return pos;
 }
 
-// One wavefront per row; the rows of all bases are numbered consecutively.
+// Row grow of the batch (rows of all bases are numbered consecutively) on the
+// calling wavefront.
 template <int MODE>
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
-    row_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
-               int64_t nrows, const float* __restrict__ tbme, int64_t* __restrict__ row_ptr, int64_t nrp,
-               int32_t* __restrict__ col, float* __restrict__ val, const float* __restrict__ gval,
-               double* __restrict__ gacc)
+__device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int nb,
+                                        const int64_t* __restrict__ basis_row0, int64_t grow,
+                                        const float* __restrict__ tbme, int64_t* __restrict__ row_ptr,
+                                        int64_t nrp, int32_t* __restrict__ col, float* __restrict__ val,
+                                        const float* __restrict__ gval, double* __restrict__ gacc,
+                                        lptr<uint32_t> hkey, lptr<float> hval, WaveLds& L)
 {
-    __shared__ WaveLds lds[kWavesPerBlock];
-    const int wid = uniform(threadIdx.x >> 6);
-    const int64_t grow = (int64_t)blockIdx.x * kWavesPerBlock + wid;
-    if (grow >= nrows) return;
     // basis of the row (few bases: linear search)
     int b = 0;
     while (b + 1 < nb && basis_row0[b + 1] <= grow) b++;
@@ -527,6 +568,9 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
     R.B = &B;
     R.tbme = tbme ? tbme + B.tbme0 : nullptr;
     R.gacc = gacc ? gacc + B.tbme0 : nullptr;
+    R.tbme0 = B.tbme0;
+    R.hkey = hkey;
+    R.hval = hval;
     R.gval = gval;
     R.col = col;
     R.val = val;
@@ -537,12 +581,103 @@ __global__ void __launch_bounds__(64 * kWavesPerBlock)
     if (MODE == kCount) {
         R.pos0 = 0;
         R.cap = 0;
-        const int64_t n = do_row<kCount>(B, lds[wid], bi, r, R);
+        const int64_t n = do_row<kCount>(B, L, bi, r, R);
         if ((threadIdx.x & 63) == 0) glbw(row_ptr)[B.row0 + i + 1] = n;
     } else {
         R.pos0 = uniform64(row_ptr[B.row0 + i]);
         R.cap = uniform64(row_ptr[nrp - 1]);  // the entries of all bases end here
-        do_row<MODE>(B, lds[wid], bi, r, R);
+        do_row<MODE>(B, L, bi, r, R);
+    }
+}
+
+// Count and fill.  grab == 0: one wavefront per row over a grid of all rows.
+// grab > 0: a persistent grid; each wavefront takes grab consecutive rows at a
+// time from the work counter *queue (zero at launch) until none are left.
+template <int MODE, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+    row_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
+               int64_t nrows, const float* __restrict__ tbme, int64_t* __restrict__ row_ptr, int64_t nrp,
+               int32_t* __restrict__ col, float* __restrict__ val, int grab, unsigned long long* __restrict__ queue)
+{
+    __shared__ WaveLds lds[WAVES];
+    const int wid = uniform(threadIdx.x >> 6);
+    if (grab <= 0) {
+        const int64_t grow = (int64_t)blockIdx.x * WAVES + wid;
+        if (grow < nrows)
+            run_row<MODE>(bases, nb, basis_row0, grow, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
+                          nullptr, lds[wid]);
+        return;
+    }
+    for (;;) {
+        unsigned long long t = 0;
+        if ((threadIdx.x & 63) == 0)
+            t = __hip_atomic_fetch_add(glbw(queue), (unsigned long long)grab, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t g0 = uniform64((int64_t)t);
+        if (g0 >= nrows) break;
+        const int64_t g1 = g0 + grab < nrows ? g0 + grab : nrows;
+        for (int64_t g = g0; g < g1; g++)
+            run_row<MODE>(bases, nb, basis_row0, g, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
+                          nullptr, lds[wid]);
+    }
+}
+
+// Adjoint: a workgroup takes a group of rows_per_group consecutive rows, its
+// wavefronts take them one at a time from a shared counter, and the
+// contributions meet in the LDS accumulator table, which is added to the FP64
+// accumulator and cleared when the group is done.  persistent == 0: group =
+// workgroup index; persistent == 1: a persistent grid takes groups from the
+// work counter *queue (zero at launch).  use_table == 0 (global table
+// positions do not fit 32 bits): every contribution goes to the accumulator.
+__global__ void __launch_bounds__(64 * kAdjWaves)
+    adjoint_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
+                   int64_t nrows, int rows_per_group, const int64_t* __restrict__ row_ptr, int64_t nrp,
+                   const float* __restrict__ gval, double* __restrict__ gacc, int use_table, int persistent,
+                   unsigned long long* __restrict__ queue)
+{
+    __shared__ WaveLds lds[kAdjWaves];
+    __shared__ uint32_t hkey[kAdjSlots];
+    __shared__ float hval[kAdjSlots];
+    __shared__ int next_row;
+    __shared__ int64_t group_first;
+    for (int s = threadIdx.x; s < kAdjSlots; s += 64 * kAdjWaves) {
+        hkey[s] = kAdjEmpty;
+        hval[s] = 0.0f;
+    }
+    const int wid = uniform(threadIdx.x >> 6);
+    const lptr<uint32_t> hk = use_table ? (lptr<uint32_t>)hkey : nullptr;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            next_row = 0;
+            const int64_t g = persistent ? (int64_t)__hip_atomic_fetch_add(glbw(queue), 1ull, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                         : (int64_t)blockIdx.x;
+            group_first = g * rows_per_group;
+        }
+        __syncthreads();
+        const int64_t first = group_first;
+        if (first >= nrows) break;
+        for (;;) {
+            int t = 0;
+            if ((threadIdx.x & 63) == 0) t = atomicAdd(&next_row, 1);
+            t = uniform(t);
+            if (t >= rows_per_group || first + t >= nrows) break;
+            run_row<kAdjoint>(bases, nb, basis_row0, first + t, nullptr, const_cast<int64_t*>(row_ptr), nrp,
+                              nullptr, nullptr, gval, gacc, hk, (lptr<float>)hval, lds[wid]);
+        }
+        __syncthreads();
+        if (use_table) {
+            for (int s = threadIdx.x; s < kAdjSlots; s += 64 * kAdjWaves) {
+                const uint32_t k = hkey[s];
+                if (k != kAdjEmpty) {
+                    atomic_add_f64(glbw(gacc) + k, (double)hval[s]);
+                    hkey[s] = kAdjEmpty;
+                    hval[s] = 0.0f;
+                }
+            }
+        }
+        __syncthreads();
+        if (!persistent) break;
     }
 }
 
@@ -668,14 +803,66 @@ hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void zero_u64(unsigned long long* __restrict__ p) { *p = 0; }
+
+// Workgroups of a persistent grid: as many as the device holds at once.
+// kind numbers the kernel for the per-device cache.
+static unsigned resident_blocks(const void* kernel, int threads, int kind)
+{
+    constexpr int kDevs = 64, kKinds = 8;
+    static std::atomic<int> cache[kDevs][kKinds];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) dev = 0;
+    int v = cache[dev][kind].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per <= 0)
+            per = 1;
+        v = cus * per;
+        cache[dev][kind].store(v, std::memory_order_relaxed);
+    }
+    return (unsigned)v;
+}
+
+template <int MODE, int WAVES>
+static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
+                          const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, int grab,
+                          unsigned long long* queue, hipStream_t s)
+{
+    unsigned grid = grid_for(nrows, WAVES);
+    if (grab > 0) {
+        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
+        const unsigned res = resident_blocks((const void*)row_kernel<MODE, WAVES>, 64 * WAVES,
+                                             2 * MODE + (WAVES == 8 ? 1 : 0));
+        const unsigned need = grid_for(nrows, WAVES * grab);
+        grid = res < need ? res : need;
+    }
+    hipLaunchKernelGGL((row_kernel<MODE, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, bases, nb, basis_row0,
+                       nrows, tbme, row_ptr, nrp, col, val, grab, queue);
+}
+
+template <int MODE>
+static hipError_t launch_rows(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
+                              const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
+                              const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+{
+    if (nrows <= 0) return hipSuccess;
+    if (t.row_waves == 8)
+        launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, s);
+    else
+        launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
-                        hipStream_t s)
+                        const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
-    if (nrows > 0)
-        hipLaunchKernelGGL(row_kernel<kCount>, dim3(grid_for(nrows, kWavesPerBlock)),
-                           dim3(64 * kWavesPerBlock), 0, s, bases, nb, basis_row0, nrows, nullptr, row_ptr,
-                           nrp, nullptr, nullptr, nullptr, nullptr);
+    hipError_t e = launch_rows<kCount>(bases, nb, basis_row0, nrows, nullptr, row_ptr, nrp, nullptr, nullptr, t,
+                                       queue, s);
+    if (e != hipSuccess) return e;
     // the first slot of each basis' segment holds 0 before the scan, so the
     // inclusive scan leaves there the number of entries of the bases before it
     hipLaunchKernelGGL(zero_i64_at, dim3(grid_for(nb, 256)), dim3(256), 0, s, row_ptr, seg_first, nb);
@@ -691,25 +878,30 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
 
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       hipStream_t s)
+                       const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
-    if (nrows > 0)
-        hipLaunchKernelGGL(row_kernel<kFill>, dim3(grid_for(nrows, kWavesPerBlock)), dim3(64 * kWavesPerBlock),
-                           0, s, bases, nb, basis_row0, nrows, tbme, const_cast<int64_t*>(row_ptr), nrp, col,
-                           val, nullptr, nullptr);
-    return hipGetLastError();
+    return launch_rows<kFill>(bases, nb, basis_row0, nrows, tbme, const_cast<int64_t*>(row_ptr), nrp, col, val, t,
+                              queue, s);
 }
 
 hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                       const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
-                      int64_t ntbme, hipStream_t s)
+                      int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
-    if (nrows > 0)
-        hipLaunchKernelGGL(row_kernel<kAdjoint>, dim3(grid_for(nrows, kWavesPerBlock)),
-                           dim3(64 * kWavesPerBlock), 0, s, bases, nb, basis_row0, nrows, nullptr,
-                           const_cast<int64_t*>(row_ptr), nrp, nullptr, nullptr, gval, gacc);
+    if (nrows > 0) {
+        const int rpg = t.adj_rows > 0 ? t.adj_rows : 32;
+        const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
+        unsigned grid = grid_for(nrows, rpg);
+        if (t.adj_persistent) {
+            hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
+            const unsigned res = resident_blocks((const void*)adjoint_kernel, 64 * kAdjWaves, 6);
+            grid = res < grid ? res : grid;
+        }
+        hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(64 * kAdjWaves), 0, s, bases, nb, basis_row0, nrows,
+                           rpg, row_ptr, nrp, gval, gacc, use_table, t.adj_persistent ? 1 : 0, queue);
+    }
     if (ntbme > 0) hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
     return hipGetLastError();
 }
