@@ -89,7 +89,7 @@ def measured_traffic(kernel_file: str):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=12.0):
+def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
     """The FP64 oracle on sampled rows: forward rows + their gradient."""
     import oracle
     import seeded_inputs as si
@@ -106,8 +106,9 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=12.0):
         o.grad_rows(rows, G)
         return int(counts.sum()), time.perf_counter() - t0, len(rows)
 
-    n, t, _ = run(64, 1)
-    nrows = int(min(o.dim, max(64, 64 * budget_s / max(t, 1e-3))))
+    run(64, 1)  # warm-up (threads, caches)
+    n, t, nr = run(256, 3)
+    nrows = int(min(o.dim, max(256, nr * budget_s / max(t, 1e-3))))
     n, t, nr = run(nrows, 2)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
@@ -317,6 +318,15 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes},
+    }
+    # measured machine ceilings (streaming stores; XOR + popcount issue rate)
+    ceil = ci.ci_probe_ceilings(1024)
+    res["measured_ceilings"] = {
+        "store_GBps": ceil["store_GBps"],
+        "xor_popcount_steps_per_s": ceil["xor_popcount_steps_per_s"],
+        "valu_lane_ops_per_s": 5 * ceil["xor_popcount_steps_per_s"],
+        "fill_store_GBps": (8 * nnz + 8 * (D + 1)) / (fill_ms * 1e-3) / 1e9,
+        "fill_frac_of_measured_store": (8 * nnz + 8 * (D + 1)) / (fill_ms * 1e-3) / 1e9 / ceil["store_GBps"],
     }
     if not args.no_batched:
         log("batched")

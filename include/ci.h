@@ -174,6 +174,15 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t);
 int ci_basis_set_tuning(ci_basis* b, const ci_tuning* t);
 
+/* Machine ceilings measured on the current device (the roofline of the
+ * construction kernels): streaming-store bandwidth over buf (device, caller
+ * owned, at least 64 MiB; overwritten) in GB/s, and the rate of 64-bit
+ * XOR + popcount difference-test steps (one step = XOR of two words, popcount,
+ * add) per second, from 8 independent chains per lane.  Synchronizes the stream.
+ * CI_ESPACE if bytes < 64 MiB. */
+int ci_probe_ceilings(void* buf, size_t bytes, double* store_gbs, double* diff_steps_per_s,
+                      ci_stream stream);
+
 /* Number of problems in the handle; info of problem `prob`. */
 int32_t ci_basis_count(const ci_basis* b);
 int ci_basis_get_info(const ci_basis* b, int32_t prob, ci_basis_info* info);

@@ -67,7 +67,7 @@ class ci_tuning(ctypes.Structure):
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
-           "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning",
+           "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
 _lib = None
@@ -95,6 +95,7 @@ def load_library():
     L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
     L.ci_basis_get_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_basis_set_tuning.argtypes = [vp, P(ci_tuning)]
+    L.ci_probe_ceilings.argtypes = [vp, sz, P(ctypes.c_double), P(ctypes.c_double), vp]
     L.ci_vjp_work_bytes.argtypes = [vp]
     L.ci_vjp_work_bytes.restype = sz
     L.ci_basis_count.argtypes = [vp]
@@ -304,6 +305,16 @@ def ci_hamiltonian_tune(basis: Basis, tbme, row_ptr, col, val, grad_val, grad_tb
                                               work.numel() * work.element_size(), int(reps),
                                               _stream_ptr(stream)))
     return basis.tuning
+
+
+def ci_probe_ceilings(mib: int = 1024, stream=None) -> dict:
+    """Measured store bandwidth (GB/s) and XOR + popcount steps/s of the device."""
+    torch = _torch()
+    buf = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    gbs, steps = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().ci_probe_ceilings(_ptr(buf), buf.numel(), ctypes.byref(gbs), ctypes.byref(steps),
+                                            _stream_ptr(stream)))
+    return {"store_GBps": gbs.value, "xor_popcount_steps_per_s": steps.value, "store_bytes": int(mib) << 20}
 
 
 def _make_autograd():

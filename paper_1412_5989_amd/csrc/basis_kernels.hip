@@ -251,6 +251,10 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_offsets(PartnerArg
         s12[A.nk] = run12;
         glbw(A.l1_ptr)[x + 1] = run1;
         glbw(A.l12_ptr)[x + 1] = run12;
+        if (x == 0) {  // so that the inclusive scan of l*_ptr gives offsets
+            glbw(A.l1_ptr)[0] = 0;
+            glbw(A.l12_ptr)[0] = 0;
+        }
     }
 }
 
@@ -270,11 +274,19 @@ static void launch_scan(const PartnerArgs& a, hipStream_t s)
     }
 }
 
+__global__ void partner_no_sd(PartnerArgs A)
+{
+    glbw(A.l1_ptr)[0] = 0;
+    glbw(A.l12_ptr)[0] = 0;
+}
+
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s)
 {
     if (a.nsd > 0) {
         launch_scan<false>(a, s);
         hipLaunchKernelGGL(partner_offsets, dim3(grid_of(a.nsd)), dim3(64 * kPartnerWaves), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(partner_no_sd, dim3(1), dim3(1), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -29,6 +29,7 @@ hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
 hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hipStream_t s);
+hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps, double* steps_per_s);
 }  // namespace ci
 
 using namespace ci;
@@ -118,6 +119,16 @@ struct UOff {
     size_t blk_kp, blk_kn, blk_off, pair, orb_n, totals;
     size_t bytes;
 };
+
+// Equal determinant tables (same orbits, words, keys and determinants) have
+// equal partner lists.
+bool same_species(const HostBasis& A, int sa, const HostBasis& B, int sb)
+{
+    const HostSpecies& a = A.sp[sa];
+    const HostSpecies& b = B.sp[sb];
+    return A.nsps == B.nsps && A.W == B.W && a.X == b.X && a.key_off == b.key_off && a.key_nq == b.key_nq &&
+           a.key_m2 == b.key_m2 && a.sd == b.sd;
+}
 
 }  // namespace
 
@@ -235,37 +246,78 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         ub.push_back(hb);
     }
 
-    // ---- allocation 1: index tables, per-problem descriptors, small buffers
+    // Species tables with equal content (protons and neutrons of an N = Z
+    // nucleus, or one species shared by several problems of a batch) are
+    // stored once and get their partner lists once: canon[2u + s] is the
+    // first equal species table.
+    const int nsp = 2 * (int)ub.size();
+    std::vector<int> canon(nsp);
+    for (int i = 0; i < nsp; i++) {
+        canon[i] = i;
+        for (int j = 0; j < i; j++)
+            if (canon[j] == j && same_species(*ub[i / 2], i % 2, *ub[j / 2], j % 2)) {
+                canon[i] = j;
+                break;
+            }
+    }
+
+    // ---- allocation 1: index tables, per-problem descriptors, small buffers.
+    // Tables the host writes come first (they are mirrored and copied up);
+    // tables the device computes follow (never copied).
     Layout L;
     std::vector<UOff> uo(ub.size());
+    std::vector<size_t> ubytes(ub.size(), 0);
     int64_t max_scan = 1;
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
-        size_t start = L.off;
         for (int sidx = 0; sidx < 2; sidx++) {
+            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
             const HostSpecies& sp = hb.sp[sidx];
             SpOff& o = uo[u].sp[sidx];
             const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
+            const size_t s0 = L.off;
             o.sd = L.take<uint64_t>(sp.sd.size());
             o.sdT = L.take<uint64_t>(sp.sd.size());
             o.sd_key = L.take<int32_t>(nsd);
             o.key_off = L.take<int32_t>(nk + 1);
             o.key_nq = L.take<int32_t>(nk);
             o.key_m2 = L.take<int32_t>(nk);
+            ubytes[u] += L.off - s0;
+        }
+        const size_t s0 = L.off;
+        uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
+        uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
+        uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
+        uo[u].pair = L.take<uint64_t>(hb.pair.size());
+        uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
+        ubytes[u] += L.off - s0;
+    }
+    const size_t o_row0 = L.take<int64_t>(n_probs + 1);
+    const size_t o_first = L.take<int64_t>(n_probs);
+    const size_t o_last = L.take<int64_t>(n_probs);
+    const size_t host_bytes = L.off;
+    for (size_t u = 0; u < ub.size(); u++) {
+        const HostBasis& hb = *ub[u];
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const int c = canon[2 * u + sidx];
+            SpOff& o = uo[u].sp[sidx];
+            if (c != (int)(2 * u + sidx)) {
+                o = uo[c / 2].sp[c % 2];
+                continue;
+            }
+            const HostSpecies& sp = hb.sp[sidx];
+            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
+            const size_t s0 = L.off;
             o.l1_ptr = L.take<int64_t>(nsd + 1);
             o.l12_ptr = L.take<int64_t>(nsd + 1);
             o.seg1 = L.take<int32_t>(nsd * (nk + 1));
             o.seg12 = L.take<int32_t>(nsd * (nk + 1));
             o.self12 = L.take<int32_t>(nsd);
+            ubytes[u] += L.off - s0;
             max_scan = std::max<int64_t>(max_scan, (int64_t)nsd + 1);
         }
-        uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
-        uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
-        uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
-        uo[u].pair = L.take<uint64_t>(hb.pair64.size());
-        uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
         uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
-        uo[u].bytes = L.off - start;
+        uo[u].bytes = ubytes[u];
     }
     int64_t R = 0, T = 0;
     for (int32_t b = 0; b < n_probs; b++) {
@@ -274,9 +326,6 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     }
     max_scan = std::max(max_scan, R);
     const size_t o_bases = L.take<BasisDev>(n_probs);
-    const size_t o_row0 = L.take<int64_t>(n_probs + 1);
-    const size_t o_first = L.take<int64_t>(n_probs);
-    const size_t o_last = L.take<int64_t>(n_probs);
     const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
     const size_t o_nnz = L.take<int64_t>(n_probs);
     const size_t o_queue = L.take<unsigned long long>(1);
@@ -290,20 +339,25 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     char* dev = (char*)h->arena;
     auto D = [&](size_t off) { return (void*)(dev + off); };
 
-    // host mirror; device pointers are the arena base plus the layout offsets
-    std::vector<char> mirror(bytes, 0);
+    // host mirror of the host-written tables (a per-thread buffer kept between
+    // builds; the stream is synchronized before this call returns, so the
+    // copy out of it is finished when the next build on the thread reuses it)
+    static thread_local std::vector<char> mirror_buf;
+    if (mirror_buf.size() < host_bytes) mirror_buf.resize(host_bytes);
+    char* mirror = mirror_buf.data();
     auto put = [&](size_t off, const void* src, size_t n) {
-        if (n) std::memcpy(mirror.data() + off, src, n);
+        if (n) std::memcpy(mirror + off, src, n);
     };
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
         for (int sidx = 0; sidx < 2; sidx++) {
+            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
             const HostSpecies& sp = hb.sp[sidx];
             const SpOff& o = uo[u].sp[sidx];
             put(o.sd, sp.sd.data(), sp.sd.size() * 8);
             {
                 const int64_t nsd = sp.nsd();
-                uint64_t* T = (uint64_t*)(mirror.data() + o.sdT);
+                uint64_t* T = (uint64_t*)(mirror + o.sdT);
                 for (int64_t x = 0; x < nsd; x++)
                     for (int w = 0; w < hb.W; w++) T[(int64_t)w * nsd + x] = sp.sd[x * hb.W + w];
             }
@@ -315,7 +369,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
         put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
         put(uo[u].blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
-        put(uo[u].pair, hb.pair64.data(), hb.pair64.size() * 8);
+        write_pair64(hb, (uint64_t*)(mirror + uo[u].pair));
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
     }
     std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
@@ -330,7 +384,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     put(o_row0, row0.data(), row0.size() * 8);
     put(o_first, first.data(), first.size() * 8);
     put(o_last, last.data(), last.size() * 8);
-    e = hipMemcpyAsync(h->arena, mirror.data(), bytes, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(h->arena, mirror, host_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index tables)");
 
     // ---- partner lists on the device: count, scan, read the lengths back
@@ -357,9 +411,10 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     int64_t* scan_tmp = (int64_t*)D(o_scan);
     for (size_t u = 0; u < ub.size(); u++)
         for (int sidx = 0; sidx < 2; sidx++) {
+            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
             PartnerArgs a = args(u, sidx);
             if ((e = launch_partner_count(a, s)) != hipSuccess) return hip_fail(e, "partner count");
-            // l*_ptr[0] is 0 from the mirror; the inclusive scan gives offsets
+            // the count pass leaves l*_ptr[0] = 0; the inclusive scan gives offsets
             if ((e = launch_inclusive_scan(a.l1_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess ||
                 (e = launch_inclusive_scan(a.l12_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess)
                 return hip_fail(e, "partner scan");
@@ -375,21 +430,31 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(partner count)");
+    for (int i = 0; i < nsp; i++) {
+        const int c = canon[i];
+        totals[2 * i] = totals[2 * c];
+        totals[2 * i + 1] = totals[2 * c + 1];
+    }
 
     // ---- allocation 2: the partner lists; fill them
     Layout LL;
     std::vector<size_t> lo1(2 * ub.size()), lo12(2 * ub.size());
-    for (size_t u = 0; u < ub.size(); u++)
-        for (int sidx = 0; sidx < 2; sidx++) {
-            lo1[2 * u + sidx] = LL.take<uint64_t>(std::max<int64_t>(totals[4 * u + 2 * sidx], 1));
-            lo12[2 * u + sidx] = LL.take<uint64_t>(std::max<int64_t>(totals[4 * u + 2 * sidx + 1], 1));
+    for (int i = 0; i < nsp; i++) {
+        if (canon[i] != i) {
+            lo1[i] = lo1[canon[i]];
+            lo12[i] = lo12[canon[i]];
+            continue;
         }
+        lo1[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i], 1));
+        lo12[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i + 1], 1));
+    }
     e = hipMalloc(&h->lists, LL.bytes());
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(partner lists)");
     h->list_bytes = LL.bytes();
     char* ldev = (char*)h->lists;
     for (size_t u = 0; u < ub.size(); u++)
         for (int sidx = 0; sidx < 2; sidx++) {
+            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
             PartnerArgs a = args(u, sidx);
             a.l1 = (uint64_t*)(ldev + lo1[2 * u + sidx]);
             a.l12 = (uint64_t*)(ldev + lo12[2 * u + sidx]);
@@ -624,6 +689,18 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                        grad_tbme, (double*)work, b->n_tbme, b->tune, b->d_queue, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "autotune final run");
+    return CI_OK;
+}
+
+int ci_probe_ceilings(void* buf, size_t bytes, double* store_gbs, double* diff_steps_per_s, ci_stream stream)
+{
+    if (!buf || !store_gbs || !diff_steps_per_s) return fail(CI_EINVAL, "null pointer");
+    if (bytes < ((size_t)64 << 20)) return fail(CI_ESPACE, "the probe buffer needs at least 64 MiB");
+    double bps = 0.0, steps = 0.0;
+    hipError_t e = run_probes(buf, bytes, (hipStream_t)stream, &bps, &steps);
+    if (e != hipSuccess) return hip_fail(e, "probe");
+    *store_gbs = bps / 1e9;
+    *diff_steps_per_s = steps;
     return CI_OK;
 }
 

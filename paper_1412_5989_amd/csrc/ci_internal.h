@@ -101,8 +101,7 @@ struct HostBasis {
     int64_t dim = 0;
     std::vector<int64_t> sec_off;
     std::vector<int32_t> sec_n;
-    std::vector<uint32_t> pair;    // 3 * n * n
-    std::vector<uint64_t> pair64;  // 3 * n * n, device form
+    std::vector<uint32_t> pair;    // 3 * n * n: sector << 16 | position, or kNoPair
     int64_t n_tbme = 0;
     int nblk() const { return (int)blk_kp.size(); }
 };
@@ -132,5 +131,7 @@ int validate_problem(const ci_problem& p, std::string& err);
 int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err);
 // Two-body keys (a, b, c, d) in table order.
 void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd);
+// Device form of the pair index ([3][n][n] uint64: base of the pair row << 32 | sector << 16 | position).
+void write_pair64(const HostBasis& hb, uint64_t* out);
 
 }  // namespace ci

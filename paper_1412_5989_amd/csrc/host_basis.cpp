@@ -45,39 +45,34 @@ using Bits = std::array<uint64_t, kMaxWords>;
 
 inline void flip_bit(Bits& b, int k) { b[k >> 6] ^= 1ull << (k & 63); }
 
-struct RawSD {
-    Bits bits;
-    int nq, m2;
-};
-
-// All X-orbit determinants with Nq <= budget, in colex order (as unsigned
-// W-word integers, word W-1 most significant): the highest orbit is chosen
-// first, in ascending order, and the rest recursively below it.  low[j] is
-// the fewest quanta j nucleons can have.
-void colex_choose(const HostBasis& hb, int left, int limit, int nq, int m2, int budget, const int* low,
-                  RawSD& cur, std::vector<RawSD>& out)
+// Visits every X-orbit determinant with Nq <= budget in colex order (as
+// unsigned W-word integers, word W-1 most significant): the highest orbit is
+// chosen first, in ascending order, and the rest recursively below it.  low[j]
+// is the fewest quanta j nucleons can have.  visit(bits, nq, 2M).
+template <class F>
+void colex_visit(const HostBasis& hb, int left, int limit, int nq, int m2, int budget, const int* low, Bits& cur,
+                 F& visit)
 {
     if (left == 0) {
-        cur.nq = nq;
-        cur.m2 = m2;
-        out.push_back(cur);
+        visit(cur, nq, m2);
         return;
     }
     for (int k = left - 1; k < limit; k++) {
         // orbits ascend in N: a larger top orbit never costs less
         if (nq + hb.orb_n[k] + low[left - 1] > budget) break;
-        flip_bit(cur.bits, k);
-        colex_choose(hb, left - 1, k, nq + hb.orb_n[k], m2 + hb.orb_m2[k], budget, low, cur, out);
-        flip_bit(cur.bits, k);
+        flip_bit(cur, k);
+        colex_visit(hb, left - 1, k, nq + hb.orb_n[k], m2 + hb.orb_m2[k], budget, low, cur, visit);
+        flip_bit(cur, k);
     }
 }
 
-void enumerate_species(const HostBasis& hb, int X, int budget, std::vector<RawSD>& out)
+template <class F>
+void visit_species(const HostBasis& hb, int X, int budget, F& visit)
 {
     std::vector<int> low(X + 1);
     for (int j = 0; j <= X; j++) low[j] = lowest_quanta(j);
-    RawSD cur{};
-    colex_choose(hb, X, hb.nsps, 0, 0, budget, low.data(), cur, out);
+    Bits cur{};
+    colex_visit(hb, X, hb.nsps, 0, 0, budget, low.data(), cur, visit);
 }
 
 bool block_ok(const HostBasis& hb, int nqp, int m2p, int nqn, int m2n)
@@ -116,26 +111,31 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
     hb.N0 = hb.N0p + hb.N0n;
     const int top = hb.N0 + p.nmax;
 
-    std::vector<RawSD> raw[2];
-    const int X[2] = {p.Z, p.N};
-    const int other0[2] = {hb.N0n, hb.N0p};
-    for (int s = 0; s < 2; s++) {
-        hb.sp[s] = HostSpecies();
-        hb.sp[s].X = X[s];
-        hb.sp[s].budget = top - other0[s];
-        enumerate_species(hb, X[s], hb.sp[s].budget, raw[s]);
-    }
-    // keys (Nq, 2M) of each species on a dense grid; keep those in a block
+    // keys (Nq, 2M) of each species on a dense grid
     int maxm = 0;
     for (int m : hb.orb_m2) maxm = std::max(maxm, m);
     const int mtot = std::max(1, std::max(p.Z, p.N)) * maxm;  // |2M| bound of one species
     const int nqs = top + 1, nms = 2 * mtot + 1;
     auto cell = [&](int nq, int m2) { return nq * nms + (m2 + mtot); };
+    const int X[2] = {p.Z, p.N};
+    const int other0[2] = {hb.N0n, hb.N0p};
+    // protons and neutrons of an N = Z problem have the same determinants
+    const bool twin = p.Z == p.N;
     std::vector<int32_t> present[2];
     for (int s = 0; s < 2; s++) {
+        hb.sp[s] = HostSpecies();
+        hb.sp[s].X = X[s];
+        hb.sp[s].budget = top - other0[s];
+        if (s == 1 && twin) {
+            present[1] = present[0];
+            continue;
+        }
         present[s].assign((size_t)nqs * nms, 0);
-        for (const RawSD& r : raw[s]) present[s][cell(r.nq, r.m2)]++;
+        std::vector<int32_t>& pr = present[s];
+        auto count = [&](const Bits&, int nq, int m2) { pr[cell(nq, m2)]++; };
+        visit_species(hb, X[s], hb.sp[s].budget, count);
     }
+    // keep the keys that take part in a block
     std::vector<char> use[2];
     use[0].assign((size_t)nqs * nms, 0);
     use[1].assign((size_t)nqs * nms, 0);
@@ -150,6 +150,13 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
         }
     for (int s = 0; s < 2; s++) {
         HostSpecies& sp = hb.sp[s];
+        if (s == 1 && twin) {
+            const int budget = sp.budget;
+            sp = hb.sp[0];
+            sp.X = X[1];
+            sp.budget = budget;
+            continue;
+        }
         // key ids in (Nq, 2M) order
         std::vector<int32_t> kid((size_t)nqs * nms, -1);
         for (int q = 0; q < nqs; q++)
@@ -163,22 +170,22 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
         sp.key_off.assign(nk + 1, 0);
         for (int k = 0; k < nk; k++)
             sp.key_off[k + 1] = sp.key_off[k] + present[s][cell(sp.key_nq[k], sp.key_m2[k])];
-        std::vector<int64_t> order(sp.key_off[nk]);
-        std::vector<int32_t> fillp(sp.key_off.begin(), sp.key_off.end() - 1);
-        for (size_t r = 0; r < raw[s].size(); r++) {
-            const int k = kid[cell(raw[s][r].nq, raw[s][r].m2)];
-            if (k >= 0) order[fillp[k]++] = (int64_t)r;
-        }
         const int W = hb.W;
-        sp.sd.assign((size_t)sp.key_off[nk] * W, 0);
-        sp.sd_key.assign(sp.key_off[nk], 0);
-        // the enumeration is in colex order, so each key's bucket already is
-        for (int k = 0; k < nk; k++) {
-            for (int64_t g = sp.key_off[k]; g < sp.key_off[k + 1]; g++) {
-                std::memcpy(&sp.sd[g * W], raw[s][order[g]].bits.data(), W * sizeof(uint64_t));
-                sp.sd_key[g] = k;
-            }
-        }
+        sp.sd.resize((size_t)sp.key_off[nk] * W);
+        sp.sd_key.resize(sp.key_off[nk]);
+        // second visit: each determinant goes to the next slot of its key, so
+        // every key's run is in colex order
+        std::vector<int32_t> fillp(sp.key_off.begin(), sp.key_off.end() - 1);
+        uint64_t* sdp = sp.sd.data();
+        int32_t* skp = sp.sd_key.data();
+        auto place = [&](const Bits& bits, int nq, int m2) {
+            const int k = kid[cell(nq, m2)];
+            if (k < 0) return;
+            const int32_t g = fillp[k]++;
+            for (int w = 0; w < W; w++) sdp[(size_t)g * W + w] = bits[w];
+            skp[g] = k;
+        };
+        visit_species(hb, X[s], sp.budget, place);
     }
     // blocks in (proton key, neutron key) order
     hb.blk_kp.clear(); hb.blk_kn.clear();
@@ -253,15 +260,6 @@ int make_tbme_index(HostBasis& hb, std::string& err)
         err = "two-body table of " + std::to_string(total) + " entries does not fit int32 indices";
         return CI_EUNSUPPORTED;
     }
-    // device form: the entry also carries the row base of the pair
-    hb.pair64.assign(hb.pair.size(), kNoPair64);
-    for (size_t t = 0; t < hb.pair.size(); t++) {
-        const uint32_t e = hb.pair[t];
-        if (e == kNoPair) continue;
-        const int64_t sec = e >> 16, r = e & 0xffff, ns = hb.sec_n[sec];
-        const int64_t base = hb.sec_off[sec] + r * (2 * ns - r + 1) / 2 - r;
-        hb.pair64[t] = ((uint64_t)(uint32_t)base << 32) | e;
-    }
     return CI_OK;
 }
 
@@ -305,6 +303,22 @@ int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
     rc = make_tbme_index(hb, err);
     if (rc != CI_OK) return rc;
     return CI_OK;
+}
+
+void write_pair64(const HostBasis& hb, uint64_t* out)
+{
+    // device form: the entry also carries the row base of the pair
+    const size_t n = hb.pair.size();
+    for (size_t t = 0; t < n; t++) {
+        const uint32_t e = hb.pair[t];
+        if (e == kNoPair) {
+            out[t] = kNoPair64;
+            continue;
+        }
+        const int64_t sec = e >> 16, r = e & 0xffff, ns = hb.sec_n[sec];
+        const int64_t base = hb.sec_off[sec] + r * (2 * ns - r + 1) / 2 - r;
+        out[t] = ((uint64_t)(uint32_t)base << 32) | e;
+    }
 }
 
 void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd)

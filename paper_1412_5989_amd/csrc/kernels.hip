@@ -168,34 +168,51 @@ __device__ __forceinline__ int tb_pos_any(const BasisDev& B, int cls, int a, int
 __device__ __forceinline__ bool rec_neg(uint64_t r) { return (r >> 56) & 1; }
 
 // Per-wavefront LDS.
+// Per-wavefront LDS: the queue of multi-term entries and the row's occupied
+// orbits.  The per-block and per-segment values of the walk stay in registers
+// (lane t holds block / segment t) and are read across lanes with ds_bpermute.
 struct WaveLds {
-    int32_t bstart[65];  // first segment of each target block of the window
-    int32_t eoff[65];    // first entry of each segment of the chunk
-    // per target block of the window
-    int32_t bp[64];    // first proton partner in the block: index into l12 (bit 31 set) or l1
-    int32_t bcol[64];  // first row of the block
-    int32_t bstr[64];  // rows per proton determinant (|Kn'|)
-    int32_t bn1[64], bl1[64];    // the row's neutron d<=1 partners in Kn': first, count
-    int32_t bn12[64], bl12[64];  // the row's neutron d<=2 partners in Kn' (N' >= N in the row's block)
-    // per segment (target block, proton partner) of the chunk
-    uint64_t spr[64];  // proton partner record
-    int32_t soff[64];  // first neutron partner: index into l12 (bit 31 set) or l1
-    int32_t scol[64];  // column of neutron local index 0
-    // queued multi-term entries
     int32_t qpos[kQueue];  // offset from the row's first entry
-    uint64_t qpr[kQueue];  // proton record (the self record when no proton moved)
-    uint64_t qnr[kQueue];  // neutron record
+    uint32_t qrec[kQueue]; // kind (0 diagonal, 1 one proton moved, 2 one neutron moved) | h << 8 | p << 16 | neg << 24
     int32_t toff[kQueue + 1];
     uint8_t occ[128];  // occupied orbits of the row: protons, then neutrons
 };
+
+__device__ __forceinline__ int q_kind(uint32_t q) { return (int)(q & 3); }
+__device__ __forceinline__ int q_h(uint32_t q) { return (int)((q >> 8) & 255); }
+__device__ __forceinline__ int q_p(uint32_t q) { return (int)((q >> 16) & 255); }
+__device__ __forceinline__ bool q_neg(uint32_t q) { return (q >> 24) & 1; }
+
+// value v of lane l (every lane of the wavefront must be active)
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_ds_bpermute(l << 2, v); }
+__device__ __forceinline__ uint64_t lane_read64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)lane_read((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)lane_read((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// largest t in [0, 64) with start(t) <= x, where lane t holds start(t),
+// non-decreasing in t, and start(0) <= x (every lane active)
+__device__ __forceinline__ int lane_search64(int start, int x)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (lane_read(start, lo + step) <= x) lo += step;
+    return lo;
+}
 
 struct RowView {
     const BasisDev* B;
     const float* tbme;  // this basis' table (fill)
     double* gacc;       // this basis' accumulators (adjoint)
     int64_t tbme0;      // this basis' first table position in the batch
-    lptr<uint32_t> hkey;  // LDS accumulator table of the workgroup (adjoint), or null
+    // LDS accumulator table of the workgroup (adjoint); used only when
+    // use_table is set (an LDS address can be 0, so no null test on it)
+    lptr<uint32_t> hkey;
     lptr<float> hval;
+    bool use_table;
     const float* gval;  // upstream values (adjoint)
     int32_t* col;
     float* val;
@@ -208,7 +225,7 @@ struct RowView {
 // Adjoint contribution g to table position k of the row's basis.
 __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
 {
-    if (R.hkey) {
+    if (R.use_table) {
         const uint32_t gk = (uint32_t)(R.tbme0 + k);
         uint32_t s = (gk * 2654435761u) >> (32 - kAdjSlotBits);
         for (int t = 0; t < kAdjProbes; t++) {
@@ -227,15 +244,14 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
 }
 
 // number of two-body terms of a queued entry
-__device__ __forceinline__ int queued_terms(const RowView& R, uint64_t pr, uint64_t nr)
+__device__ __forceinline__ int queued_terms(const RowView& R, uint32_t q)
 {
     const int A = R.Z + R.NN;
-    return (rec_d(pr) == 0 && rec_d(nr) == 0) ? A * (A - 1) / 2 : A - 1;
+    return q_kind(q) == 0 ? A * (A - 1) / 2 : A - 1;
 }
 
 // The u-th two-body term of a queued entry: table position and sign.
-__device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, uint64_t pr, uint64_t nr, int u,
-                                           bool* neg)
+__device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, uint32_t q, int u, bool* neg)
 {
     const BasisDev& B = *R.B;
     const int Z = R.Z, NN = R.NN;
@@ -243,8 +259,8 @@ __device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, u
     const uint8_t* oN = L.occ + Z;
     bool s;
     int k;
-    if (rec_d(pr) == 1) {  // one proton moved: p (row) -> h (column)
-        const int h = rec_h1(pr), p = rec_p1(pr);
+    if (q_kind(q) == 1) {  // one proton moved: p (row) -> h (column)
+        const int h = q_h(q), p = q_p(q);
         if (u < Z - 1) {  // the u-th proton spectator (the row's protons without p)
             const int kk = (oP[u] >= p) ? oP[u + 1] : oP[u];
             k = tb_pos_any(B, 0, p, kk, h, kk, &s);
@@ -252,11 +268,11 @@ __device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, u
             const int b = oN[u - (Z - 1)];
             k = tb_pos_any(B, 1, p, b, h, b, &s);
         }
-        *neg = s ^ rec_neg(pr);
+        *neg = s ^ q_neg(q);
         return k;
     }
-    if (rec_d(nr) == 1) {  // one neutron moved
-        const int h = rec_h1(nr), p = rec_p1(nr);
+    if (q_kind(q) == 2) {  // one neutron moved
+        const int h = q_h(q), p = q_p(q);
         if (u < NN - 1) {
             const int kk = (oN[u] >= p) ? oN[u + 1] : oN[u];
             k = tb_pos_any(B, 2, p, kk, h, kk, &s);
@@ -264,7 +280,7 @@ __device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, u
             const int a = oP[u - (NN - 1)];
             k = tb_pos_any(B, 1, a, p, a, h, &s);
         }
-        *neg = s ^ rec_neg(nr);
+        *neg = s ^ q_neg(q);
         return k;
     }
     // diagonal: every occupied pair, pp then nn then pn (all ordered)
@@ -302,7 +318,7 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
     int tot = 0;
     for (int base = 0; base < qn; base += 64) {
         const int q = base + lane;
-        const int t = q < qn ? queued_terms(R, L.qpr[q], L.qnr[q]) : 0;
+        const int t = q < qn ? queued_terms(R, L.qrec[q]) : 0;
         const int incl = wave_incl_scan(t);
         if (q < kQueue) L.toff[q + 1] = tot + incl;
         if (lane == 0 && base == 0) L.toff[0] = 0;
@@ -319,7 +335,7 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
         if (act) {
             q = seg_search(L.toff, qn, t);
             bool neg;
-            const int k = queued_term(R, L, L.qpr[q], L.qnr[q], t - L.toff[q], &neg);
+            const int k = queued_term(R, L, L.qrec[q], t - L.toff[q], &neg);
             if (k >= 0) {
                 if (MODE == kFill) {
                     const double x = (double)glb(R.tbme)[k];
@@ -347,7 +363,7 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
                 // the entry's last term: write it
                 const int64_t p = R.pos0 + L.qpos[q];
                 double x = v;
-                if (rec_d(L.qpr[q]) == 0 && rec_d(L.qnr[q]) == 0) x += R.spe_sum;
+                if (q_kind(L.qrec[q]) == 0) x += R.spe_sum;
                 if (p < R.cap) glbw(R.val)[p] = (float)x;
             }
             // an entry cut by the end of the round continues in the next one
@@ -409,57 +425,56 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
     for (int w0 = bi; w0 < B.nblk; w0 += 64) {
-        // 1. per target block of the window: proton partners of P, neutron
-        //    partners of N, column base
+        // 1. lane t: target block w0 + t of the window: proton partners of P,
+        //    the row's neutron partners, column base
         const int b2 = w0 + lane;
-        int np = 0;
+        int np = 0, bp = 0, bcol = 0, bstr = 0, bn1 = 0, bl1 = 0, bn12 = 0, bl12 = 0;
         if (b2 < B.nblk) {
             const int kp2 = blk_kp[b2], kn2 = blk_kn[b2];
             const bool same_n = (kn2 == kn);
             const int ps = same_n ? sP12[kp2] : sP1[kp2];
             np = (same_n ? sP12[kp2 + 1] : sP1[kp2 + 1]) - ps;
-            L.bp[lane] = ps | (same_n ? (int)0x80000000 : 0);
-            L.bcol[lane] = (int)blk_off[b2];
-            L.bstr[lane] = nkoff[kn2 + 1] - nkoff[kn2];
-            const int s1 = sN1[kn2], s12 = sN12[kn2] + (b2 == bi ? self12 : 0);  // diagonal block: N' >= N
-            const int l1 = sN1[kn2 + 1] - s1, l12 = sN12[kn2 + 1] - s12;
-            L.bn1[lane] = s1;
-            L.bl1[lane] = l1;
-            L.bn12[lane] = s12;
-            L.bl12[lane] = l12;
+            bp = ps | (same_n ? (int)0x80000000 : 0);
+            bcol = (int)blk_off[b2];
+            bstr = nkoff[kn2 + 1] - nkoff[kn2];
+            bn1 = sN1[kn2];
+            bl1 = sN1[kn2 + 1] - bn1;
+            bn12 = sN12[kn2] + (b2 == bi ? self12 : 0);  // diagonal block: N' >= N
+            bl12 = sN12[kn2 + 1] - bn12;
             // a block with another neutron key needs a neutron partner of N in it
             // (d <= 1 for a moved proton, d <= 2 for P' = P): otherwise every
             // segment of the block is empty
-            if (!same_n && l1 == 0 && (kp2 != kp || l12 == 0)) np = 0;
+            if (!same_n && bl1 == 0 && (kp2 != kp || bl12 == 0)) np = 0;
         }
         const int bincl = wave_incl_scan(np);
-        L.bstart[lane + 1] = bincl;
-        if (lane == 0) L.bstart[0] = 0;
+        const int bstart = bincl - np;  // first segment of the lane's block
         const int S = lane63(bincl);
-        wave_sync();
         for (int s0 = 0; s0 < S; s0 += 64) {
-            // 2. entries of each segment (target block, P')
+            // 2. lane j: segment s0 + j = (target block, P'): its entry count
             const int s = s0 + lane;
+            const int t = lane_search64(bstart, s < S ? s : S - 1);
+            const int t_bp = lane_read(bp, t), t_start = lane_read(bstart, t);
+            const int t_col = lane_read(bcol, t), t_str = lane_read(bstr, t);
+            const int t_n1 = lane_read(bn1, t), t_l1 = lane_read(bl1, t);
+            const int t_n12 = lane_read(bn12, t), t_l12 = lane_read(bl12, t);
             int len = 0;
             uint64_t pr = 0;
             int so = 0, sc = 0;
             if (s < S) {
-                const int t = seg_search64(L.bstart, s);
-                const int bp = L.bp[t];
-                const int q = (bp & 0x7fffffff) + s - L.bstart[t];
-                pr = bp < 0 ? P12[q] : P1[q];
+                const int q = (t_bp & 0x7fffffff) + s - t_start;
+                pr = t_bp < 0 ? P12[q] : P1[q];
                 const int dp = rec_d(pr), ipp = rec_local(pr);
-                sc = L.bcol[t] + ipp * L.bstr[t];
+                sc = t_col + ipp * t_str;
                 if (w0 + t == bi && ipp < ip) {
                     len = 0;  // lower triangle
                 } else if (dp == 2) {
                     len = 1;  // two protons moved: N' = N
                 } else if (dp == 1) {
-                    so = L.bn1[t];
-                    len = L.bl1[t];
+                    so = t_n1;
+                    len = t_l1;
                 } else {
-                    so = L.bn12[t] | (int)0x80000000;
-                    len = L.bl12[t];
+                    so = t_n12 | (int)0x80000000;
+                    len = t_l12;
                 }
             }
             const int eincl = wave_incl_scan(len);
@@ -468,24 +483,19 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                 pos += T;
                 continue;
             }
-            L.eoff[lane + 1] = eincl;
-            if (lane == 0) L.eoff[0] = 0;
-            L.spr[lane] = pr;
-            L.soff[lane] = so;
-            L.scol[lane] = sc;
-            wave_sync();
+            const int estart = eincl - len;  // first entry of the lane's segment
             // 3. the entries of the chunk, 64 consecutive ones per round
             for (int e0 = 0; e0 < T; e0 += 64) {
                 const int e = e0 + lane;
+                const int j = lane_search64(estart, e < T ? e : T - 1);
+                const uint64_t prj = lane_read64(pr, j);
+                const int so2 = lane_read(so, j), sc2 = lane_read(sc, j), k = e - lane_read(estart, j);
                 bool special = false;
-                uint64_t prj = 0, nr = 0;
+                uint32_t qr = 0;
                 if (e < T) {
-                    const int j = seg_search64(L.eoff, e);
-                    const int k = e - L.eoff[j];
-                    prj = L.spr[j];
                     const int dp = rec_d(prj);
+                    uint64_t nr = 0;
                     if (dp != 2) {
-                        const int so2 = L.soff[j];
                         const int idx = (so2 & 0x7fffffff) + k;
                         nr = so2 < 0 ? N12[idx] : N1[idx];
                     }
@@ -504,7 +514,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                     const int key = special ? -1 : tb_pos(B, cls, a, b, c, d);
                     if (p < R.cap) {
                         if (MODE == kFill) {
-                            glbw(R.col)[p] = L.scol[j] + (dp == 2 ? in : rec_local(nr));
+                            glbw(R.col)[p] = sc2 + (dp == 2 ? in : rec_local(nr));
                             if (!special) {
                                 const float x = key >= 0 ? glb(R.tbme)[key] : 0.0f;
                                 glbw(R.val)[p] = neg ? -x : x;
@@ -513,6 +523,13 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                             adj_add(R, key, neg ? -gv : gv);
                         }
                     }
+                    if (special) {
+                        // queued: the moved nucleon's orbits and phase, or the diagonal
+                        const uint64_t mr = dp == 1 ? prj : nr;
+                        const uint32_t kind = dp == 1 ? 1u : (dn == 1 ? 2u : 0u);
+                        qr = kind | ((uint32_t)rec_h1(mr) << 8) | ((uint32_t)rec_p1(mr) << 16) |
+                             ((uint32_t)rec_neg(mr) << 24);
+                    }
                 }
                 const uint64_t m = __ballot(special);
                 if (m) {
@@ -520,8 +537,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
                     if (special) {
                         L.qpos[qn + rank] = (int32_t)(pos + e);
-                        L.qpr[qn + rank] = prj;
-                        L.qnr[qn + rank] = nr;
+                        L.qrec[qn + rank] = qr;
                     }
                     qn += __popcll(m);
                     wave_sync();
@@ -532,7 +548,6 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                 }
             }
             pos += T;
-            wave_sync();
         }
     }
     if (MODE != kCount) flush_queue<MODE>(R, L, qn);
@@ -547,7 +562,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
                                         const float* __restrict__ tbme, int64_t* __restrict__ row_ptr,
                                         int64_t nrp, int32_t* __restrict__ col, float* __restrict__ val,
                                         const float* __restrict__ gval, double* __restrict__ gacc,
-                                        lptr<uint32_t> hkey, lptr<float> hval, WaveLds& L)
+                                        lptr<uint32_t> hkey, lptr<float> hval, bool use_table, WaveLds& L)
 {
     // basis of the row (few bases: linear search)
     int b = 0;
@@ -571,6 +586,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
     R.tbme0 = B.tbme0;
     R.hkey = hkey;
     R.hval = hval;
+    R.use_table = use_table;
     R.gval = gval;
     R.col = col;
     R.val = val;
@@ -605,7 +621,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t grow = (int64_t)blockIdx.x * WAVES + wid;
         if (grow < nrows)
             run_row<MODE>(bases, nb, basis_row0, grow, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, lds[wid]);
+                          nullptr, false, lds[wid]);
         return;
     }
     for (;;) {
@@ -618,7 +634,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t g1 = g0 + grab < nrows ? g0 + grab : nrows;
         for (int64_t g = g0; g < g1; g++)
             run_row<MODE>(bases, nb, basis_row0, g, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, lds[wid]);
+                          nullptr, false, lds[wid]);
     }
 }
 
@@ -645,7 +661,6 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
         hval[s] = 0.0f;
     }
     const int wid = uniform(threadIdx.x >> 6);
-    const lptr<uint32_t> hk = use_table ? (lptr<uint32_t>)hkey : nullptr;
     for (;;) {
         if (threadIdx.x == 0) {
             next_row = 0;
@@ -663,7 +678,8 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
             t = uniform(t);
             if (t >= rows_per_group || first + t >= nrows) break;
             run_row<kAdjoint>(bases, nb, basis_row0, first + t, nullptr, const_cast<int64_t*>(row_ptr), nrp,
-                              nullptr, nullptr, gval, gacc, hk, (lptr<float>)hval, lds[wid]);
+                              nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval, use_table != 0,
+                              lds[wid]);
         }
         __syncthreads();
         if (use_table) {

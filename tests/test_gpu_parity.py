@@ -438,3 +438,11 @@ def test_batched_64_bases_sampled_rows(ci):
             i = b.info[k]
             gref = o.grad_rows(rows, Gs.astype(np.float64))
             assert rel_err(g[i["tbme_offset"]: i["tbme_offset"] + i["n_tbme"]], gref) <= GRAD_TOL, probs[k]
+
+
+def test_probe_ceilings(ci):
+    # the measured ceilings are in the range the device's published figures allow
+    c = ci.ci_probe_ceilings(256)
+    say("ceilings", c)
+    assert 500.0 < c["store_GBps"] < 8000.0 * 1.05
+    assert 1e11 < c["xor_popcount_steps_per_s"] < 1e14

@@ -84,3 +84,21 @@ def test_tbme_keys_capacity():
     buf = np.zeros((10, 4), np.int32)
     rc = L.ci_tbme_keys(arr, buf.ctypes.data_as(ci.ctypes.c_void_p), 10)
     assert rc == ci.CI_ESPACE
+
+
+def test_argument_errors_before_any_device_call():
+    # null handles and short buffers are refused on the host
+    L = ci.load_library()
+    c = ci.ctypes
+    d = c.c_double()
+    assert L.ci_probe_ceilings(None, 1 << 30, c.byref(d), c.byref(d), None) == ci.CI_EINVAL
+    # a non-null placeholder address is never dereferenced: the size check comes first
+    assert L.ci_probe_ceilings(c.c_void_p(256), 1 << 20, c.byref(d), c.byref(d), None) == ci.CI_ESPACE
+    t = ci.ci_tuning()
+    assert L.ci_basis_get_tuning(None, c.byref(t)) == ci.CI_EINVAL
+    assert L.ci_basis_set_tuning(None, c.byref(t)) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_tune(None, None, None, None, None, None, None, None, 0, 1, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_fill(None, None, None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_vjp(None, None, None, None, None, 0, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_count(None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_vjp_work_bytes(None) == 0 and L.ci_basis_count(None) == 0
