@@ -186,9 +186,9 @@ def main():
     ap.add_argument("--workload", default="li6_nmax6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--tuning", default=None, metavar="W,G,R,P",
-                    help="fixed launch shapes row_waves,row_grab,adj_rows,adj_persistent instead of the "
-                         "autotuner (for profiling runs)")
+    ap.add_argument("--tuning", default=None, metavar="W,G,R,N,P",
+                    help="fixed launch shapes row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent instead "
+                         "of the autotuner (for profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device to device three times (a plain "
                          "copy of known size, to scale hardware byte counters under rocprofv3)")
@@ -228,7 +228,7 @@ def main():
     fixed = None
     t0 = time.perf_counter()
     if args.tuning:
-        fixed = dict(zip(("row_waves", "row_grab", "adj_rows", "adj_persistent"),
+        fixed = dict(zip(("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent"),
                          (int(x) for x in args.tuning.split(","))))
         b.tuning = fixed
         tuning = b.tuning

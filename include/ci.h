@@ -105,13 +105,16 @@ typedef struct ci_basis ci_basis; /* opaque */
  * row once (row_grab = 0), or a persistent grid (as many workgroups as the
  * device holds at once) whose wavefronts take row_grab consecutive rows at a
  * time from a work counter until none are left.  The adjoint gives each
- * workgroup groups of adj_rows consecutive rows whose contributions are summed
- * in one shared-memory table before they reach the FP64 accumulators. */
+ * workgroup a tile of rows of one block -- tn = min(adj_tile_n, |Kn|) neutron
+ * determinants times tp = max(1, adj_rows / tn) proton determinants -- whose
+ * contributions are summed in one shared-memory table before they reach the
+ * FP64 accumulators. */
 typedef struct {
     int32_t row_waves;      /* wavefronts per workgroup of count and fill: 4 or 8 */
     int32_t row_grab;       /* 0: one grid over all rows; 1..4096: persistent, rows per grab */
-    int32_t adj_rows;       /* adjoint rows per group: 1..4096 */
-    int32_t adj_persistent; /* adjoint: 0 one workgroup per group, 1 persistent workgroups */
+    int32_t adj_rows;       /* adjoint: target rows per tile, 1..4096 */
+    int32_t adj_tile_n;     /* adjoint: neutron determinants per tile, 1..4096 */
+    int32_t adj_persistent; /* adjoint: 0 one workgroup per tile, 1 persistent workgroups */
 } ci_tuning;
 
 /* Thread-local text of the last error. */

@@ -58,7 +58,7 @@ class ci_basis_info(ctypes.Structure):
 
 class ci_tuning(ctypes.Structure):
     _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
-                ("adj_persistent", ctypes.c_int32)]
+                ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

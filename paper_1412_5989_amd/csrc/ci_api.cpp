@@ -22,9 +22,10 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
                        const ci_tuning& t, unsigned long long* queue, hipStream_t s);
-hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
-                      const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
-                      int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
+                      int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
+                      const float* gval, float* gtbme, double* gacc, int64_t ntbme, const ci_tuning& t,
+                      unsigned long long* queue, hipStream_t s);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
@@ -62,6 +63,10 @@ struct ci_basis {
     int64_t* d_scan_tmp = nullptr;
     int64_t* d_nnz = nullptr;
     unsigned long long* d_queue = nullptr;  // work counter of the persistent launches
+    int32_t* d_blk_basis = nullptr;         // global block list of the batch: problem, local block
+    int32_t* d_blk_local = nullptr;
+    int64_t* d_tile_off = nullptr;          // adjoint tiles per block (inclusive scan), [nblocks + 1]
+    int nblocks = 0;
     ci_tuning tune{};
     std::vector<ci_problem> probs;          // key of the process-wide tuning cache
     int64_t n_rowptr = 0;
@@ -167,7 +172,7 @@ std::vector<std::tuple<int, int, int, int, int, double>> tune_key(const std::vec
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 0}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
@@ -295,6 +300,10 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     const size_t o_row0 = L.take<int64_t>(n_probs + 1);
     const size_t o_first = L.take<int64_t>(n_probs);
     const size_t o_last = L.take<int64_t>(n_probs);
+    int nblocks = 0;
+    for (int32_t b = 0; b < n_probs; b++) nblocks += ub[which[b]]->nblk();
+    const size_t o_blk_basis = L.take<int32_t>(std::max(nblocks, 1));
+    const size_t o_blk_local = L.take<int32_t>(std::max(nblocks, 1));
     const size_t host_bytes = L.off;
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
@@ -329,6 +338,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
     const size_t o_nnz = L.take<int64_t>(n_probs);
     const size_t o_queue = L.take<unsigned long long>(1);
+    const size_t o_tile_off = L.take<int64_t>(nblocks + 1);
     const size_t bytes = L.bytes();
 
     hipError_t e = hipGetDevice(&h->device);
@@ -380,6 +390,16 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         last[b] = R + hb.dim;
         row0[b + 1] = row0[b] + hb.dim;
         R += hb.dim + 1;
+    }
+    {
+        int32_t* bb = (int32_t*)(mirror + o_blk_basis);
+        int32_t* bl = (int32_t*)(mirror + o_blk_local);
+        int gb = 0;
+        for (int32_t b = 0; b < n_probs; b++)
+            for (int k = 0; k < ub[which[b]]->nblk(); k++, gb++) {
+                bb[gb] = b;
+                bl[gb] = k;
+            }
     }
     put(o_row0, row0.data(), row0.size() * 8);
     put(o_first, first.data(), first.size() * 8);
@@ -523,6 +543,10 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     h->d_scan_tmp = scan_tmp;
     h->d_nnz = (int64_t*)D(o_nnz);
     h->d_queue = (unsigned long long*)D(o_queue);
+    h->d_blk_basis = (int32_t*)D(o_blk_basis);
+    h->d_blk_local = (int32_t*)D(o_blk_local);
+    h->d_tile_off = (int64_t*)D(o_tile_off);
+    h->nblocks = nblocks;
     h->probs.assign(probs, probs + n_probs);
     h->tune = cached_tuning(h->probs);
     h->nrows = row0[n_probs];
@@ -574,6 +598,33 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
     return CI_OK;
 }
 
+// Number of adjoint tiles of the handle for shape t (the device computes the
+// same counts in tile_offsets).
+static int64_t count_tiles(const ci_basis* b, const ci_tuning& t)
+{
+    int64_t n = 0;
+    for (size_t p = 0; p < b->host.size(); p++) {
+        const HostBasis& hb = *b->host[p];
+        for (int bi = 0; bi < hb.nblk(); bi++) {
+            const HostSpecies &P = hb.sp[0], &N = hb.sp[1];
+            const int64_t nKp = P.key_off[hb.blk_kp[bi] + 1] - P.key_off[hb.blk_kp[bi]];
+            const int64_t nKn = N.key_off[hb.blk_kn[bi] + 1] - N.key_off[hb.blk_kn[bi]];
+            const int64_t tn = std::min<int64_t>(t.adj_tile_n, nKn);
+            const int64_t tp = std::max<int64_t>(1, t.adj_rows / tn);
+            n += ((nKp + tp - 1) / tp) * ((nKn + tn - 1) / tn);
+        }
+    }
+    return n;
+}
+
+static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
+                             void* work, const ci_tuning& t, hipStream_t s)
+{
+    return launch_vjp(b->d_bases, b->d_blk_basis, b->d_blk_local, b->nblocks, count_tiles(b, t), b->d_tile_off,
+                      b->nrows, row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work, b->n_tbme, t, b->d_queue,
+                      s);
+}
+
 size_t ci_vjp_work_bytes(const ci_basis* b) { return b ? (size_t)b->n_tbme * sizeof(double) : 0; }
 
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
@@ -583,9 +634,7 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
-    hipError_t e = launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr,
-                              grad_val, grad_tbme, (double*)work, b->n_tbme, b->tune, b->d_queue,
-                              (hipStream_t)stream);
+    hipError_t e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "vjp launch");
     return CI_OK;
 }
@@ -593,7 +642,8 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
 static bool tuning_ok(const ci_tuning& t)
 {
     return (t.row_waves == 4 || t.row_waves == 8) && t.row_grab >= 0 && t.row_grab <= 4096 && t.adj_rows >= 1 &&
-           t.adj_rows <= 4096 && (t.adj_persistent == 0 || t.adj_persistent == 1);
+           t.adj_rows <= 4096 && t.adj_tile_n >= 1 && t.adj_tile_n <= 4096 &&
+           (t.adj_persistent == 0 || t.adj_persistent == 1);
 }
 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
@@ -653,22 +703,23 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                 have = true;
             }
         }
-    // adjoint: rows per shared table x (grid, persistent)
+    // adjoint: tile (rows, neutron width) x (grid, persistent)
     have = false;
-    for (int rows : {16, 32, 64})
+    const int tiles[][2] = {{32, 32}, {32, 8}, {32, 4}, {64, 16}, {64, 8}};
+    for (const auto& tl : tiles)
         for (int pers : {0, 1}) {
             if (rc != CI_OK) break;
             b->tune = best;
-            b->tune.adj_rows = rows;
+            b->tune.adj_rows = tl[0];
+            b->tune.adj_tile_n = tl[1];
             b->tune.adj_persistent = pers;
             float ms = 0.0f;
-            rc = time_ms([&] { return launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows,
-                                                 row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work,
-                                                 b->n_tbme, b->tune, b->d_queue, s); },
-                         reps, s, e0, e1, &ms);
+            rc = time_ms([&] { return vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s); }, reps, s, e0,
+                         e1, &ms);
             if (rc == CI_OK && (!have || ms < best_ms)) {
                 best_ms = ms;
-                best.adj_rows = rows;
+                best.adj_rows = tl[0];
+                best.adj_tile_n = tl[1];
                 best.adj_persistent = pers;
                 have = true;
             }
@@ -684,9 +735,7 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     // leave col / val / grad_tbme as the chosen shapes compute them
     e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
                     val, b->tune, b->d_queue, s);
-    if (e == hipSuccess)
-        e = launch_vjp(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, grad_val,
-                       grad_tbme, (double*)work, b->n_tbme, b->tune, b->d_queue, s);
+    if (e == hipSuccess) e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "autotune final run");
     return CI_OK;

@@ -554,6 +554,13 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     return pos;
 }
 
+template <int MODE>
+__device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int r, const float* __restrict__ tbme,
+                                           int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
+                                           float* __restrict__ val, const float* __restrict__ gval,
+                                           double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
+                                           bool use_table, WaveLds& L);
+
 // Row grow of the batch (rows of all bases are numbered consecutively) on the
 // calling wavefront.
 template <int MODE>
@@ -579,6 +586,18 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
         else hi = mid;
     }
     const int bi = uniform(lo);
+    run_row_at<MODE>(B, bi, i, i - (int)blk_off[bi], tbme, row_ptr, nrp, col, val, gval, gacc, hkey, hval, use_table,
+                     L);
+}
+
+// Row i of basis B, row r of its block bi.
+template <int MODE>
+__device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int r, const float* __restrict__ tbme,
+                                           int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
+                                           float* __restrict__ val, const float* __restrict__ gval,
+                                           double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
+                                           bool use_table, WaveLds& L)
+{
     RowView R;
     R.B = &B;
     R.tbme = tbme ? tbme + B.tbme0 : nullptr;
@@ -593,7 +612,6 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
     R.Z = B.Z;
     R.NN = B.NN;
     R.spe_sum = 0.0;
-    const int r = i - (int)blk_off[bi];
     if (MODE == kCount) {
         R.pos0 = 0;
         R.cap = 0;
@@ -638,16 +656,69 @@ __global__ void __launch_bounds__(64 * WAVES)
     }
 }
 
-// Adjoint: a workgroup takes a group of rows_per_group consecutive rows, its
-// wavefronts take them one at a time from a shared counter, and the
-// contributions meet in the LDS accumulator table, which is added to the FP64
-// accumulator and cleared when the group is done.  persistent == 0: group =
-// workgroup index; persistent == 1: a persistent grid takes groups from the
-// work counter *queue (zero at launch).  use_table == 0 (global table
-// positions do not fit 32 bits): every contribution goes to the accumulator.
+// Adjoint row groups: each block (proton key Kp, neutron key Kn) is cut into
+// tiles of tp x tn determinants, tn = min(tile_n, |Kn|), tp = max(1, rows /
+// tn); the rows of a tile share proton moves (same P) and neutron moves (same
+// N), so their table positions repeat.  tile_off[gb + 1] (inclusive scan over
+// the global block list of the batch) is the number of tiles of blocks <= gb.
+__device__ __forceinline__ void block_tile_shape(int nKp, int nKn, int rows, int tile_n, int* tp, int* tn)
+{
+    const int n = tile_n < nKn ? tile_n : nKn;
+    const int p = rows / n;
+    *tn = n;
+    *tp = p > 1 ? p : 1;
+    (void)nKp;
+}
+
+__global__ void __launch_bounds__(256) tile_offsets(const BasisDev* __restrict__ bases,
+                                                    const int32_t* __restrict__ blk_basis,
+                                                    const int32_t* __restrict__ blk_local, int nblocks, int rows,
+                                                    int tile_n, int64_t* __restrict__ tile_off)
+{
+    __shared__ int64_t part[4];
+    int64_t carry = 0;
+    if (threadIdx.x == 0) tile_off[0] = 0;
+    for (int g0 = 0; g0 < nblocks; g0 += 256) {
+        const int gb = g0 + (int)threadIdx.x;
+        int64_t n = 0;
+        if (gb < nblocks) {
+            const BasisDev& B = bases[blk_basis[gb]];
+            const int bi = blk_local[gb];
+            const int kn = B.blk_kn[bi];
+            const int nKn = B.sp[1].key_off[kn + 1] - B.sp[1].key_off[kn];
+            const int nKp = (int)((B.blk_off[bi + 1] - B.blk_off[bi]) / nKn);
+            int tp, tn;
+            block_tile_shape(nKp, nKn, rows, tile_n, &tp, &tn);
+            n = (int64_t)((nKp + tp - 1) / tp) * ((nKn + tn - 1) / tn);
+        }
+        // inclusive scan over the 256 threads: wave scan, then wave totals
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        int64_t v = n;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(v, o, 64);
+            if (lane >= o) v += u;
+        }
+        if (lane == 63) part[w] = v;
+        __syncthreads();
+        int64_t add = carry;
+        for (int k = 0; k < w; k++) add += part[k];
+        if (gb < nblocks) tile_off[gb + 1] = v + add;
+        carry += part[0] + part[1] + part[2] + part[3];
+        __syncthreads();
+    }
+}
+
+// Adjoint: a workgroup takes one tile of rows (above), its wavefronts take
+// the tile's rows one at a time from a shared counter, and the contributions
+// meet in the LDS accumulator table, which is added to the FP64 accumulator
+// and cleared when the tile is done.  persistent == 0: tile = workgroup
+// index; persistent == 1: a persistent grid takes tiles from the work counter
+// *queue (zero at launch).  use_table == 0 (global table positions do not fit
+// 32 bits): every contribution goes to the accumulator.
 __global__ void __launch_bounds__(64 * kAdjWaves)
-    adjoint_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
-                   int64_t nrows, int rows_per_group, const int64_t* __restrict__ row_ptr, int64_t nrp,
+    adjoint_kernel(const BasisDev* __restrict__ bases, const int32_t* __restrict__ blk_basis,
+                   const int32_t* __restrict__ blk_local, int nblocks, const int64_t* __restrict__ tile_off,
+                   int rows, int tile_n, const int64_t* __restrict__ row_ptr, int64_t nrp,
                    const float* __restrict__ gval, double* __restrict__ gacc, int use_table, int persistent,
                    unsigned long long* __restrict__ queue)
 {
@@ -655,31 +726,61 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
     __shared__ uint32_t hkey[kAdjSlots];
     __shared__ float hval[kAdjSlots];
     __shared__ int next_row;
-    __shared__ int64_t group_first;
+    __shared__ int t_gb, t_ip0, t_in0, t_tp, t_tn, t_nKn, t_valid;
     for (int s = threadIdx.x; s < kAdjSlots; s += 64 * kAdjWaves) {
         hkey[s] = kAdjEmpty;
         hval[s] = 0.0f;
     }
     const int wid = uniform(threadIdx.x >> 6);
+    const int64_t ntiles = tile_off[nblocks];
     for (;;) {
         if (threadIdx.x == 0) {
             next_row = 0;
             const int64_t g = persistent ? (int64_t)__hip_atomic_fetch_add(glbw(queue), 1ull, __ATOMIC_RELAXED,
                                                                             __HIP_MEMORY_SCOPE_AGENT)
                                          : (int64_t)blockIdx.x;
-            group_first = g * rows_per_group;
+            t_valid = g < ntiles;
+            if (g < ntiles) {
+                // block of the tile: largest gb with tile_off[gb] <= g
+                int lo = 0, hi = nblocks;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (tile_off[mid] <= g) lo = mid;
+                    else hi = mid;
+                }
+                const BasisDev& B = bases[blk_basis[lo]];
+                const int bi = blk_local[lo];
+                const int kn = B.blk_kn[bi];
+                const int nKn = B.sp[1].key_off[kn + 1] - B.sp[1].key_off[kn];
+                const int nKp = (int)((B.blk_off[bi + 1] - B.blk_off[bi]) / nKn);
+                int tp, tn;
+                block_tile_shape(nKp, nKn, rows, tile_n, &tp, &tn);
+                const int t = (int)(g - tile_off[lo]), ntn = (nKn + tn - 1) / tn;
+                const int ip0 = (t / ntn) * tp, in0 = (t % ntn) * tn;
+                t_gb = lo;
+                t_ip0 = ip0;
+                t_in0 = in0;
+                t_tp = (nKp - ip0) < tp ? nKp - ip0 : tp;
+                t_tn = (nKn - in0) < tn ? nKn - in0 : tn;
+                t_nKn = nKn;
+            }
         }
         __syncthreads();
-        const int64_t first = group_first;
-        if (first >= nrows) break;
+        if (!t_valid) break;
+        const int gb = t_gb, ip0 = t_ip0, in0 = t_in0, tp = t_tp, tn = t_tn, nKn = t_nKn;
+        const BasisDev& B = bases[blk_basis[gb]];
+        const int bi = blk_local[gb];
+        const int cnt = tp * tn;
         for (;;) {
             int t = 0;
             if ((threadIdx.x & 63) == 0) t = atomicAdd(&next_row, 1);
             t = uniform(t);
-            if (t >= rows_per_group || first + t >= nrows) break;
-            run_row<kAdjoint>(bases, nb, basis_row0, first + t, nullptr, const_cast<int64_t*>(row_ptr), nrp,
-                              nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval, use_table != 0,
-                              lds[wid]);
+            if (t >= cnt) break;
+            const int u = t / tn, v = t - u * tn;
+            const int r = (ip0 + u) * nKn + in0 + v;
+            run_row_at<kAdjoint>(B, bi, (int)B.blk_off[bi] + r, r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
+                                 nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval,
+                                 use_table != 0, lds[wid]);
         }
         __syncthreads();
         if (use_table) {
@@ -900,23 +1001,26 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
                               queue, s);
 }
 
-hipError_t launch_vjp(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
-                      const int64_t* row_ptr, int64_t nrp, const float* gval, float* gtbme, double* gacc,
-                      int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
+                      int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
+                      const float* gval, float* gtbme, double* gacc, int64_t ntbme, const ci_tuning& t,
+                      unsigned long long* queue, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
-    if (nrows > 0) {
-        const int rpg = t.adj_rows > 0 ? t.adj_rows : 32;
+    if (nrows > 0 && ntiles > 0) {
         const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
-        unsigned grid = grid_for(nrows, rpg);
+        hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, t.adj_rows,
+                           t.adj_tile_n, tile_off);
+        unsigned grid = (unsigned)ntiles;
         if (t.adj_persistent) {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
             const unsigned res = resident_blocks((const void*)adjoint_kernel, 64 * kAdjWaves, 6);
             grid = res < grid ? res : grid;
         }
-        hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(64 * kAdjWaves), 0, s, bases, nb, basis_row0, nrows,
-                           rpg, row_ptr, nrp, gval, gacc, use_table, t.adj_persistent ? 1 : 0, queue);
+        hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(64 * kAdjWaves), 0, s, bases, blk_basis, blk_local,
+                           nblocks, tile_off, t.adj_rows, t.adj_tile_n, row_ptr, nrp, gval, gacc, use_table,
+                           t.adj_persistent ? 1 : 0, queue);
     }
     if (ntbme > 0) hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
     return hipGetLastError();

@@ -307,7 +307,8 @@ def test_autograd_function(ci):
 # ------------------------------------------------------------------ launch shapes and batches
 
 SHAPES = [dict(row_waves=w, row_grab=g) for w in (4, 8) for g in (0, 1, 7)]
-ADJ_SHAPES = [dict(adj_rows=r, adj_persistent=q) for r in (1, 17, 64) for q in (0, 1)]
+ADJ_SHAPES = [dict(adj_rows=r, adj_tile_n=n, adj_persistent=q) for r, n in ((1, 1), (17, 5), (64, 16), (32, 64))
+              for q in (0, 1)]
 
 
 def test_launch_shapes_give_the_same_result(ci):
@@ -346,7 +347,7 @@ def test_tuning_validation_and_tuner(ci):
     probs = SMALL[:6]
     seeds = [300 + k for k in range(len(probs))]
     b, rp, col, val, tb = run_forward(ci, probs, seeds)
-    for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_persistent=2)):
+    for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_tile_n=0), dict(adj_persistent=2)):
         with pytest.raises(ci.CIError):
             b.tuning = bad
     rp_t = torch.from_numpy(rp).cuda()
@@ -358,7 +359,8 @@ def test_tuning_validation_and_tuner(ci):
     t = ci.ci_hamiltonian_tune(b, tbme, rp_t, c, v, G, reps=1)
     say("tuned", t)
     assert t["row_waves"] in (4, 8) and t["row_grab"] in (0, 1, 4, 16)
-    assert t["adj_rows"] in (16, 32, 64) and t["adj_persistent"] in (0, 1)
+    assert (t["adj_rows"], t["adj_tile_n"]) in ((32, 32), (32, 8), (32, 4), (64, 16), (64, 8))
+    assert t["adj_persistent"] in (0, 1)
     torch.cuda.synchronize()
     assert np.array_equal(c.cpu().numpy(), col)
     assert np.array_equal(v.cpu().numpy().view(np.int32), val.view(np.int32))
