@@ -121,7 +121,7 @@ struct SpOff {
 };
 struct UOff {
     SpOff sp[2];
-    size_t blk_kp, blk_kn, blk_off, pair, orb_n, totals;
+    size_t blk_kp, blk_kn, blk_off, blk, pair, orb_n, totals;
     size_t bytes;
 };
 
@@ -293,6 +293,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
         uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
         uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
+        uo[u].blk = L.take<BlockInfo>(hb.blk_kp.size());
         uo[u].pair = L.take<uint64_t>(hb.pair.size());
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
         ubytes[u] += L.off - s0;
@@ -379,6 +380,16 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
         put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
         put(uo[u].blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
+        {
+            BlockInfo* bk = (BlockInfo*)(mirror + uo[u].blk);
+            for (int k = 0; k < hb.nblk(); k++) {
+                const HostSpecies& N = hb.sp[1];
+                bk[k].kp = hb.blk_kp[k];
+                bk[k].kn = hb.blk_kn[k];
+                bk[k].row0 = (int32_t)hb.blk_off[k];
+                bk[k].nkn = N.key_off[hb.blk_kn[k] + 1] - N.key_off[hb.blk_kn[k]];
+            }
+        }
         write_pair64(hb, (uint64_t*)(mirror + uo[u].pair));
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
     }
@@ -510,6 +521,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.blk_kp = (const int32_t*)D(uo[u].blk_kp);
         d.blk_kn = (const int32_t*)D(uo[u].blk_kn);
         d.blk_off = (const int64_t*)D(uo[u].blk_off);
+        d.blk = (const BlockInfo*)D(uo[u].blk);
         d.pair = (const uint64_t*)D(uo[u].pair);
         d.orb_n = (const int32_t*)D(uo[u].orb_n);
         d.dim = hb.dim;

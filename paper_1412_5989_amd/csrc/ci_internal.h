@@ -62,8 +62,16 @@ struct SpeciesDev {
     int32_t nsd, nk;
 };
 
+// One block (proton key, neutron key) as one 16-byte record.
+struct alignas(16) BlockInfo {
+    int32_t kp, kn;  // proton and neutron key
+    int32_t row0;    // first row (the block offset)
+    int32_t nkn;     // rows per proton determinant (|Kn|)
+};
+
 struct BasisDev {
     SpeciesDev sp[2];          // 0 = protons, 1 = neutrons
+    const BlockInfo* blk;      // [nblk]
     const int32_t* blk_kp;     // [nblk]
     const int32_t* blk_kn;     // [nblk]
     const int64_t* blk_off;    // [nblk + 1] first row of each block

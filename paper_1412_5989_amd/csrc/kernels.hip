@@ -74,6 +74,8 @@ __device__ __forceinline__ gmut<T> glbw(T* p)
 template <typename T>
 using lptr = __attribute__((address_space(3))) T*;
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));  // a BlockInfo record
+
 // Adjoint: the rows of a workgroup scatter into a shared LDS table first
 // (open addressing on the global table position, FP32 partial sums), and each
 // occupied slot is added to the FP64 accumulator once at the end.  Table keys
@@ -401,25 +403,26 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     const int self12 = glb(SN.self12)[gN];
 
     if (MODE != kCount) {
-        // occupied orbits of the row (for the multi-term entries)
-        double e = 0.0;
-        if (lane == 0) {
-            int t = 0;
-            for (int s = 0; s < 2; s++) {
-                const gptr<uint64_t> w = glb(s == 0 ? SP.sd + (int64_t)gP * B.W : SN.sd + (int64_t)gN * B.W);
-                for (int k = 0; k < B.W; k++) {
-                    uint64_t x = w[k];
-                    while (x) {
-                        const int o = k * 64 + __ffsll((long long)x) - 1;
-                        x &= x - 1;
-                        L.occ[t++] = (uint8_t)o;
-                        e += (glb(B.orb_n)[o] + 1.5) * B.hw;
-                    }
-                }
-            }
-        }
-        R.spe_sum = __shfl(e, 0, 64);
+        // occupied orbits of the row (for the multi-term entries): lane j < 2W
+        // holds determinant word j (protons, then neutrons), a wave scan gives
+        // each word's first slot in occ, and the shells of the occupied orbits
+        // give the single-particle sum
+        const int W = B.W;
+        uint64_t word = 0;
+        if (lane < 2 * W)
+            word = lane < W ? glb(SP.sd)[(int64_t)gP * W + lane] : glb(SN.sd)[(int64_t)gN * W + (lane - W)];
+        const int cnt = __popcll(word);
+        int t = wave_incl_scan(cnt) - cnt;
+        const int obase = (lane < W ? lane : lane - W) * 64;
+        for (uint64_t x = word; x; x &= x - 1) L.occ[t++] = (uint8_t)(obase + __ffsll((long long)x) - 1);
         wave_sync();
+        const int A = R.Z + R.NN;
+        int shells = 0;
+        for (int j0 = 0; j0 < A; j0 += 64) {
+            const int j = j0 + lane;
+            shells += lane63(wave_incl_scan(j < A ? glb(B.orb_n)[L.occ[j]] : 0));
+        }
+        R.spe_sum = ((double)shells + 1.5 * A) * B.hw;
     }
 
     int64_t pos = 0;  // entries of the row so far
@@ -430,13 +433,14 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
         const int b2 = w0 + lane;
         int np = 0, bp = 0, bcol = 0, bstr = 0, bn1 = 0, bl1 = 0, bn12 = 0, bl12 = 0;
         if (b2 < B.nblk) {
-            const int kp2 = blk_kp[b2], kn2 = blk_kn[b2];
+            const i32x4 bk = glb((const i32x4*)B.blk)[b2];  // one 16-byte load
+            const int kp2 = bk.x, kn2 = bk.y;
             const bool same_n = (kn2 == kn);
             const int ps = same_n ? sP12[kp2] : sP1[kp2];
             np = (same_n ? sP12[kp2 + 1] : sP1[kp2 + 1]) - ps;
             bp = ps | (same_n ? (int)0x80000000 : 0);
-            bcol = (int)blk_off[b2];
-            bstr = nkoff[kn2 + 1] - nkoff[kn2];
+            bcol = bk.z;  // first row of the block
+            bstr = bk.w;  // |Kn'|
             bn1 = sN1[kn2];
             bl1 = sN1[kn2 + 1] - bn1;
             bn12 = sN12[kn2] + (b2 == bi ? self12 : 0);  // diagonal block: N' >= N
