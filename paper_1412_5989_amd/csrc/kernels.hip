@@ -76,6 +76,18 @@ using lptr = __attribute__((address_space(3))) T*;
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));  // a BlockInfo record
 
+// The index tables and row_ptr do not change while a row kernel runs, so the
+// row-uniform reads of them go through the constant address space: the
+// compiler then issues scalar loads (scalar cache) instead of vector loads,
+// which would all pass through the vector memory pipeline.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> cst(const T* p)
+{
+    return (cptr<T>)p;
+}
+
 // Adjoint: the rows of a workgroup scatter into a shared LDS table first
 // (open addressing on the global table position, FP32 partial sums), and each
 // occupied slot is added to the FP64 accumulator once at the end.  Table keys
@@ -383,24 +395,22 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     const int lane = threadIdx.x & 63;
     const SpeciesDev& SP = B.sp[0];
     const SpeciesDev& SN = B.sp[1];
-    const gptr<int32_t> blk_kp = glb(B.blk_kp), blk_kn = glb(B.blk_kn);
-    const gptr<int64_t> blk_off = glb(B.blk_off);
-    const gptr<int32_t> pkoff = glb(SP.key_off), nkoff = glb(SN.key_off);
-    const int kp = blk_kp[bi], kn = blk_kn[bi];
+    const cptr<int32_t> pkoff = cst(SP.key_off), nkoff = cst(SN.key_off);
+    const int kp = uniform(cst(B.blk_kp)[bi]), kn = uniform(cst(B.blk_kn)[bi]);
     const int nKn = nkoff[kn + 1] - nkoff[kn];
-    const int ip = r / nKn, in = r - ip * nKn;
-    const int gP = pkoff[kp] + ip;
-    const int gN = nkoff[kn] + in;
+    const int ip = uniform(r / nKn), in = uniform(r - ip * nKn);
+    const int gP = uniform(pkoff[kp] + ip);
+    const int gN = uniform(nkoff[kn] + in);
     const int nkp = SP.nk, nkn = SN.nk;
-    const gptr<uint64_t> P1 = glb(SP.l1 + glb(SP.l1_ptr)[gP]);
-    const gptr<uint64_t> P12 = glb(SP.l12 + glb(SP.l12_ptr)[gP]);
+    const gptr<uint64_t> P1 = glb(SP.l1 + cst(SP.l1_ptr)[gP]);
+    const gptr<uint64_t> P12 = glb(SP.l12 + cst(SP.l12_ptr)[gP]);
     const gptr<int32_t> sP1 = glb(SP.seg1 + (int64_t)gP * (nkp + 1));
     const gptr<int32_t> sP12 = glb(SP.seg12 + (int64_t)gP * (nkp + 1));
-    const gptr<uint64_t> N1 = glb(SN.l1 + glb(SN.l1_ptr)[gN]);
-    const gptr<uint64_t> N12 = glb(SN.l12 + glb(SN.l12_ptr)[gN]);
+    const gptr<uint64_t> N1 = glb(SN.l1 + cst(SN.l1_ptr)[gN]);
+    const gptr<uint64_t> N12 = glb(SN.l12 + cst(SN.l12_ptr)[gN]);
     const gptr<int32_t> sN1 = glb(SN.seg1 + (int64_t)gN * (nkn + 1));
     const gptr<int32_t> sN12 = glb(SN.seg12 + (int64_t)gN * (nkn + 1));
-    const int self12 = glb(SN.self12)[gN];
+    const int self12 = uniform(cst(SN.self12)[gN]);
 
     if (MODE != kCount) {
         // occupied orbits of the row (for the multi-term entries): lane j < 2W
@@ -577,12 +587,12 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
 {
     // basis of the row (few bases: linear search)
     int b = 0;
-    while (b + 1 < nb && basis_row0[b + 1] <= grow) b++;
+    while (b + 1 < nb && cst(basis_row0)[b + 1] <= grow) b++;
     b = uniform(b);
     const BasisDev& B = bases[b];
-    const int i = (int)(grow - basis_row0[b]);
+    const int i = uniform((int)(grow - cst(basis_row0)[b]));
     // block of the row
-    const gptr<int64_t> blk_off = glb(B.blk_off);
+    const cptr<int64_t> blk_off = cst(B.blk_off);
     int lo = 0, hi = B.nblk;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -622,8 +632,8 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
         const int64_t n = do_row<kCount>(B, L, bi, r, R);
         if ((threadIdx.x & 63) == 0) glbw(row_ptr)[B.row0 + i + 1] = n;
     } else {
-        R.pos0 = uniform64(row_ptr[B.row0 + i]);
-        R.cap = uniform64(row_ptr[nrp - 1]);  // the entries of all bases end here
+        R.pos0 = uniform64(cst(row_ptr)[B.row0 + i]);
+        R.cap = uniform64(cst(row_ptr)[nrp - 1]);  // the entries of all bases end here
         do_row<MODE>(B, L, bi, r, R);
     }
 }
@@ -771,9 +781,10 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
         }
         __syncthreads();
         if (!t_valid) break;
-        const int gb = t_gb, ip0 = t_ip0, in0 = t_in0, tp = t_tp, tn = t_tn, nKn = t_nKn;
-        const BasisDev& B = bases[blk_basis[gb]];
-        const int bi = blk_local[gb];
+        const int gb = uniform(t_gb), ip0 = uniform(t_ip0), in0 = uniform(t_in0), tp = uniform(t_tp),
+                  tn = uniform(t_tn), nKn = uniform(t_nKn);
+        const BasisDev& B = bases[uniform(cst(blk_basis)[gb])];
+        const int bi = uniform(cst(blk_local)[gb]);
         const int cnt = tp * tn;
         for (;;) {
             int t = 0;
@@ -782,7 +793,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
             if (t >= cnt) break;
             const int u = t / tn, v = t - u * tn;
             const int r = (ip0 + u) * nKn + in0 + v;
-            run_row_at<kAdjoint>(B, bi, (int)B.blk_off[bi] + r, r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
+            run_row_at<kAdjoint>(B, bi, uniform((int)cst(B.blk_off)[bi] + r), r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
                                  nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval,
                                  use_table != 0, lds[wid]);
         }
