@@ -244,7 +244,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             continue;
         }
         auto hb = std::make_shared<HostBasis>();
-        rc = plan_basis(probs[b], *hb, err);
+        rc = plan_structure(probs[b], *hb, err);  // the pair index follows, overlapped with the device
         if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
         which[b] = (int)ub.size();
         uniq[key_of(probs[b])] = which[b];
@@ -294,7 +294,6 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
         uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
         uo[u].blk = L.take<BlockInfo>(hb.blk_kp.size());
-        uo[u].pair = L.take<uint64_t>(hb.pair.size());
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
         ubytes[u] += L.off - s0;
     }
@@ -305,6 +304,13 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     for (int32_t b = 0; b < n_probs; b++) nblocks += ub[which[b]]->nblk();
     const size_t o_blk_basis = L.take<int32_t>(std::max(nblocks, 1));
     const size_t o_blk_local = L.take<int32_t>(std::max(nblocks, 1));
+    // the pair indices last: they are written after the partner kernels start
+    const size_t pair_start = L.off;
+    for (size_t u = 0; u < ub.size(); u++) {
+        const size_t n = (size_t)ub[u]->nsps;
+        uo[u].pair = L.take<uint64_t>(3 * n * n);
+        ubytes[u] += 3 * n * n * sizeof(uint64_t);
+    }
     const size_t host_bytes = L.off;
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
@@ -329,11 +335,8 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
         uo[u].bytes = ubytes[u];
     }
-    int64_t R = 0, T = 0;
-    for (int32_t b = 0; b < n_probs; b++) {
-        R += ub[which[b]]->dim + 1;
-        T += ub[which[b]]->n_tbme;
-    }
+    int64_t R = 0, T = 0;  // T (table offsets) is known once the pair index is built
+    for (int32_t b = 0; b < n_probs; b++) R += ub[which[b]]->dim + 1;
     max_scan = std::max(max_scan, R);
     const size_t o_bases = L.take<BasisDev>(n_probs);
     const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
@@ -390,7 +393,6 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
                 bk[k].nkn = N.key_off[hb.blk_kn[k] + 1] - N.key_off[hb.blk_kn[k]];
             }
         }
-        write_pair64(hb, (uint64_t*)(mirror + uo[u].pair));
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
     }
     std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
@@ -415,7 +417,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     put(o_row0, row0.data(), row0.size() * 8);
     put(o_first, first.data(), first.size() * 8);
     put(o_last, last.data(), last.size() * 8);
-    e = hipMemcpyAsync(h->arena, mirror, host_bytes, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(h->arena, mirror, pair_start, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index tables)");
 
     // ---- partner lists on the device: count, scan, read the lengths back
@@ -454,6 +456,17 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
                 (e = launch_copy_i64(a.l12_ptr + a.nsd, tot + 2 * sidx + 1, s)) != hipSuccess)
                 return hip_fail(e, "partner totals");
         }
+    // two-body pair index on the host while the partner kernels run
+    for (size_t u = 0; u < ub.size(); u++) {
+        const int rc = plan_tbme_index(*ub[u], err);
+        if (rc != CI_OK) {
+            hipStreamSynchronize(s);
+            return fail(rc, "problem " + std::to_string(u) + ": " + err);
+        }
+        write_pair64(*ub[u], (uint64_t*)(mirror + uo[u].pair));
+    }
+    e = hipMemcpyAsync(dev + pair_start, mirror + pair_start, host_bytes - pair_start, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pair index)");
     std::vector<int64_t> totals(4 * ub.size());
     for (size_t u = 0; u < ub.size(); u++) {
         e = hipMemcpyAsync(&totals[4 * u], D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);

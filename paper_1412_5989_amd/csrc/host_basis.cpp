@@ -294,15 +294,20 @@ int validate_problem(const ci_problem& p, std::string& err)
     return CI_OK;
 }
 
-int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
+int plan_structure(const ci_problem& p, HostBasis& hb, std::string& err)
 {
     int rc = validate_problem(p, err);
     if (rc != CI_OK) return rc;
-    rc = make_structure(p, hb, err);
+    return make_structure(p, hb, err);
+}
+
+int plan_tbme_index(HostBasis& hb, std::string& err) { return make_tbme_index(hb, err); }
+
+int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
+{
+    int rc = plan_structure(p, hb, err);
     if (rc != CI_OK) return rc;
-    rc = make_tbme_index(hb, err);
-    if (rc != CI_OK) return rc;
-    return CI_OK;
+    return plan_tbme_index(hb, err);
 }
 
 void write_pair64(const HostBasis& hb, uint64_t* out)

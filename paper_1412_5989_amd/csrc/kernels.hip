@@ -442,6 +442,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
         //    the row's neutron partners, column base
         const int b2 = w0 + lane;
         int np = 0, bp = 0, bcol = 0, bstr = 0, bn1 = 0, bl1 = 0, bn12 = 0, bl12 = 0;
+        int64_t blen = 0;  // count pass: entries of the lane's block (other blocks than the row's)
         if (b2 < B.nblk) {
             const i32x4 bk = glb((const i32x4*)B.blk)[b2];  // one 16-byte load
             const int kp2 = bk.x, kn2 = bk.y;
@@ -459,6 +460,23 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             // (d <= 1 for a moved proton, d <= 2 for P' = P): otherwise every
             // segment of the block is empty
             if (!same_n && bl1 == 0 && (kp2 != kp || bl12 == 0)) np = 0;
+            if (MODE == kCount && b2 != bi) {
+                // entries of a block other than the row's own, from the per-key
+                // counts: P' = P gives bl12, every one-proton move bl1, every
+                // two-proton move (same neutron key only) one entry
+                const int d0 = kp2 == kp ? 1 : 0;
+                const int c1 = sP1[kp2 + 1] - sP1[kp2];  // d <= 1 partners of P in Kp'
+                const int c12 = same_n ? np : c1;         // d <= 2 partners (same 2M and parity keys)
+                blen = (int64_t)(c12 - c1) + (int64_t)(c1 - d0) * bl1 + (int64_t)d0 * bl12;
+                np = 0;
+            }
+        }
+        if (MODE == kCount) {
+            // only the row's own block (lane 0 of the first window) is walked
+            // segment by segment: it is cut at the diagonal
+            int64_t t = blen;
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            pos += t;
         }
         const int bincl = wave_incl_scan(np);
         const int bstart = bincl - np;  // first segment of the lane's block
