@@ -31,6 +31,13 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* glbw(T* p)
 {
     return (__attribute__((address_space(1))) T*)p;
 }
+// tables that a kernel only reads, read with wavefront-uniform addresses:
+// through the constant address space they become scalar loads
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cst(const T* p)
+{
+    return (const __attribute__((address_space(4))) T*)p;
+}
 
 // number of set bits of the W-word string strictly below orbit k
 __device__ __forceinline__ int bits_below(const uint64_t* w, int W, int k)
@@ -83,15 +90,18 @@ __device__ uint64_t partner_record(const uint64_t* x, const uint64_t* y, int W, 
     return make_rec(yl, 2, h1, p1, h2, p2, e & 1);
 }
 
-// Work item = (determinant x, key group g): the keys are cut into kGroups
-// groups by the position of their first determinant, and one wavefront scans
-// the candidates of one group for one x.  The count pass writes the number of
-// partners of x in each key; a per-x scan turns those into segment offsets;
-// the fill pass writes each key's records at its offset.
+// Work item = (block of kXB consecutive determinants x, key group g): the
+// keys are cut into kGroups groups by the position of their first
+// determinant, and one wavefront scans the candidates of one group for kXB
+// determinants at once (every candidate chunk is loaded once and tested
+// against all of them).  The count pass writes the number of partners of each
+// x in each key; a per-x scan turns those into segment offsets; the fill pass
+// writes each key's records at its offset.
 constexpr int kGroups = 8;
+constexpr int kXB = 4;
 
 // keys [k0, k1) of group g: those whose first determinant lies in the g-th slice
-__device__ __forceinline__ void key_group(const __attribute__((address_space(1))) int32_t* key_off, int nk,
+__device__ __forceinline__ void key_group(const __attribute__((address_space(4))) int32_t* key_off, int nk,
                                           int nsd, int g, int* k0, int* k1)
 {
     const int lo = (int)((int64_t)nsd * g / kGroups), hi = (int)((int64_t)nsd * (g + 1) / kGroups);
@@ -103,16 +113,9 @@ __device__ __forceinline__ void key_group(const __attribute__((address_space(1))
     *k1 = b;
 }
 
-// sum over the 64 lanes (DPP row shifts, row broadcasts), result in every lane
-__device__ __forceinline__ int wave_sum(int v)
+__device__ __forceinline__ int rank_in(uint64_t m)
 {
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
-    return __builtin_amdgcn_readlane(v, 63);
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
 template <int W, bool FILL>
@@ -120,75 +123,79 @@ __global__ void __launch_bounds__(64 * kPartnerWaves) partner_kernel(PartnerArgs
 {
     const int lane = threadIdx.x & 63;
     const int item = (int)blockIdx.x * kPartnerWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int x = item / kGroups, g = item - x * kGroups;
-    if (x >= A.nsd) return;
+    const int xb = item / kGroups, g = item - xb * kGroups;
+    const int x0 = xb * kXB;
+    if (x0 >= A.nsd) return;
     const int nsd = A.nsd;
-    const auto sd = glb(A.sd);
-    const auto key_off = glb(A.key_off), key_nq = glb(A.key_nq), key_m2 = glb(A.key_m2);
+    const int nx = nsd - x0 < kXB ? nsd - x0 : kXB;  // determinants of this block
+    const auto sd = cst(A.sd);
+    const auto key_off = cst(A.key_off), key_nq = cst(A.key_nq), key_m2 = cst(A.key_m2);
     int k0, k1;
     key_group(key_off, A.nk, nsd, g, &k0, &k1);
     if (k0 >= k1) return;
-    uint64_t xw[W];
+    uint64_t xw[kXB][W];
+    int mx[kXB], qx[kXB];
+    int64_t o1[kXB], o12[kXB];
+#pragma unroll
+    for (int j = 0; j < kXB; j++) {
+        const int x = x0 + (j < nx ? j : 0);
+#pragma unroll
+        for (int t = 0; t < W; t++) xw[j][t] = sd[(int64_t)x * W + t];
+        const int kx = cst(A.sd_key)[x];
+        mx[j] = key_m2[kx];
+        qx[j] = key_nq[kx];
+        o1[j] = FILL ? cst(A.l1_ptr)[x] : 0;
+        o12[j] = FILL ? cst(A.l12_ptr)[x] : 0;
+    }
     const __attribute__((address_space(1))) uint64_t* col[W];  // word t of every determinant
 #pragma unroll
-    for (int t = 0; t < W; t++) {
-        xw[t] = sd[(int64_t)x * W + t];
-        col[t] = glb(A.sdT) + (int64_t)t * nsd;
-    }
-    const int kx = glb(A.sd_key)[x];
-    const int mx = key_m2[kx], qx = key_nq[kx];
-    const auto s1 = glbw(A.seg1 + (int64_t)x * (A.nk + 1));
-    const auto s12 = glbw(A.seg12 + (int64_t)x * (A.nk + 1));
-    const int64_t o1 = FILL ? glb(A.l1_ptr)[x] : 0, o12 = FILL ? glb(A.l12_ptr)[x] : 0;
+    for (int t = 0; t < W; t++) col[t] = glb(A.sdT) + (int64_t)t * nsd;
     const auto l1 = glbw(A.l1), l12 = glbw(A.l12);
     for (int k = k0; k < k1; k++) {
-        const bool same = key_m2[k] == mx && ((key_nq[k] - qx) & 1) == 0;
+        const int km = key_m2[k], kq = key_nq[k];
         const int y0 = key_off[k], y1 = key_off[k + 1];
-        if (!FILL) {
-            // count only: per-lane counters, one reduction per key
-            int n1 = 0, n12 = 0;
-            for (int yb = y0; yb < y1; yb += 64) {
-                const int y = yb + lane;
-                const int yc = y < y1 ? y : y1 - 1;
-                int pc = 0;
+        int c1[kXB], c12[kXB];
+        bool same[kXB];
 #pragma unroll
-                for (int t = 0; t < W; t++) pc += __popcll(xw[t] ^ col[t][yc]);
-                const bool ok = y < y1;
-                n1 += (ok && pc <= 2) ? 1 : 0;
-                n12 += (ok && same && pc <= 4) ? 1 : 0;
-            }
-            n1 = wave_sum(n1);
-            n12 = wave_sum(n12);
-            if (lane == 0) {
-                s1[k] = n1;
-                s12[k] = n12;
-            }
-            continue;
+        for (int j = 0; j < kXB; j++) {
+            same[j] = km == mx[j] && ((kq - qx[j]) & 1) == 0;
+            const int64_t sb = (int64_t)(x0 + j) * (A.nk + 1);
+            c1[j] = (FILL && j < nx) ? cst(A.seg1)[sb + k] : 0;
+            c12[j] = (FILL && j < nx) ? cst(A.seg12)[sb + k] : 0;
         }
-        int c1 = s1[k], c12 = s12[k];
         for (int yb = y0; yb < y1; yb += 64) {
             const int y = yb + lane;
             const int yc = y < y1 ? y : y1 - 1;
-            int pc = 0;
+            uint64_t yw[W];
 #pragma unroll
-            for (int t = 0; t < W; t++) pc += __popcll(xw[t] ^ col[t][yc]);
-            const bool in1 = y < y1 && pc <= 2;
-            const bool in12 = y < y1 && same && pc <= 4;
-            const uint64_t m1 = __ballot(in1), m12 = __ballot(in12);
+            for (int t = 0; t < W; t++) yw[t] = col[t][yc];
+            const bool ok = y < y1;
             // placeholder (x, y); decoded into a partner record afterwards
-            const uint64_t ph = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
-            if (in1) {
-                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0));
-                l1[o1 + c1 + r] = ph;
+#pragma unroll
+            for (int j = 0; j < kXB; j++) {
+                int pc = 0;
+#pragma unroll
+                for (int t = 0; t < W; t++) pc += __popcll(xw[j][t] ^ yw[t]);
+                const bool in1 = ok && j < nx && pc <= 2;
+                const bool in12 = ok && j < nx && same[j] && pc <= 4;
+                const uint64_t m1 = __ballot(in1), m12 = __ballot(in12);
+                if (FILL) {
+                    const uint64_t ph = ((uint64_t)(uint32_t)(x0 + j) << 32) | (uint32_t)y;
+                    if (in1) l1[o1[j] + c1[j] + rank_in(m1)] = ph;
+                    if (in12) l12[o12[j] + c12[j] + rank_in(m12)] = ph;
+                }
+                c1[j] += __popcll(m1);
+                c12[j] += __popcll(m12);
             }
-            if (in12) {
-                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m12 >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m12, 0));
-                l12[o12 + c12 + r] = ph;
-            }
-            c1 += __popcll(m1);
-            c12 += __popcll(m12);
+        }
+        if (!FILL && lane == 0) {
+#pragma unroll
+            for (int j = 0; j < kXB; j++)
+                if (j < nx) {
+                    const int64_t sb = (int64_t)(x0 + j) * (A.nk + 1);
+                    glbw(A.seg1)[sb + k] = c1[j];
+                    glbw(A.seg12)[sb + k] = c12[j];
+                }
         }
     }
 }
@@ -265,7 +272,7 @@ static inline unsigned grid_of(int64_t items) { return (unsigned)((items + kPart
 template <bool FILL>
 static void launch_scan(const PartnerArgs& a, hipStream_t s)
 {
-    const dim3 g(grid_of((int64_t)a.nsd * kGroups)), b(64 * kPartnerWaves);
+    const dim3 g(grid_of((int64_t)((a.nsd + kXB - 1) / kXB) * kGroups)), b(64 * kPartnerWaves);
     switch (a.W) {
         case 1: hipLaunchKernelGGL((partner_kernel<1, FILL>), g, b, 0, s, a); break;
         case 2: hipLaunchKernelGGL((partner_kernel<2, FILL>), g, b, 0, s, a); break;
