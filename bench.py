@@ -121,6 +121,43 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
     }
 
 
+def run_lanczos(ci, torch, prob, tbme_seed):
+    """The step after construction: full symmetric CSR, H x, lowest eigenpair."""
+    import seeded_inputs as si
+
+    b = ci.ci_basis_build([prob])
+    D = b.info[0]["dim"]
+    tb = torch.from_numpy(si.tbme_f32(tbme_seed, b.n_tbme)).cuda()
+    rp, nnz = ci.ci_hamiltonian_count_full(b)
+    col, val = ci.ci_hamiltonian_fill_full(b, tb, rp)
+    stream = torch.cuda.current_stream()
+    ev = EventTimer(torch, stream)
+    for _ in range(3):
+        with ev:
+            ci.ci_hamiltonian_fill_full(b, tb, rp, col, val)
+    fill_ms = ev.mean_ms()
+    x = torch.ones(D, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ci.ci_hamiltonian_spmv(b, 0, rp, col, val, x, y)
+    es = EventTimer(torch, stream)
+    for _ in range(10):
+        with es:
+            ci.ci_hamiltonian_spmv(b, 0, rp, col, val, x, y)
+    spmv_ms = es.mean_ms()
+    # algorithmic bytes of H x: col + val per entry, row_ptr per row, x read
+    # once and y written once
+    alg = 8 * nnz[0] + 8 * (D + 1) + 16 * D
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-12)
+    t_l = time.perf_counter() - t0
+    b.free()
+    return {"nnz_full": nnz[0], "fill_full_ms": fill_ms, "fill_full_nnz_per_s": nnz[0] / (fill_ms * 1e-3),
+            "spmv_ms": spmv_ms, "spmv_GBps": alg / (spmv_ms * 1e-3) / 1e9,
+            "spmv_frac_of_hbm_peak": alg / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E}
+
+
 def run_batched(ci, torch, steps, warmup):
     """64 bases in one handle; fill + vjp captured in one HIP graph."""
     import seeded_inputs as si
@@ -328,6 +365,8 @@ def main():
         "fill_store_GBps": (8 * nnz + 8 * (D + 1)) / (fill_ms * 1e-3) / 1e9,
         "fill_frac_of_measured_store": (8 * nnz + 8 * (D + 1)) / (fill_ms * 1e-3) / 1e9 / ceil["store_GBps"],
     }
+    log("lanczos")
+    res["lanczos"] = run_lanczos(ci, torch, prob, w["tbme_seed"])
     if not args.no_batched:
         log("batched")
         res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)

@@ -156,6 +156,38 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val,
                        float* grad_tbme, void* work, size_t work_bytes, ci_stream stream);
 
+/* The same two passes for the FULL symmetric matrix (both triangles, every
+ * (i, j) with d(i, j) <= 2, columns ascending in a row), as the eigensolver
+ * needs it; same layout and batch conventions as above. */
+int ci_hamiltonian_count_full(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
+int ci_hamiltonian_fill_full(const ci_basis* b, const float* tbme, const int64_t* row_ptr,
+                             int32_t* col, float* val, ci_stream stream);
+
+/* y = H x for problem `prob` of the handle, H in full CSR form (row_ptr, col,
+ * val from ci_hamiltonian_count_full / _fill_full; the problem's own row
+ * segment is used).  x, y: device FP64 [D]; FP64 sums in a fixed order per
+ * row (reproducible).  Asynchronous.  The step that follows construction in a
+ * CI run (repeated products with a vector, paper Sec. 1-2). */
+int ci_hamiltonian_spmv(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                        const float* val, const double* x, double* y, ci_stream stream);
+
+/* Lowest eigenvalue and eigenvector of H (full CSR as above) for problem
+ * `prob` by the Lanczos method with full reorthogonalization (every new
+ * vector is projected out of all earlier ones twice).  x0: device FP64 [D]
+ * start vector (any nonzero vector).  Stops when the lowest Ritz value moves
+ * by at most tol * max(1, |E|) between iterations, or after max_iter (1..4096)
+ * iterations.  Outputs: *eval (host), *iters (host), evec (device FP64 [D],
+ * unit norm).  work: device scratch of ci_lanczos_work_bytes(D, max_iter)
+ * bytes.  Synchronizes the stream (the tridiagonal problem is solved on the
+ * host each iteration).  CI_EINVAL for a zero start vector or bad sizes,
+ * CI_ESPACE for a short work buffer. */
+int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+               const float* val, const double* x0, int32_t max_iter, double tol, double* eval,
+               int32_t* iters, double* evec, void* work, size_t work_bytes, ci_stream stream);
+
+/* Bytes of work for ci_lanczos: (max_iter + 1) vectors of D doubles plus small buffers. */
+size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter);
+
 /* Bytes of work needed by ci_hamiltonian_vjp for this handle. */
 size_t ci_vjp_work_bytes(const ci_basis* b);
 

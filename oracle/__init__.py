@@ -63,6 +63,8 @@ def _load():
     L.orc_vget.argtypes = [vp, i32, i32, i32, i32]
     L.orc_row_counts.argtypes = [vp, vp, i64, vp]
     L.orc_rows.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.orc_row_counts_full.argtypes = [vp, vp, i64, vp]
+    L.orc_rows_full.argtypes = [vp, vp, i64, vp, vp, vp]
     L.orc_element.restype = dbl
     L.orc_element.argtypes = [vp, i64, i64]
     L.orc_grad_rows.argtypes = [vp, vp, i64, vp, vp]
@@ -182,6 +184,23 @@ class Oracle:
                              _ptr(vals) if values else None)
         return counts, cols[:tot], (vals[:tot] if values else None)
 
+    def rows_full(self, rows, values: bool = True):
+        """Like rows(), for the full symmetric matrix (every column of the row)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        counts = np.zeros(len(rows), np.int64)
+        if len(rows):
+            _load().orc_row_counts_full(self._h, _ptr(rows), len(rows), _ptr(counts))
+        offs = np.zeros(len(rows), np.int64)
+        if len(rows):
+            offs[1:] = np.cumsum(counts)[:-1]
+        tot = int(counts.sum())
+        cols = np.zeros(max(tot, 1), np.int32)
+        vals = np.zeros(max(tot, 1), np.float64) if values else None
+        if len(rows):
+            _load().orc_rows_full(self._h, _ptr(rows), len(rows), _ptr(offs), _ptr(cols),
+                                  _ptr(vals) if values else None)
+        return counts, cols[:tot], (vals[:tot] if values else None)
+
     def csr(self, values: bool = True):
         """Full upper-triangle CSR (row_ptr int64[D+1], col int32, val float64)."""
         counts, cols, vals = self.rows(np.arange(self.dim), values)
@@ -199,6 +218,24 @@ class Oracle:
         g = np.zeros(max(self.n_tbme, 1), np.float64)
         _load().orc_grad_rows(self._h, _ptr(rows), len(rows), _ptr(G), _ptr(g))
         return g[: self.n_tbme]
+
+    def lowest_eigenpair(self):
+        """Lowest eigenvalue and a unit eigenvector of the full symmetric H:
+        the plain definition, numpy's dense symmetric eigensolver on dense()
+        (tiny bases only)."""
+        w, v = np.linalg.eigh(self.dense())
+        return float(w[0]), v[:, 0].copy()
+
+    def hellmann_feynman(self, psi) -> np.ndarray:
+        """dE/dV for the eigenvalue E = psi^T H psi of unit eigenvector psi:
+        the gradient of the sum over the stored (upper) entries with upstream
+        value psi_i psi_j, doubled off the diagonal (each off-diagonal entry
+        stands for two matrix elements)."""
+        rows = np.arange(self.dim)
+        counts, cols, _ = self.rows(rows, values=False)
+        ri = np.repeat(rows, counts)
+        G = psi[ri] * psi[cols] * np.where(ri == cols, 1.0, 2.0)
+        return self.grad_rows(rows, G)
 
     def dense(self) -> np.ndarray:
         """Full symmetric matrix (tiny bases only)."""

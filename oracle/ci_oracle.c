@@ -676,6 +676,37 @@ void orc_rows(void* h, const int64_t* rows, int64_t nrows, const int64_t* offs, 
     }
 }
 
+/* The same for the full symmetric matrix: every column j (both triangles)
+ * with at most two nucleons different, ascending; the elements below the
+ * diagonal are computed directly (row i, column j < i), not copied. */
+void orc_row_counts_full(void* h, const int64_t* rows, int64_t nrows, int64_t* counts)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t n = 0;
+        for (int64_t j = 0; j < c->D; j++)
+            if (ndiff(c, rows[r], j) <= 2) n++;
+        counts[r] = n;
+    }
+}
+
+void orc_rows_full(void* h, const int64_t* rows, int64_t nrows, const int64_t* offs, int32_t* cols,
+                   double* vals)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t i = rows[r], o = offs[r];
+        for (int64_t j = 0; j < c->D; j++) {
+            if (ndiff(c, i, j) > 2) continue;
+            cols[o] = (int32_t)j;
+            if (vals) vals[o] = element(c, i, j, NULL, 0.0);
+            o++;
+        }
+    }
+}
+
 /* Lower-triangle element <Phi_j|H|Phi_i> computed with the roles swapped:
  * used to check that the matrix is symmetric. */
 double orc_element(void* h, int64_t i, int64_t j)

@@ -67,6 +67,8 @@ class ci_tuning(ctypes.Structure):
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
+           "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
+           "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
@@ -92,6 +94,13 @@ def load_library():
     L.ci_hamiltonian_count.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.ci_hamiltonian_count_full.argtypes = [vp, vp, vp, vp]
+    L.ci_hamiltonian_fill_full.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.ci_hamiltonian_spmv.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.ci_lanczos.argtypes = [vp, i32, vp, vp, vp, vp, i32, ctypes.c_double, P(ctypes.c_double), P(i32), vp, vp,
+                             sz, vp]
+    L.ci_lanczos_work_bytes.argtypes = [i64, i32]
+    L.ci_lanczos_work_bytes.restype = sz
     L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
     L.ci_basis_get_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_basis_set_tuning.argtypes = [vp, P(ci_tuning)]
@@ -103,7 +112,8 @@ def load_library():
     L.ci_basis_get_info.argtypes = [vp, i32, P(ci_basis_info)]
     L.ci_basis_states.argtypes = [vp, i32, vp, vp]
     for name in EXPORTS:
-        if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count"):
+        if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count",
+                        "ci_lanczos_work_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -239,6 +249,66 @@ def ci_hamiltonian_count(basis: Basis, stream=None):
                                                nnz.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
     basis.nnz = [int(x) for x in nnz]
     return row_ptr, basis.nnz
+
+
+def ci_hamiltonian_count_full(basis: Basis, stream=None):
+    """Count pass of the full symmetric matrix: (row_ptr, nnz list per basis)."""
+    torch = _torch()
+    row_ptr = torch.empty(basis.n_rowptr, dtype=torch.int64, device=basis.device)
+    nnz = np.zeros(basis.n_probs, np.int64)
+    _check(load_library().ci_hamiltonian_count_full(basis.handle, _ptr(row_ptr),
+                                                    nnz.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+    basis.nnz_full = [int(x) for x in nnz]
+    return row_ptr, basis.nnz_full
+
+
+def ci_hamiltonian_fill_full(basis: Basis, tbme, row_ptr, col=None, val=None, stream=None):
+    """Fill pass of the full symmetric matrix: (col int32, val float32)."""
+    torch = _torch()
+    tot = sum(basis.nnz_full)
+    _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    if col is None:
+        col = torch.empty(tot, dtype=torch.int32, device=basis.device)
+    if val is None:
+        val = torch.empty(tot, dtype=torch.float32, device=basis.device)
+    _check_tensor(col, torch.int32, tot, "col")
+    _check_tensor(val, torch.float32, tot, "val")
+    _check(load_library().ci_hamiltonian_fill_full(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                                   _stream_ptr(stream)))
+    return col, val
+
+
+def ci_hamiltonian_spmv(basis: Basis, prob: int, row_ptr, col, val, x, y=None, stream=None):
+    """y = H x (float64) for problem `prob`, H in full CSR form."""
+    torch = _torch()
+    D = basis.info[prob]["dim"]
+    _check_tensor(x, torch.float64, D, "x")
+    if y is None:
+        y = torch.empty(D, dtype=torch.float64, device=basis.device)
+    _check_tensor(y, torch.float64, D, "y")
+    _check(load_library().ci_hamiltonian_spmv(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x),
+                                              _ptr(y), _stream_ptr(stream)))
+    return y
+
+
+def ci_lanczos(basis: Basis, prob: int, row_ptr, col, val, x0=None, max_iter: int = 200, tol: float = 1e-12,
+               stream=None):
+    """Lowest eigenpair of H (full CSR): (eigenvalue, eigenvector float64 tensor, iterations)."""
+    torch = _torch()
+    D = basis.info[prob]["dim"]
+    if x0 is None:
+        x0 = torch.ones(D, dtype=torch.float64, device=basis.device)
+    _check_tensor(x0, torch.float64, D, "x0")
+    L = load_library()
+    nwork = int(L.ci_lanczos_work_bytes(D, int(max_iter)))
+    work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
+    evec = torch.empty(D, dtype=torch.float64, device=basis.device)
+    ev, it = ctypes.c_double(), ctypes.c_int32()
+    _check(L.ci_lanczos(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x0), int(max_iter),
+                        float(tol), ctypes.byref(ev), ctypes.byref(it), _ptr(evec), _ptr(work),
+                        work.numel(), _stream_ptr(stream)))
+    return ev.value, evec, it.value
 
 
 def _check_tensor(t, dtype, n, name):

@@ -16,12 +16,12 @@
 namespace ci {
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
-                        const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+                        const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
 hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_t* last, int64_t* nnz,
                       int n, hipStream_t s);
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+                       const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
 hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
                       int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
                       const float* gval, float* gtbme, double* gacc, int64_t ntbme, const ci_tuning& t,
@@ -31,6 +31,11 @@ hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
 hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hipStream_t s);
 hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps, double* steps_per_s);
+hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
+                       int64_t nrows, hipStream_t s);
+size_t lanczos_work_bytes(int64_t dim, int max_iter);
+hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
+                       int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
 }  // namespace ci
 
 using namespace ci;
@@ -596,13 +601,12 @@ int ci_basis_get_info(const ci_basis* b, int32_t prob, ci_basis_info* info)
     return CI_OK;
 }
 
-int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int full, hipStream_t s)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
-    hipStream_t s = (hipStream_t)stream;
     const int n = (int)b->info.size();
     hipError_t e = launch_count(b->d_bases, n, b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, b->d_seg_first,
-                                b->d_scan_tmp, b->tune, b->d_queue, s);
+                                b->d_scan_tmp, b->tune, b->d_queue, full, s);
     if (e != hipSuccess) return hip_fail(e, "count launch");
     e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
     if (e != hipSuccess) return hip_fail(e, "nnz launch");
@@ -613,14 +617,36 @@ int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_s
     return CI_OK;
 }
 
-int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
-                        float* val, ci_stream stream)
+static int fill_impl(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
+                     int full, hipStream_t s)
 {
     if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     hipError_t e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr,
-                               b->n_rowptr, col, val, b->tune, b->d_queue, (hipStream_t)stream);
+                               b->n_rowptr, col, val, b->tune, b->d_queue, full, s);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     return CI_OK;
+}
+
+int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    return count_impl(b, row_ptr, nnz, 0, (hipStream_t)stream);
+}
+
+int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                        float* val, ci_stream stream)
+{
+    return fill_impl(b, tbme, row_ptr, col, val, 0, (hipStream_t)stream);
+}
+
+int ci_hamiltonian_count_full(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    return count_impl(b, row_ptr, nnz, 1, (hipStream_t)stream);
+}
+
+int ci_hamiltonian_fill_full(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                             float* val, ci_stream stream)
+{
+    return fill_impl(b, tbme, row_ptr, col, val, 1, (hipStream_t)stream);
 }
 
 // Number of adjoint tiles of the handle for shape t (the device computes the
@@ -719,7 +745,7 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
             b->tune.row_grab = grab;
             float ms = 0.0f;
             rc = time_ms([&] { return launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme,
-                                                  row_ptr, b->n_rowptr, col, val, b->tune, b->d_queue, s); },
+                                                  row_ptr, b->n_rowptr, col, val, b->tune, b->d_queue, 0, s); },
                          reps, s, e0, e1, &ms);
             if (rc == CI_OK && (!have || ms < best_ms)) {
                 best_ms = ms;
@@ -759,10 +785,49 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     remember_tuning(b->probs, best);
     // leave col / val / grad_tbme as the chosen shapes compute them
     e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
-                    val, b->tune, b->d_queue, s);
+                    val, b->tune, b->d_queue, 0, s);
     if (e == hipSuccess) e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "autotune final run");
+    return CI_OK;
+}
+
+int ci_hamiltonian_spmv(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                        const float* val, const double* x, double* y, ci_stream stream)
+{
+    if (!b || !row_ptr || !x || !y) return fail(CI_EINVAL, "null pointer");
+    if (prob < 0 || prob >= (int32_t)b->info.size()) return fail(CI_EINVAL, "problem index out of range");
+    const ci_basis_info& I = b->info[prob];
+    if (I.dim > 0 && (!col || !val)) return fail(CI_EINVAL, "null pointer");
+    hipError_t e = launch_spmv(row_ptr + I.row_ptr_offset, col, val, x, y, I.dim, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spmv launch");
+    return CI_OK;
+}
+
+size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter)
+{
+    return (dim > 0 && max_iter > 0) ? lanczos_work_bytes(dim, max_iter) : 0;
+}
+
+int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
+               const double* x0, int32_t max_iter, double tol, double* eval, int32_t* iters, double* evec,
+               void* work, size_t work_bytes, ci_stream stream)
+{
+    if (!b || !row_ptr || !col || !val || !x0 || !eval || !iters || !evec || !work)
+        return fail(CI_EINVAL, "null pointer");
+    if (prob < 0 || prob >= (int32_t)b->info.size()) return fail(CI_EINVAL, "problem index out of range");
+    if (max_iter < 1 || max_iter > 4096 || !(tol >= 0.0)) return fail(CI_EINVAL, "max_iter in 1..4096, tol >= 0");
+    const ci_basis_info& I = b->info[prob];
+    if (I.dim < 1) return fail(CI_EINVAL, "empty basis");
+    if (work_bytes < lanczos_work_bytes(I.dim, max_iter))
+        return fail(CI_ESPACE, "Lanczos work buffer needs " + std::to_string(lanczos_work_bytes(I.dim, max_iter)) +
+                                   " bytes");
+    int it = 0;
+    hipError_t e = run_lanczos(row_ptr + I.row_ptr_offset, col, val, I.dim, x0, max_iter, tol, eval, &it, evec, work,
+                               (hipStream_t)stream);
+    if (e == hipErrorInvalidValue) return fail(CI_EINVAL, "start vector is zero");
+    if (e != hipSuccess) return hip_fail(e, "lanczos");
+    *iters = it;
     return CI_OK;
 }
 

@@ -233,6 +233,7 @@ struct RowView {
     int64_t pos0;  // first entry of the row
     int64_t cap;   // end of all entries (no access at or beyond)
     int Z, NN;     // particles
+    bool full;     // both triangles (every column), not only j >= i
     double spe_sum;
 };
 
@@ -437,7 +438,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
 
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
-    for (int w0 = bi; w0 < B.nblk; w0 += 64) {
+    for (int w0 = R.full ? 0 : bi; w0 < B.nblk; w0 += 64) {
         // 1. lane t: target block w0 + t of the window: proton partners of P,
         //    the row's neutron partners, column base
         const int b2 = w0 + lane;
@@ -454,13 +455,13 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             bstr = bk.w;  // |Kn'|
             bn1 = sN1[kn2];
             bl1 = sN1[kn2 + 1] - bn1;
-            bn12 = sN12[kn2] + (b2 == bi ? self12 : 0);  // diagonal block: N' >= N
+            bn12 = sN12[kn2] + (b2 == bi && !R.full ? self12 : 0);  // diagonal block: N' >= N
             bl12 = sN12[kn2 + 1] - bn12;
             // a block with another neutron key needs a neutron partner of N in it
             // (d <= 1 for a moved proton, d <= 2 for P' = P): otherwise every
             // segment of the block is empty
             if (!same_n && bl1 == 0 && (kp2 != kp || bl12 == 0)) np = 0;
-            if (MODE == kCount && b2 != bi) {
+            if (MODE == kCount && (b2 != bi || R.full)) {
                 // entries of a block other than the row's own, from the per-key
                 // counts: P' = P gives bl12, every one-proton move bl1, every
                 // two-proton move (same neutron key only) one entry
@@ -497,7 +498,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                 pr = t_bp < 0 ? P12[q] : P1[q];
                 const int dp = rec_d(pr), ipp = rec_local(pr);
                 sc = t_col + ipp * t_str;
-                if (w0 + t == bi && ipp < ip) {
+                if (w0 + t == bi && ipp < ip && !R.full) {
                     len = 0;  // lower triangle
                 } else if (dp == 2) {
                     len = 1;  // two protons moved: N' = N
@@ -591,7 +592,7 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
                                            double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, WaveLds& L);
+                                           bool use_table, bool full, WaveLds& L);
 
 // Row grow of the batch (rows of all bases are numbered consecutively) on the
 // calling wavefront.
@@ -601,7 +602,8 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
                                         const float* __restrict__ tbme, int64_t* __restrict__ row_ptr,
                                         int64_t nrp, int32_t* __restrict__ col, float* __restrict__ val,
                                         const float* __restrict__ gval, double* __restrict__ gacc,
-                                        lptr<uint32_t> hkey, lptr<float> hval, bool use_table, WaveLds& L)
+                                        lptr<uint32_t> hkey, lptr<float> hval, bool use_table, bool full,
+                                        WaveLds& L)
 {
     // basis of the row (few bases: linear search)
     int b = 0;
@@ -619,7 +621,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
     }
     const int bi = uniform(lo);
     run_row_at<MODE>(B, bi, i, i - (int)blk_off[bi], tbme, row_ptr, nrp, col, val, gval, gacc, hkey, hval, use_table,
-                     L);
+                     full, L);
 }
 
 // Row i of basis B, row r of its block bi.
@@ -628,7 +630,7 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
                                            double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, WaveLds& L)
+                                           bool use_table, bool full, WaveLds& L)
 {
     RowView R;
     R.B = &B;
@@ -644,6 +646,7 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
     R.Z = B.Z;
     R.NN = B.NN;
     R.spe_sum = 0.0;
+    R.full = full;
     if (MODE == kCount) {
         R.pos0 = 0;
         R.cap = 0;
@@ -663,7 +666,8 @@ template <int MODE, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
     row_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
                int64_t nrows, const float* __restrict__ tbme, int64_t* __restrict__ row_ptr, int64_t nrp,
-               int32_t* __restrict__ col, float* __restrict__ val, int grab, unsigned long long* __restrict__ queue)
+               int32_t* __restrict__ col, float* __restrict__ val, int grab, unsigned long long* __restrict__ queue,
+               int full)
 {
     __shared__ WaveLds lds[WAVES];
     const int wid = uniform(threadIdx.x >> 6);
@@ -671,7 +675,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t grow = (int64_t)blockIdx.x * WAVES + wid;
         if (grow < nrows)
             run_row<MODE>(bases, nb, basis_row0, grow, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, false, lds[wid]);
+                          nullptr, false, full != 0, lds[wid]);
         return;
     }
     for (;;) {
@@ -684,7 +688,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t g1 = g0 + grab < nrows ? g0 + grab : nrows;
         for (int64_t g = g0; g < g1; g++)
             run_row<MODE>(bases, nb, basis_row0, g, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, false, lds[wid]);
+                          nullptr, false, full != 0, lds[wid]);
     }
 }
 
@@ -813,7 +817,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
             const int r = (ip0 + u) * nKn + in0 + v;
             run_row_at<kAdjoint>(B, bi, uniform((int)cst(B.blk_off)[bi] + r), r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
                                  nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval,
-                                 use_table != 0, lds[wid]);
+                                 use_table != 0, false, lds[wid]);
         }
         __syncthreads();
         if (use_table) {
@@ -979,7 +983,7 @@ static unsigned resident_blocks(const void* kernel, int threads, int kind)
 template <int MODE, int WAVES>
 static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                           const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, int grab,
-                          unsigned long long* queue, hipStream_t s)
+                          unsigned long long* queue, int full, hipStream_t s)
 {
     unsigned grid = grid_for(nrows, WAVES);
     if (grab > 0) {
@@ -990,28 +994,30 @@ static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_ro
         grid = res < need ? res : need;
     }
     hipLaunchKernelGGL((row_kernel<MODE, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, bases, nb, basis_row0,
-                       nrows, tbme, row_ptr, nrp, col, val, grab, queue);
+                       nrows, tbme, row_ptr, nrp, col, val, grab, queue, full);
 }
 
 template <int MODE>
 static hipError_t launch_rows(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                               const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                              const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+                              const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
     if (t.row_waves == 8)
-        launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, s);
+        launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, full,
+                               s);
     else
-        launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, s);
+        launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, full,
+                               s);
     return hipGetLastError();
 }
 
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
-                        const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+                        const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
     hipError_t e = launch_rows<kCount>(bases, nb, basis_row0, nrows, nullptr, row_ptr, nrp, nullptr, nullptr, t,
-                                       queue, s);
+                                       queue, full, s);
     if (e != hipSuccess) return e;
     // the first slot of each basis' segment holds 0 before the scan, so the
     // inclusive scan leaves there the number of entries of the bases before it
@@ -1028,10 +1034,10 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
 
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+                       const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
     return launch_rows<kFill>(bases, nb, basis_row0, nrows, tbme, const_cast<int64_t*>(row_ptr), nrp, col, val, t,
-                              queue, s);
+                              queue, full, s);
 }
 
 hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,

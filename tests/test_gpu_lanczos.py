@@ -1,0 +1,200 @@
+"""Full symmetric CSR, H x and the lowest eigenpair (Lanczos) on the GPU
+against the FP64 oracle, through the C ABI.
+
+Parity bar: full-matrix structure bit-exact, values and products within 1e-5
+relative (max norm); the Lanczos eigenvalue within 1e-5 relative of the
+oracle's dense eigensolver on the same (FP32-rounded) two-body table, the
+eigenvector overlap within 1e-6 of 1; the Hellmann-Feynman gradient (adjoint of
+the fill with upstream psi_i psi_j) within 1e-4 of the oracle's.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "structure.json")
+SMALL = [(2, 2, 2, 0, 1), (1, 1, 2, 0, 1), (2, 1, 2, 1, 1), (1, 2, 2, -1, -1), (2, 0, 4, 0, 1),
+         (0, 3, 2, 1, 1), (3, 2, 2, 1, 1), (2, 2, 0, 0, 1), (2, 2, 4, 0, 1), (3, 3, 2, 0, 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ci():
+    import torch
+
+    import paper_1412_5989_amd as lib
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    lib.load_library()
+    return lib
+
+
+def oracle_for(p, seed):
+    o = Oracle(Problem(*p))
+    o.set_tbme(si.tbme_f32(seed, o.n_tbme).astype(np.float64))
+    return o
+
+
+def full_matrix(ci, p, seed):
+    import torch
+
+    b = ci.ci_basis_build([p])
+    rp, nnz = ci.ci_hamiltonian_count_full(b)
+    tb = torch.from_numpy(si.tbme_f32(seed, b.n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian_fill_full(b, tb, rp)
+    torch.cuda.synchronize()
+    return b, rp, col, val, tb
+
+
+def rel(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)) if ref.size else 0.0
+
+
+@pytest.mark.parametrize("p", SMALL)
+def test_full_csr_small(ci, p):
+    say("full csr", p)
+    b, rp, col, val, _ = full_matrix(ci, p, 21)
+    o = oracle_for(p, 21)
+    counts, cols, vals = o.rows_full(np.arange(o.dim))
+    r = rp.cpu().numpy()
+    assert np.array_equal(np.diff(r), counts)
+    assert np.array_equal(col.cpu().numpy(), cols)
+    assert rel(val.cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+
+
+@pytest.mark.parametrize("name", ["li6_nmax6", "b10_nmax4"])
+def test_full_csr_workloads_sampled(ci, name):
+    w = si.WORKLOADS[name]
+    with open(GOLDEN) as f:
+        gold = json.load(f)[name]
+    say("full csr", name)
+    b, rp, col, val, _ = full_matrix(ci, w["problem"], w["tbme_seed"])
+    D = b.info[0]["dim"]
+    assert b.nnz_full[0] == 2 * gold["nnz"] - D
+    o = oracle_for(w["problem"], w["tbme_seed"])
+    rows = si.sample_rows(D, 120, seed=31)
+    counts, cols, vals = o.rows_full(rows)
+    r = rp.cpu().numpy()
+    assert np.array_equal(r[rows + 1] - r[rows], counts)
+    import torch
+
+    pos = torch.from_numpy(np.concatenate([np.arange(r[i], r[i + 1]) for i in rows])).cuda()
+    assert np.array_equal(col[pos].cpu().numpy(), cols)
+    assert rel(val[pos].cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1)])
+def test_spmv_small(ci, p):
+    import torch
+
+    b, rp, col, val, _ = full_matrix(ci, p, 22)
+    o = oracle_for(p, 22)
+    x = np.random.default_rng(5).standard_normal(o.dim)
+    y = ci.ci_hamiltonian_spmv(b, 0, rp, col, val, torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), o.dense() @ x) <= VAL_TOL
+
+
+def test_spmv_li6_sampled(ci):
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp, col, val, _ = full_matrix(ci, w["problem"], w["tbme_seed"])
+    D = b.info[0]["dim"]
+    x = np.random.default_rng(6).standard_normal(D)
+    y = ci.ci_hamiltonian_spmv(b, 0, rp, col, val, torch.from_numpy(x).cuda()).cpu().numpy()
+    o = oracle_for(w["problem"], w["tbme_seed"])
+    rows = si.sample_rows(D, 100, seed=32)
+    counts, cols, vals = o.rows_full(rows)
+    ref = np.add.reduceat(vals * x[cols], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    assert rel(y[rows], ref) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1), (3, 3, 2, 0, 1), (1, 1, 4, 2, 1)])
+def test_lanczos_small(ci, p):
+    b, rp, col, val, _ = full_matrix(ci, p, 23)
+    o = oracle_for(p, 23)
+    E_ref, v_ref = o.lowest_eigenpair()
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    say("lanczos", p, "D", o.dim, "iters", it, "E", E, "ref", E_ref)
+    v = v.cpu().numpy()
+    assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
+    assert abs(np.linalg.norm(v) - 1.0) <= 1e-10
+    assert abs(float(v @ v_ref)) >= 1.0 - 1e-6
+
+
+def test_lanczos_li6(ci):
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp, col, val, _ = full_matrix(ci, w["problem"], w["tbme_seed"])
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-12)
+    Hv = ci.ci_hamiltonian_spmv(b, 0, rp, col, val, v)
+    torch.cuda.synchronize()
+    r = float(torch.linalg.norm(Hv - E * v))
+    diag_min = None
+    # the diagonal entries of the full CSR (column == row)
+    D = b.info[0]["dim"]
+    rows = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp))
+    diag_min = float(val[col.long() == rows].min())
+    say("lanczos li6 iters", it, "E", E, "residual", r, "min diagonal", diag_min)
+    assert r <= 1e-5 * abs(E)
+    assert E == pytest.approx(float(v @ Hv), rel=1e-12)
+    assert E < diag_min  # variational bound
+
+
+def upper_G(ci, b, psi):
+    """Upstream values psi_i psi_j on the stored (upper) entries, doubled off the diagonal."""
+    import torch
+
+    rp_u, nnz = ci.ci_hamiltonian_count(b)
+    D = b.info[0]["dim"]
+    # columns of the upper CSR come from a fill with any table
+    col_u, _ = ci.ci_hamiltonian_fill(b, torch.zeros(b.n_tbme, device="cuda"), rp_u)
+    rows = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp_u))
+    c = col_u.long()
+    G = (psi[rows] * psi[c] * torch.where(rows == c, 1.0, 2.0).double()).float()
+    return rp_u, G
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1)])
+def test_hellmann_feynman_gradient(ci, p):
+    # the eigenvalue's gradient with respect to the two-body table, from the
+    # GPU eigenvector and the GPU adjoint, against the oracle's (dense
+    # eigensolver + FP64 adjoint) and against central differences of the GPU
+    # eigenvalue itself
+    import torch
+
+    b, rp, col, val, tb = full_matrix(ci, p, 24)
+    E, psi, _ = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    rp_u, G = upper_G(ci, b, psi)
+    g = ci.ci_hamiltonian_vjp(b, rp_u, G).cpu().numpy().astype(np.float64)
+    o = oracle_for(p, 24)
+    E_ref, psi_ref = o.lowest_eigenpair()
+    g_ref = o.hellmann_feynman(psi_ref)
+    scale = np.abs(g_ref).max()
+    say("hellmann-feynman", p, "max err / scale", np.abs(g - g_ref).max() / scale)
+    assert np.abs(g - g_ref).max() <= 1e-4 * scale
+    keys = np.random.default_rng(11).choice(b.n_tbme, size=8, replace=False)
+    h = 1e-2
+    for k in keys:
+        Es = []
+        for sgn in (1, -1):
+            t2 = tb.clone()
+            t2[int(k)] += sgn * h
+            col2, val2 = ci.ci_hamiltonian_fill_full(b, t2, rp)
+            Es.append(ci.ci_lanczos(b, 0, rp, col2, val2, max_iter=300, tol=1e-13)[0])
+        fd = (Es[0] - Es[1]) / (2 * h)
+        assert abs(fd - g[k]) <= 2e-2 * scale, (k, fd, g[k])

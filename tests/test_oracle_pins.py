@@ -394,3 +394,87 @@ def test_gradient_row_subset_is_additive():
         Gc = np.concatenate([G[off[i]:off[i + 1]] for i in chunk])
         parts += o.grad_rows(chunk, Gc)
     np.testing.assert_allclose(parts, full, rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------------------ full matrix and lowest eigenpair
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (1, 1, 4, 2, 1), (0, 3, 2, 1, 1)])
+def test_full_rows_are_upper_rows_plus_transposed_entries(p):
+    o = Oracle(Problem(*p))
+    o.set_tbme(si.tbme_f64(7, o.n_tbme))
+    rows = np.arange(o.dim)
+    cu, colu, valu = o.rows(rows)
+    cf, colf, valf = o.rows_full(rows)
+    assert int(cf.sum()) == 2 * int(cu.sum()) - o.dim
+    # upper part of each full row is exactly the stored row
+    ru = np.repeat(rows, cu)
+    rf = np.repeat(rows, cf)
+    up = colf >= rf
+    assert np.array_equal(colf[up], colu) and np.array_equal(valf[up], valu)
+    # lower part: row i, column j < i equals the stored entry (j, i), computed
+    # independently (roles swapped) -- symmetric to rounding
+    lower = {(int(j), int(i)): v for i, j, v in zip(rf[~up], colf[~up], valf[~up])}
+    stored = {(int(i), int(j)): v for i, j, v in zip(ru, colu, valu) if i != j}
+    assert lower.keys() == stored.keys()
+    assert max(abs(lower[k] - stored[k]) for k in stored) <= 1e-12 * max(1.0, np.abs(valu).max())
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 3, 2, 0, 1), (2, 3, 2, 1, 1)])
+def test_lowest_eigenvalue_one_body_closed_form(p):
+    # with no two-body term H is diagonal: the lowest eigenvalue is the
+    # smallest single-particle sum, 15 (Nq_min + 3A/2) with Nq_min = N0 for a
+    # natural-parity space
+    o = Oracle(Problem(*p))
+    o.set_tbme(np.zeros(o.n_tbme))
+    E, v = o.lowest_eigenpair()
+    A = p[0] + p[1]
+
+    def n0(X):  # quanta of the lowest filling: shells of (N+1)(N+2) states from the bottom
+        s, N, left = 0, 0, X
+        while left > 0:
+            take = min(left, (N + 1) * (N + 2))
+            s, left, N = s + take * N, left - take, N + 1
+        return s
+
+    N0 = n0(p[0]) + n0(p[1])
+    nq_min = N0 if ((N0 % 2 == 0) == (p[4] == 1)) else N0 + 1
+    assert E == pytest.approx(15.0 * (nq_min + 1.5 * A), abs=1e-9)
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1)])
+def test_lowest_eigenpair_residual(p):
+    o = Oracle(Problem(*p))
+    o.set_tbme(si.tbme_f64(8, o.n_tbme))
+    H = o.dense()
+    E, v = o.lowest_eigenpair()
+    assert abs(np.linalg.norm(v) - 1.0) < 1e-12
+    assert np.linalg.norm(H @ v - E * v) <= 1e-10 * abs(E)
+    assert E == pytest.approx(float(v @ H @ v), rel=1e-13)
+    # variational: below every diagonal element
+    assert E <= H.diagonal().min() + 1e-9
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1)])
+def test_hellmann_feynman_matches_eigenvalue_differences(p):
+    # dE/dV_k from the adjoint with upstream psi_i psi_j (doubled off the
+    # diagonal) equals the central difference of the lowest eigenvalue
+    o = Oracle(Problem(*p))
+    V = si.tbme_f64(9, o.n_tbme)
+    o.set_tbme(V)
+    E, psi = o.lowest_eigenpair()
+    w, _ = np.linalg.eigh(o.dense())
+    assert w[1] - w[0] > 1e-3  # nondegenerate ground state
+    g = o.hellmann_feynman(psi)
+    keys = np.random.default_rng(10).choice(o.n_tbme, size=12, replace=False)
+    h = 1e-4
+    for k in keys:
+        Vp, Vm = V.copy(), V.copy()
+        Vp[k] += h
+        Vm[k] -= h
+        o.set_tbme(Vp)
+        Ep, _ = o.lowest_eigenpair()
+        o.set_tbme(Vm)
+        Em, _ = o.lowest_eigenpair()
+        assert (Ep - Em) / (2 * h) == pytest.approx(g[k], abs=1e-6 * max(1.0, np.abs(g).max()))
+    o.set_tbme(V)
