@@ -50,7 +50,7 @@ def _load():
     L = ctypes.CDLL(_LIB)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.orc_new.restype = vp
-    L.orc_new.argtypes = [i32, i32, i32, i32, i32, dbl]
+    L.orc_new.argtypes = [i32, i32, i32, i32, i32, dbl, i32]
     L.orc_free.argtypes = [vp]
     L.orc_info.argtypes = [vp, vp]
     L.orc_orbits.argtypes = [vp, vp]
@@ -84,6 +84,7 @@ class Problem:
     two_m: int
     parity: int = 1
     hw: float = HW_MEV
+    kinetic: int = 0  # 1: off-diagonal harmonic-oscillator kinetic elements in the one-body term
 
     def astuple(self):
         return (self.Z, self.N, self.nmax, self.two_m, self.parity)
@@ -95,7 +96,7 @@ class Oracle:
     def __init__(self, prob: Problem):
         self.prob = prob
         L = _load()
-        h = L.orc_new(prob.Z, prob.N, prob.nmax, prob.two_m, prob.parity, float(prob.hw))
+        h = L.orc_new(prob.Z, prob.N, prob.nmax, prob.two_m, prob.parity, float(prob.hw), int(prob.kinetic))
         if not h:
             raise ValueError("invalid problem %r" % (prob,))
         self._h = ctypes.c_void_p(h)

@@ -19,6 +19,7 @@ so that the two can be compared index by index.
 from __future__ import annotations
 
 import itertools
+import math
 
 import numpy as np
 
@@ -125,13 +126,43 @@ def _create(occ: tuple, a: int):
     return occ[:k] + (a,) + occ[k:], (-1) ** k
 
 
-def hamiltonian(basis: BruteBasis, keys: np.ndarray, values: np.ndarray) -> np.ndarray:
+def kinetic_offdiag(basis: BruteBasis, a: int, b: int) -> float:
+    """Harmonic-oscillator kinetic energy between orbits a != b (combined
+    index) of one species: nonzero only for the same (l, j, m) and radial
+    quantum numbers n, n + 1, where it is (hw/2) sqrt((n+1)(n+l+3/2))."""
+    if a == b or a // basis.nsps != b // basis.nsps:
+        return 0.0
+    Na, na, la, ja, ma = basis.orb[a % basis.nsps]
+    Nb, nb, lb, jb, mb = basis.orb[b % basis.nsps]
+    if (la, ja, ma) != (lb, jb, mb) or abs(na - nb) != 1:
+        return 0.0
+    n = min(na, nb)
+    return 0.5 * basis.hw * math.sqrt((n + 1) * (n + la + 1.5))
+
+
+def hamiltonian(basis: BruteBasis, keys: np.ndarray, values: np.ndarray, kinetic: bool = False) -> np.ndarray:
     """Dense <Phi_i|H|Phi_j> by operator application.
 
     `keys[t] = (a, b, c, d)` with a<b, c<d is the two-body table as a list of
-    canonical elements V_{ab,cd} = V_{cd,ab}; anything not listed is zero."""
+    canonical elements V_{ab,cd} = V_{cd,ab}; anything not listed is zero.
+    kinetic: add sum_{a != b} t_ab a+_a a_b (kinetic_offdiag)."""
     D = basis.dim
     H = np.zeros((D, D))
+    if kinetic:
+        norb = 2 * basis.nsps
+        for j, phi in enumerate(basis.states):
+            for b in phi:
+                x0, s1 = _annihilate(phi, b)
+                for a in range(norb):
+                    t = kinetic_offdiag(basis, a, b)
+                    if t == 0.0:
+                        continue
+                    x, s2 = _create(x0, a)
+                    if x is None:
+                        continue
+                    i = basis.index.get(x)
+                    if i is not None:
+                        H[i, j] += s1 * s2 * t
     # ket pair (c,d) -> list of (a, b, V_{ab,cd}); both orientations of each key
     by_ket = {}
     for (a, b, c, d), v in zip(map(tuple, keys), values):

@@ -22,6 +22,7 @@
  *   - every two-body element is found by binary search of the sorted key list.
  */
 #include <stdint.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -38,6 +39,7 @@ typedef struct {
 typedef struct {
     /* problem */
     int Z, NN, nmax, two_m, parity;
+    int kinetic; /* 1: off-diagonal harmonic-oscillator kinetic elements in the one-body term */
     double hw;
     /* orbits */
     int S, nsps, W;
@@ -473,6 +475,21 @@ static int count_below(const int* L, int n, int v)
 /* Slater-Condon element <Phi_i | H | Phi_j> for d <= 2.  With gradient
  * output (g != NULL) it instead adds w * d<H_ij>/dV_k into g[k] for every
  * two-body term, and returns 0. */
+/* Off-diagonal one-body element t_ab between combined orbits a != b of one
+ * species: the harmonic-oscillator kinetic energy connects radial quantum
+ * numbers n and n + 1 of the same (l, j, m), with <n+1 l|T|n l> =
+ * (hw/2) sqrt((n+1)(n+l+3/2)) (radial functions positive near the origin);
+ * everything else is 0. */
+static double onebody_offdiag(const orc_ctx* c, int a, int b)
+{
+    if (!c->kinetic || a == b || (a < c->nsps) != (b < c->nsps)) return 0.0;
+    const orc_orbit *oa = corb(c, a), *ob = corb(c, b);
+    if (oa->l != ob->l || oa->j2 != ob->j2 || oa->m2 != ob->m2) return 0.0;
+    int lo = oa->n < ob->n ? oa->n : ob->n, hi = oa->n < ob->n ? ob->n : oa->n;
+    if (hi != lo + 1) return 0.0;
+    return 0.5 * c->hw * sqrt((double)(lo + 1) * (lo + oa->l + 1.5));
+}
+
 static double element(const orc_ctx* c, int64_t i, int64_t j, double* g, double w)
 {
     int oi[2 * 64 * ORC_MAXW], oj[2 * 64 * ORC_MAXW];
@@ -514,6 +531,7 @@ static double element(const orc_ctx* c, int64_t i, int64_t j, double* g, double 
                 v += Vget(c, p[0], kk, h[0], kk);
             }
         }
+        if (!g) v += onebody_offdiag(c, p[0], h[0]);  /* a+_p a_h: the same phase */
         return g ? 0.0 : sg * v;
     }
     /* nh == 2: h[], p[] are ascending because the lists are */
@@ -546,12 +564,14 @@ static void ctx_free(orc_ctx* c)
 }
 
 /* Returns NULL for an invalid problem. */
-void* orc_new(int Z, int N, int nmax, int two_m, int parity, double hw)
+void* orc_new(int Z, int N, int nmax, int two_m, int parity, double hw, int kinetic)
 {
     if (Z < 0 || N < 0 || Z + N == 0 || nmax < 0 || (parity != 1 && parity != -1)) return NULL;
+    if (kinetic != 0 && kinetic != 1) return NULL;
     if (((two_m + Z + N) % 2 + 2) % 2 != 0) return NULL;
     orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     c->Z = Z; c->NN = N; c->nmax = nmax; c->two_m = two_m; c->parity = parity; c->hw = hw;
+    c->kinetic = kinetic;
     int tz = ntop(Z), tn = ntop(N);
     c->S = (tz > tn ? tz : tn) + nmax;
     c->nsps = make_orbits(c->S, NULL);

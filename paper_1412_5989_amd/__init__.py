@@ -40,7 +40,7 @@ class CIError(RuntimeError):
 
 class ci_problem(ctypes.Structure):
     _fields_ = [("Z", ctypes.c_int32), ("N", ctypes.c_int32), ("nmax", ctypes.c_int32),
-                ("two_m", ctypes.c_int32), ("parity", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("two_m", ctypes.c_int32), ("parity", ctypes.c_int32), ("kinetic", ctypes.c_int32),
                 ("hw_mev", ctypes.c_double)]
 
 
@@ -133,7 +133,8 @@ def _problems(problems) -> Tuple[ctypes.Array, int]:
         Z, N, nmax, two_m = (int(x) for x in p[:4])
         parity = int(p[4]) if len(p) > 4 else 1
         hw = float(p[5]) if len(p) > 5 else HW_MEV
-        arr[k] = ci_problem(Z, N, nmax, two_m, parity, 0, hw)
+        kinetic = int(p[6]) if len(p) > 6 else 0
+        arr[k] = ci_problem(Z, N, nmax, two_m, parity, kinetic, hw)
     return arr, len(ps)
 
 

@@ -99,9 +99,9 @@ struct Layout {
     size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
-using Key = std::tuple<int, int, int, int, int, double>;
+using Key = std::tuple<int, int, int, int, int, double, int>;
 
-Key key_of(const ci_problem& p) { return Key(p.Z, p.N, p.nmax, p.two_m, p.parity, p.hw_mev); }
+Key key_of(const ci_problem& p) { return Key(p.Z, p.N, p.nmax, p.two_m, p.parity, p.hw_mev, p.kinetic); }
 
 void fill_info(const HostBasis& hb, ci_basis_info& in)
 {
@@ -126,7 +126,7 @@ struct SpOff {
 };
 struct UOff {
     SpOff sp[2];
-    size_t blk_kp, blk_kn, blk_off, blk, pair, orb_n, totals;
+    size_t blk_kp, blk_kn, blk_off, blk, pair, orb_n, orb_qn, totals;
     size_t bytes;
 };
 
@@ -168,12 +168,12 @@ extern "C" {
 // Process-wide cache of tuned launch shapes, keyed by the problem list.
 namespace {
 std::mutex g_tune_mu;
-std::map<std::vector<std::tuple<int, int, int, int, int, double>>, ci_tuning> g_tune;
+std::map<std::vector<std::tuple<int, int, int, int, int, double, int>>, ci_tuning> g_tune;
 
-std::vector<std::tuple<int, int, int, int, int, double>> tune_key(const std::vector<ci_problem>& p)
+std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std::vector<ci_problem>& p)
 {
-    std::vector<std::tuple<int, int, int, int, int, double>> k;
-    for (const ci_problem& q : p) k.emplace_back(q.Z, q.N, q.nmax, q.two_m, q.parity, q.hw_mev);
+    std::vector<std::tuple<int, int, int, int, int, double, int>> k;
+    for (const ci_problem& q : p) k.emplace_back(q.Z, q.N, q.nmax, q.two_m, q.parity, q.hw_mev, q.kinetic);
     return k;
 }
 
@@ -300,6 +300,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
         uo[u].blk = L.take<BlockInfo>(hb.blk_kp.size());
         uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
+        uo[u].orb_qn = L.take<int32_t>(hb.orb_n.size());
         ubytes[u] += L.off - s0;
     }
     const size_t o_row0 = L.take<int64_t>(n_probs + 1);
@@ -399,6 +400,12 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             }
         }
         put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
+        {
+            int32_t* q = (int32_t*)(mirror + uo[u].orb_qn);
+            for (int o = 0; o < hb.nsps; o++)
+                q[o] = ((hb.orb_n[o] - hb.orb_l[o]) / 2) | (hb.orb_l[o] << 8) | (hb.orb_j2[o] << 16) |
+                       ((hb.orb_m2[o] + 64) << 24);
+        }
     }
     std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
     R = 0;
@@ -542,6 +549,8 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.blk = (const BlockInfo*)D(uo[u].blk);
         d.pair = (const uint64_t*)D(uo[u].pair);
         d.orb_n = (const int32_t*)D(uo[u].orb_n);
+        d.orb_qn = (const int32_t*)D(uo[u].orb_qn);
+        d.kinetic = hb.prob.kinetic;
         d.dim = hb.dim;
         d.row0 = R;
         d.tbme0 = T;

@@ -77,10 +77,12 @@ struct BasisDev {
     const int64_t* blk_off;    // [nblk + 1] first row of each block
     const uint64_t* pair;      // [3][n][n] pp, pn, nn pair entries (species-local orbits)
     const int32_t* orb_n;      // [n] oscillator shell of each orbit
+    const int32_t* orb_qn;     // [n] n | l << 8 | 2j << 16 | (2m + 64) << 24 of each orbit
     int64_t dim;               // D
     int64_t row0;              // R_b: this basis' segment of row_ptr
     int64_t tbme0;             // T_b: this basis' slice of the two-body table
     int32_t W, nsps, nblk, nsec, Z, NN;
+    int32_t kinetic;           // off-diagonal oscillator kinetic term in the one-body part
     double hw;
 };
 

@@ -287,6 +287,10 @@ int validate_problem(const ci_problem& p, std::string& err)
         err = "two_m must have the parity of Z + N";
         return CI_EINVAL;
     }
+    if (p.kinetic != 0 && p.kinetic != 1) {
+        err = "kinetic must be 0 or 1";
+        return CI_EINVAL;
+    }
     if (!(p.hw_mev > 0.0) || p.hw_mev > 1e6) {
         err = "hw_mev must be a positive finite energy";
         return CI_EINVAL;

@@ -258,16 +258,39 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
     atomic_add_f64(glbw(R.gacc) + k, (double)g);
 }
 
-// number of two-body terms of a queued entry
+// number of terms of a queued entry: two-body terms, plus the one-body
+// kinetic term of a one-nucleon difference when the problem has it
 __device__ __forceinline__ int queued_terms(const RowView& R, uint32_t q)
 {
     const int A = R.Z + R.NN;
-    return q_kind(q) == 0 ? A * (A - 1) / 2 : A - 1;
+    return q_kind(q) == 0 ? A * (A - 1) / 2 : A - 1 + R.B->kinetic;
+}
+
+// Off-diagonal oscillator kinetic element between species-local orbits p != h:
+// (hw/2) sqrt((n+1)(n+l+3/2)) for radial quantum numbers n, n+1 of the same
+// (l, j, m), else 0.
+__device__ __forceinline__ double kinetic_offdiag(const BasisDev& B, int p, int h)
+{
+    const int qp = glb(B.orb_qn)[p], qh = glb(B.orb_qn)[h];
+    if ((qp >> 8) != (qh >> 8)) return 0.0;  // l, 2j, 2m differ
+    const int np = qp & 255, nh = qh & 255, l = (qp >> 8) & 255;
+    const int lo = np < nh ? np : nh, hi = np < nh ? nh : np;
+    if (hi != lo + 1) return 0.0;
+    return 0.5 * B.hw * sqrt((double)(lo + 1) * ((double)lo + l + 1.5));
 }
 
 // The u-th two-body term of a queued entry: table position and sign.
-__device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, uint32_t q, int u, bool* neg)
+// The u-th term: table position (or -1) and sign; *ob receives the one-body
+// value of the kinetic term (0 for two-body terms).
+__device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, uint32_t q, int u, bool* neg,
+                                           double* ob)
 {
+    *ob = 0.0;
+    if (q_kind(q) != 0 && u == R.Z + R.NN - 1) {  // the kinetic term a+_p a_h
+        *neg = q_neg(q);
+        *ob = kinetic_offdiag(*R.B, q_p(q), q_h(q));
+        return -1;
+    }
     const BasisDev& B = *R.B;
     const int Z = R.Z, NN = R.NN;
     const uint8_t* oP = L.occ;
@@ -334,6 +357,12 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
     for (int base = 0; base < qn; base += 64) {
         const int q = base + lane;
         const int t = q < qn ? queued_terms(R, L.qrec[q]) : 0;
+        if (MODE == kFill && q < qn && t == 0) {
+            // no terms (a single nucleon): the diagonal is its single-particle
+            // energy, a one-nucleon difference is 0
+            const int64_t p = R.pos0 + L.qpos[q];
+            if (p < R.cap) glbw(R.val)[p] = q_kind(L.qrec[q]) == 0 ? (float)R.spe_sum : 0.0f;
+        }
         const int incl = wave_incl_scan(t);
         if (q < kQueue) L.toff[q + 1] = tot + incl;
         if (lane == 0 && base == 0) L.toff[0] = 0;
@@ -350,7 +379,9 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
         if (act) {
             q = seg_search(L.toff, qn, t);
             bool neg;
-            const int k = queued_term(R, L, L.qrec[q], t - L.toff[q], &neg);
+            double ob;
+            const int k = queued_term(R, L, L.qrec[q], t - L.toff[q], &neg, &ob);
+            if (MODE == kFill && k < 0) v = neg ? -ob : ob;
             if (k >= 0) {
                 if (MODE == kFill) {
                     const double x = (double)glb(R.tbme)[k];

@@ -198,3 +198,22 @@ def test_hellmann_feynman_gradient(ci, p):
             Es.append(ci.ci_lanczos(b, 0, rp, col2, val2, max_iter=300, tol=1e-13)[0])
         fd = (Es[0] - Es[1]) / (2 * h)
         assert abs(fd - g[k]) <= 2e-2 * scale, (k, fd, g[k])
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (2, 2, 4, 0, 1)])
+def test_lanczos_with_kinetic_term(ci, p):
+    import torch
+
+    import paper_1412_5989_amd as lib
+
+    b = ci.ci_basis_build([p + (lib.HW_MEV, 1)])
+    rp, nnz = ci.ci_hamiltonian_count_full(b)
+    tb = si.tbme_f32(25, b.n_tbme)
+    col, val = ci.ci_hamiltonian_fill_full(b, torch.from_numpy(tb).cuda(), rp)
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    o = Oracle(Problem(*p, kinetic=1))
+    o.set_tbme(tb.astype(np.float64))
+    E_ref, v_ref = o.lowest_eigenpair()
+    say("lanczos kinetic", p, E, E_ref)
+    assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
+    assert abs(float(v.cpu().numpy() @ v_ref)) >= 1.0 - 1e-6

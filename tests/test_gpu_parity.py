@@ -448,3 +448,54 @@ def test_probe_ceilings(ci):
     say("ceilings", c)
     assert 500.0 < c["store_GBps"] < 8000.0 * 1.05
     assert 1e11 < c["xor_popcount_steps_per_s"] < 1e14
+
+
+# ------------------------------------------------------------------ off-diagonal kinetic one-body term
+
+KINETIC = [(2, 2, 2, 0, 1), (1, 1, 4, 2, 1), (2, 1, 4, 1, 1), (2, 2, 4, 0, 1), (1, 0, 6, 1, 1), (3, 3, 2, 0, 1)]
+
+
+@pytest.mark.parametrize("p", [(1, 0, 4, 1, 1), (0, 1, 6, -1, 1), (1, 0, 2, 1, -1)])
+def test_single_nucleon_full_matrix(ci, p):
+    # one nucleon: no two-body terms at all; the diagonal is the single-particle
+    # energy and one-nucleon differences are structural zeros
+    b, rp, col, val, tb = run_forward(ci, [p], [42])
+    o = Oracle(Problem(*p))
+    o.set_tbme(tb.astype(np.float64))
+    rpo, co, vo = o.csr()
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(col, co)
+    assert rel_err(val.astype(np.float64), vo) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", KINETIC)
+def test_kinetic_full_matrix(ci, p):
+    import torch
+
+    say("kinetic", p)
+    b = ci.ci_basis_build([p + (ci.HW_MEV, 1)])
+    rp, nnz = ci.ci_hamiltonian_count(b)
+    tb = si.tbme_f32(41, b.n_tbme)
+    col, val = ci.ci_hamiltonian_fill(b, torch.from_numpy(tb).cuda(), rp)
+    torch.cuda.synchronize()
+    o = Oracle(Problem(*p, kinetic=1))
+    o.set_tbme(tb.astype(np.float64))
+    rpo, co, vo = o.csr()
+    assert np.array_equal(rp.cpu().numpy(), rpo)
+    assert np.array_equal(col.cpu().numpy(), co)
+    assert rel_err(val.cpu().numpy().astype(np.float64), vo) <= VAL_TOL
+
+
+def test_kinetic_leaves_the_adjoint_unchanged(ci):
+    import torch
+
+    p = (2, 2, 4, 0, 1)
+    b0, b1 = ci.ci_basis_build([p]), ci.ci_basis_build([p + (ci.HW_MEV, 1)])
+    rp0, nnz0 = ci.ci_hamiltonian_count(b0)
+    rp1, nnz1 = ci.ci_hamiltonian_count(b1)
+    assert nnz0 == nnz1 and torch.equal(rp0, rp1)
+    G = torch.rand(nnz0[0], device="cuda") - 0.5
+    g0 = ci.ci_hamiltonian_vjp(b0, rp0, G)
+    g1 = ci.ci_hamiltonian_vjp(b1, rp1, G)
+    torch.cuda.synchronize()
+    assert float((g0 - g1).abs().max()) <= GRAD_TOL * float(g0.abs().max())

@@ -102,3 +102,12 @@ def test_argument_errors_before_any_device_call():
     assert L.ci_hamiltonian_vjp(None, None, None, None, None, 0, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_count(None, None, None, None) == ci.CI_EINVAL
     assert L.ci_vjp_work_bytes(None) == 0 and L.ci_basis_count(None) == 0
+
+
+def test_kinetic_flag_validation():
+    with pytest.raises(ci.CIError) as e:
+        ci.ci_basis_plan([(2, 2, 2, 0, 1, ci.HW_MEV, 2)])
+    assert e.value.code == ci.CI_EINVAL
+    a = ci.ci_basis_plan([(2, 2, 2, 0, 1, ci.HW_MEV, 1)])[0]
+    b = ci.ci_basis_plan([(2, 2, 2, 0, 1)])[0]
+    assert a == b  # the one-body term changes values, not sizes

@@ -478,3 +478,76 @@ def test_hellmann_feynman_matches_eigenvalue_differences(p):
         Em, _ = o.lowest_eigenpair()
         assert (Ep - Em) / (2 * h) == pytest.approx(g[k], abs=1e-6 * max(1.0, np.abs(g).max()))
     o.set_tbme(V)
+
+
+# ------------------------------------------------------------------ off-diagonal kinetic one-body term
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (1, 1, 4, 2, 1), (3, 2, 2, 1, 1), (2, 1, 4, 1, 1), (0, 3, 2, 1, 1),
+                               (2, 2, 4, 0, 1)])
+def test_kinetic_matrix_equals_operator_application(p):
+    o = Oracle(Problem(*p, kinetic=1))
+    v = si.tbme_f64(12, o.n_tbme)
+    o.set_tbme(v)
+    H = o.dense()
+    Hb = brute.hamiltonian(brute.BruteBasis(*p), o.tbme_keys(), v, kinetic=True)
+    assert np.abs(H - Hb).max() <= 1e-12 * max(1.0, np.abs(Hb).max())
+    # the term changes the matrix where the space holds states two quanta
+    # apart (a radial excitation n -> n + 1); otherwise it must vanish
+    o0 = Oracle(Problem(*p))
+    o0.set_tbme(v)
+    words = o.states()
+    nq = set()
+    orbs = brute.orbits(o.shell_max)
+    for row in words:
+        q = 0
+        for sp in range(2):
+            for w in range(o.n_words):
+                x = int(row[sp * o.n_words + w])
+                while x:
+                    b = (x & -x).bit_length() - 1
+                    x &= x - 1
+                    q += orbs[w * 64 + b][0]
+        nq.add(q)
+    if len(nq) > 1:
+        assert np.abs(H - o0.dense()).max() > 1.0
+    else:
+        assert np.abs(H - o0.dense()).max() == 0.0
+
+
+def test_kinetic_single_nucleon_closed_form():
+    # one proton: the matrix is the one-body operator itself on the allowed
+    # orbits, (N + 3/2) hw on the diagonal and (hw/2) sqrt((n+1)(n+l+3/2))
+    # between radial quantum numbers n, n+1 of the same (l, j, m)
+    p = (1, 0, 4, 1, 1)
+    o = Oracle(Problem(*p, kinetic=1))
+    o.set_tbme(np.zeros(o.n_tbme))
+    H = o.dense()
+    orbs = brute.orbits(o.shell_max)
+    states = [a for a, (N, n, l, j2, m2) in enumerate(orbs) if m2 == 1 and N % 2 == 0 and N <= 4]
+    assert o.dim == len(states)
+    T = np.zeros((o.dim, o.dim))
+    for x, a in enumerate(states):
+        for y, b in enumerate(states):
+            Na, na, la, ja, ma = orbs[a]
+            Nb, nb, lb, jb, mb = orbs[b]
+            if a == b:
+                T[x, y] = (Na + 1.5) * 15.0
+            elif (la, ja, ma) == (lb, jb, mb) and abs(na - nb) == 1:
+                n = min(na, nb)
+                T[x, y] = 7.5 * np.sqrt((n + 1) * (n + la + 1.5))
+    # the basis order of one proton is the orbit order (colex of one bit)
+    assert np.abs(H - T).max() <= 1e-12
+
+
+def test_kinetic_leaves_the_gradient_unchanged():
+    # the one-body term does not depend on the two-body table
+    p = (3, 2, 2, 1, 1)
+    o1, o0 = Oracle(Problem(*p, kinetic=1)), Oracle(Problem(*p))
+    v = si.tbme_f64(13, o1.n_tbme)
+    o1.set_tbme(v)
+    o0.set_tbme(v)
+    rows = np.arange(o1.dim)
+    counts, cols, _ = o1.rows(rows, values=False)
+    G = np.random.default_rng(3).standard_normal(int(counts.sum()))
+    assert np.array_equal(o1.grad_rows(rows, G), o0.grad_rows(rows, G))
