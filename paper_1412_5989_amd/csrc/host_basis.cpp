@@ -168,8 +168,21 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
                 }
         const int nk = sp.nk();
         sp.key_off.assign(nk + 1, 0);
-        for (int k = 0; k < nk; k++)
-            sp.key_off[k + 1] = sp.key_off[k] + present[s][cell(sp.key_nq[k], sp.key_m2[k])];
+        int64_t tot = 0;
+        for (int k = 0; k < nk; k++) {
+            const int64_t n = present[s][cell(sp.key_nq[k], sp.key_m2[k])];
+            // partner records hold a determinant's position in its key in 24 bits
+            if (n > (int64_t)kRecLocalMask + 1) {
+                err = "a species key holds more than 2^24 determinants";
+                return CI_EUNSUPPORTED;
+            }
+            tot += n;
+            if (tot >= ((int64_t)1 << 31)) {
+                err = "more than 2^31 determinants of one species";
+                return CI_EUNSUPPORTED;
+            }
+            sp.key_off[k + 1] = (int32_t)tot;
+        }
         const int W = hb.W;
         sp.sd.resize((size_t)sp.key_off[nk] * W);
         sp.sd_key.resize(sp.key_off[nk]);
