@@ -158,6 +158,42 @@ def run_lanczos(ci, torch, prob, tbme_seed):
             "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E}
 
 
+def run_threebody(ci, torch, n1max=6, n3max=6):
+    """The paper's own GPU kernel: coupled-JT -> m-scheme three-body
+    elements on request, timed per chunk of requests (the chunk-size knee)."""
+    import seeded_inputs as si
+
+    t = ci.ThreeBody(n1max, n3max)
+    A = torch.from_numpy(np.random.default_rng(9).standard_normal(t.n_coupled).astype(np.float32)).cuda()
+    req = si.requests_3b(91, 100000, n1max, n3max)
+    big = torch.from_numpy(np.ascontiguousarray(np.tile(req, (10, 1)))).cuda()
+    out = torch.empty(big.shape[0], dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    rates = {}
+    for n in (1000, 10000, 100000, 1000000):
+        r, o = big[:n], out[:n]
+        t.decouple(A, r, o)
+        ev = EventTimer(torch, stream)
+        for _ in range(5):
+            with ev:
+                t.decouple(A, r, o)
+        rates[str(n)] = n / (ev.mean_ms() * 1e-3)
+    # the oracle (plain Python sums) on a sample of the same requests, one core
+    from oracle.threebody import ThreeBody as OracleTB
+
+    o3 = OracleTB(n1max, n3max)
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < 5.0 and k < len(req):
+        o3.element(req[k], lambda *key: 1.0)
+        k += 1
+    cpu = k / (time.perf_counter() - t0)
+    t.free()
+    return {"workload": "three-body decoupling, shells 0..%d, triples inside %d" % (n1max, n3max),
+            "n_coupled": t.n_coupled, "requests_per_s_by_chunk": rates,
+            "cpu_oracle_requests_per_s": cpu, "cpu_oracle_cores": 1, "cpu_oracle_sample": k}
+
+
 def run_batched(ci, torch, steps, warmup):
     """64 bases in one handle; fill + vjp captured in one HIP graph."""
     import seeded_inputs as si
@@ -367,6 +403,8 @@ def main():
     }
     log("lanczos")
     res["lanczos"] = run_lanczos(ci, torch, prob, w["tbme_seed"])
+    log("three-body")
+    res["threebody"] = run_threebody(ci, torch)
     if not args.no_batched:
         log("batched")
         res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)

@@ -214,6 +214,46 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t);
 int ci_basis_set_tuning(ci_basis* b, const ci_tuning* t);
 
+/* ---- Three-body basis transformation (paper Sec. 3, the paper's own GPU
+ * kernel): m-scheme elements of a three-body interaction, decoupled on request
+ * from its coupled-JT form.
+ *
+ * Coupled basis: ordered triples (a, b, c) of oscillator orbitals (n, l, j) of
+ * shells 0..n1max with N_a + N_b + N_c <= n3max, coupled as ((j_a j_b) J_ab,
+ * j_c) J and ((1/2 1/2) T_ab, 1/2) T.  The input ("coupled", device FP32,
+ * n_coupled values) holds one dense block per (bra triple, ket triple, J, T)
+ * of equal parity, over channels (J_ab, T_ab) x (J_de, T_de); ci_threebody_keys
+ * lists, per element in storage order, (t, t', 2J, 2T, 2J_ab, 2T_ab, 2J_de,
+ * 2T_de).  A request is six int32 m-scheme orbits a b c d e f (orbit k of the
+ * n_sps m-orbits of shells 0..n1max, ordered by N, l, 2j, 2m as for the basis;
+ * proton k -> k, neutron k -> n_sps + k; isospin projection +1/2 for a
+ * proton); its value is <abc|V|def> for the product states coupled in the
+ * order (ab)c: the sum over J_ab, J_de, J, T_ab, T_de, T of the bra and ket
+ * Clebsch-Gordan coefficients times the coupled element.  0 when M, M_T or
+ * parity differ, when a triple lies beyond n3max, or for an index outside
+ * [0, 2 n_sps). */
+typedef struct ci_threebody ci_threebody; /* opaque: the layout and its device tables */
+
+/* Host only: the sizes of the layout (same checks as ci_threebody_build). */
+int ci_threebody_plan(int32_t n1max, int32_t n3max, int64_t* n_coupled, int32_t* n_triples);
+
+/* Builds the layout and its device tables (one allocation, one copy).
+ * CI_EINVAL unless 0 <= n1max <= 12 and 0 <= n3max <= 3 n1max;
+ * CI_EUNSUPPORTED for more than 8192 triples. */
+int ci_threebody_build(int32_t n1max, int32_t n3max, ci_threebody** out);
+void ci_threebody_free(ci_threebody* t);
+int ci_threebody_info(const ci_threebody* t, int64_t* n_coupled, int32_t* n_sps, int32_t* n_nlj,
+                      int32_t* n_triples);
+/* Host: keys [n_coupled][8] int32 (room for cap rows, else CI_ESPACE). */
+int ci_threebody_keys(const ci_threebody* t, int32_t* keys, int64_t cap);
+/* Host: nlj [n_nlj][3] = (N, l, 2j); morb [n_sps][2] = (orbital, 2m);
+ * triples [n_triples][3] = orbitals (a, b, c). */
+int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, int32_t* triples);
+/* out[r] (device FP32) = element of request r (device int32 [n][6]); one
+ * request per lane, FP64 sums.  Asynchronous. */
+int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,
+                          float* out, ci_stream stream);
+
 /* Machine ceilings measured on the current device (the roofline of the
  * construction kernels): streaming-store bandwidth over buf (device, caller
  * owned, at least 64 MiB; overwritten) in GB/s, and the rate of 64-bit

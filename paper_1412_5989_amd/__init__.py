@@ -70,6 +70,8 @@ EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "
            "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
            "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
+           "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
+           "ci_threebody_orbitals", "ci_threebody_decouple",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
 _lib = None
@@ -105,6 +107,14 @@ def load_library():
     L.ci_basis_get_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_basis_set_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_probe_ceilings.argtypes = [vp, sz, P(ctypes.c_double), P(ctypes.c_double), vp]
+    L.ci_threebody_plan.argtypes = [i32, i32, P(i64), P(i32)]
+    L.ci_threebody_build.argtypes = [i32, i32, P(vp)]
+    L.ci_threebody_free.argtypes = [vp]
+    L.ci_threebody_free.restype = None
+    L.ci_threebody_info.argtypes = [vp, P(i64), P(i32), P(i32), P(i32)]
+    L.ci_threebody_keys.argtypes = [vp, vp, i64]
+    L.ci_threebody_orbitals.argtypes = [vp, vp, vp, vp]
+    L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp]
     L.ci_vjp_work_bytes.argtypes = [vp]
     L.ci_vjp_work_bytes.restype = sz
     L.ci_basis_count.argtypes = [vp]
@@ -113,7 +123,7 @@ def load_library():
     L.ci_basis_states.argtypes = [vp, i32, vp, vp]
     for name in EXPORTS:
         if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count",
-                        "ci_lanczos_work_bytes"):
+                        "ci_lanczos_work_bytes", "ci_threebody_free"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -386,6 +396,65 @@ def ci_probe_ceilings(mib: int = 1024, stream=None) -> dict:
     _check(load_library().ci_probe_ceilings(_ptr(buf), buf.numel(), ctypes.byref(gbs), ctypes.byref(steps),
                                             _stream_ptr(stream)))
     return {"store_GBps": gbs.value, "xor_popcount_steps_per_s": steps.value, "store_bytes": int(mib) << 20}
+
+
+def ci_threebody_plan(n1max: int, n3max: int) -> dict:
+    """Sizes of the three-body layout (host only)."""
+    n, t = ctypes.c_int64(), ctypes.c_int32()
+    _check(load_library().ci_threebody_plan(int(n1max), int(n3max), ctypes.byref(n), ctypes.byref(t)))
+    return {"n_coupled": n.value, "n_triples": t.value}
+
+
+class ThreeBody:
+    """Three-body layout (coupled-JT input order, device tables) of shells
+    0..n1max with triples inside n3max."""
+
+    def __init__(self, n1max: int, n3max: int):
+        _torch()
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.ci_threebody_build(int(n1max), int(n3max), ctypes.byref(h)))
+        self._h = h
+        nc, ns, nn, nt = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.ci_threebody_info(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(nn), ctypes.byref(nt)))
+        self.n_coupled, self.n_sps, self.n_nlj, self.n_triples = nc.value, ns.value, nn.value, nt.value
+        self.nlj = np.zeros((self.n_nlj, 3), np.int32)
+        self.morb = np.zeros((self.n_sps, 2), np.int32)
+        self.triples = np.zeros((max(self.n_triples, 1), 3), np.int32)
+        _check(L.ci_threebody_orbitals(h, self.nlj.ctypes.data_as(ctypes.c_void_p),
+                                       self.morb.ctypes.data_as(ctypes.c_void_p),
+                                       self.triples.ctypes.data_as(ctypes.c_void_p)))
+
+    def keys(self) -> np.ndarray:
+        """[n_coupled, 8] int32: (t, t', 2J, 2T, 2J_ab, 2T_ab, 2J_de, 2T_de) in storage order."""
+        out = np.zeros((max(self.n_coupled, 1), 8), np.int32)
+        _check(load_library().ci_threebody_keys(self._h, out.ctypes.data_as(ctypes.c_void_p), self.n_coupled))
+        return out[: self.n_coupled]
+
+    def decouple(self, coupled, requests, out=None, stream=None):
+        """m-scheme elements (float32 device tensor) of requests (int32 [n, 6] device tensor)."""
+        torch = _torch()
+        _check_tensor(coupled, torch.float32, self.n_coupled, "coupled")
+        if requests.dtype != torch.int32 or not requests.is_cuda or not requests.is_contiguous():
+            raise ValueError("requests must be a contiguous int32 CUDA tensor [n, 6]")
+        n = requests.numel() // 6
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=coupled.device)
+        _check_tensor(out, torch.float32, n, "out")
+        _check(load_library().ci_threebody_decouple(self._h, _ptr(coupled), _ptr(requests), n, _ptr(out),
+                                                    _stream_ptr(stream)))
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ci_threebody_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def _make_autograd():

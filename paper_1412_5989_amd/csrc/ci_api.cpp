@@ -33,6 +33,10 @@ hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hi
 hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps, double* steps_per_s);
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
+hipError_t threebody_upload(ThreeBodyHost& h);
+void threebody_release(ThreeBodyHost& h);
+hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, float* out,
+                           hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
@@ -837,6 +841,83 @@ int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const in
     if (e == hipErrorInvalidValue) return fail(CI_EINVAL, "start vector is zero");
     if (e != hipSuccess) return hip_fail(e, "lanczos");
     *iters = it;
+    return CI_OK;
+}
+
+struct ci_threebody {
+    ThreeBodyHost h;
+    ~ci_threebody() { threebody_release(h); }
+};
+
+int ci_threebody_plan(int32_t n1max, int32_t n3max, int64_t* n_coupled, int32_t* n_triples)
+{
+    if (!n_coupled || !n_triples) return fail(CI_EINVAL, "null pointer");
+    ThreeBodyHost h;
+    std::string err;
+    const int rc = threebody_plan(n1max, n3max, h, err);
+    if (rc != CI_OK) return fail(rc, err);
+    *n_coupled = h.n_coupled;
+    *n_triples = (int32_t)(h.trip.size() / 3);
+    return CI_OK;
+}
+
+int ci_threebody_build(int32_t n1max, int32_t n3max, ci_threebody** out)
+{
+    if (!out) return fail(CI_EINVAL, "null pointer");
+    *out = nullptr;
+    std::unique_ptr<ci_threebody> t(new ci_threebody());
+    std::string err;
+    const int rc = threebody_plan(n1max, n3max, t->h, err);
+    if (rc != CI_OK) return fail(rc, err);
+    hipError_t e = threebody_upload(t->h);
+    if (e != hipSuccess) return hip_fail(e, "three-body tables");
+    *out = t.release();
+    return CI_OK;
+}
+
+void ci_threebody_free(ci_threebody* t) { delete t; }
+
+int ci_threebody_info(const ci_threebody* t, int64_t* n_coupled, int32_t* n_sps, int32_t* n_nlj, int32_t* n_triples)
+{
+    if (!t || !n_coupled || !n_sps || !n_nlj || !n_triples) return fail(CI_EINVAL, "null pointer");
+    *n_coupled = t->h.n_coupled;
+    *n_sps = (int32_t)t->h.orb_alpha.size();
+    *n_nlj = (int32_t)t->h.nlj_j2.size();
+    *n_triples = (int32_t)(t->h.trip.size() / 3);
+    return CI_OK;
+}
+
+int ci_threebody_keys(const ci_threebody* t, int32_t* keys, int64_t cap)
+{
+    if (!t || (!keys && cap > 0)) return fail(CI_EINVAL, "null pointer");
+    if (cap < t->h.n_coupled) return fail(CI_ESPACE, "need room for " + std::to_string(t->h.n_coupled) + " keys");
+    threebody_keys(t->h, keys);
+    return CI_OK;
+}
+
+int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, int32_t* triples)
+{
+    if (!t || !nlj || !morb || !triples) return fail(CI_EINVAL, "null pointer");
+    const ThreeBodyHost& h = t->h;
+    for (size_t a = 0; a < h.nlj_j2.size(); a++) {
+        nlj[3 * a] = h.nlj_N[a];
+        nlj[3 * a + 1] = h.nlj_l[a];
+        nlj[3 * a + 2] = h.nlj_j2[a];
+    }
+    for (size_t o = 0; o < h.orb_alpha.size(); o++) {
+        morb[2 * o] = h.orb_alpha[o];
+        morb[2 * o + 1] = h.orb_m2[o];
+    }
+    std::memcpy(triples, h.trip.data(), h.trip.size() * sizeof(int32_t));
+    return CI_OK;
+}
+
+int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,
+                          float* out, ci_stream stream)
+{
+    if (!t || n < 0 || (n > 0 && (!coupled || !requests || !out))) return fail(CI_EINVAL, "null pointer");
+    hipError_t e = launch_decouple(t->h, coupled, requests, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "decouple launch");
     return CI_OK;
 }
 

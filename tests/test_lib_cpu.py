@@ -111,3 +111,35 @@ def test_kinetic_flag_validation():
     a = ci.ci_basis_plan([(2, 2, 2, 0, 1, ci.HW_MEV, 1)])[0]
     b = ci.ci_basis_plan([(2, 2, 2, 0, 1)])[0]
     assert a == b  # the one-body term changes values, not sizes
+
+
+@pytest.mark.parametrize("n1,n3", [(2, 2), (3, 3), (4, 4)])
+def test_threebody_layout_size_matches_the_oracle_count(n1, n3):
+    # the coupled input holds one block per equal-parity triple pair and (J, T)
+    # over the channels of both triples: count them from the oracle's channels
+    from oracle.threebody import ThreeBody, channels
+
+    tb = ThreeBody(n1, n3)
+    nlj = tb.nlj
+    T = [(a, b, c) for a in range(len(nlj)) for b in range(len(nlj)) for c in range(len(nlj))
+         if nlj[a][0] + nlj[b][0] + nlj[c][0] <= n3]
+    par = [(nlj[a][1] + nlj[b][1] + nlj[c][1]) % 2 for a, b, c in T]
+    ch = []
+    for t in T:
+        j = [nlj[x][2] for x in t]
+        ch.append({(J, TT): len(channels(j[0], j[1], j[2], J, TT)) for J in range(1, sum(j) + 1, 2) for TT in (1, 3)})
+    tot = 0
+    for x in range(len(T)):
+        for y in range(len(T)):
+            if par[x] == par[y]:
+                tot += sum(n * ch[y].get(k, 0) for k, n in ch[x].items())
+    plan = ci.ci_threebody_plan(n1, n3)
+    assert plan["n_triples"] == len(T)
+    assert plan["n_coupled"] == tot
+
+
+def test_threebody_plan_validation():
+    for bad in ((-1, 0), (13, 3), (2, 7)):
+        with pytest.raises(ci.CIError) as e:
+            ci.ci_threebody_plan(*bad)
+        assert e.value.code == ci.CI_EINVAL
