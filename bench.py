@@ -158,7 +158,32 @@ def run_lanczos(ci, torch, prob, tbme_seed):
             "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E}
 
 
-def run_threebody(ci, torch, n1max=6, n3max=6):
+def threebody_block_elements(t, req):
+    """Coupled elements each request depends on: the (J, T) blocks of its
+    triple pair with |M| <= J and |M_T| <= T, nb x nk elements each
+    (the row of D^T, block of A, column of D of paper Sec. 3.1)."""
+    q = req % t.n_sps
+    j = t.nlj[t.morb[q, 0], 2].astype(np.int64)
+    m = t.morb[q, 1].astype(np.int64)
+    tz = np.where(req >= t.n_sps, -1, 1)
+    M, MT = np.abs(m[:, :3].sum(1)), np.abs(tz[:, :3].sum(1))
+    Jmax = np.minimum(j[:, :3].sum(1), j[:, 3:].sum(1))
+
+    def njab(a, b, c, J):
+        lo = np.maximum(np.abs(a - b), np.abs(J - c))
+        hi = np.minimum(a + b, J + c)
+        return np.where(hi >= lo, (hi - lo) // 2 + 1, 0)
+
+    total = np.zeros(len(req), np.int64)
+    for J in range(1, int(Jmax.max()) + 1, 2):
+        nb = njab(j[:, 0], j[:, 1], j[:, 2], J)
+        nk = njab(j[:, 3], j[:, 4], j[:, 5], J)
+        live = (J <= Jmax) & (M <= J)
+        total += np.where(live & (MT <= 1), nb * nk * 4, 0) + np.where(live, nb * nk, 0)
+    return total
+
+
+def run_threebody(ci, torch, with_oracle, n1max=6, n3max=6):
     """The paper's own GPU kernel: coupled-JT -> m-scheme three-body
     elements on request, timed per chunk of requests (the chunk-size knee)."""
     import seeded_inputs as si
@@ -166,10 +191,11 @@ def run_threebody(ci, torch, n1max=6, n3max=6):
     t = ci.ThreeBody(n1max, n3max)
     A = torch.from_numpy(np.random.default_rng(9).standard_normal(t.n_coupled).astype(np.float32)).cuda()
     req = si.requests_3b(91, 100000, n1max, n3max)
+    elems = threebody_block_elements(t, req)
     big = torch.from_numpy(np.ascontiguousarray(np.tile(req, (10, 1)))).cuda()
     out = torch.empty(big.shape[0], dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-    rates = {}
+    rates, ms = {}, {}
     for n in (1000, 10000, 100000, 1000000):
         r, o = big[:n], out[:n]
         t.decouple(A, r, o)
@@ -177,21 +203,29 @@ def run_threebody(ci, torch, n1max=6, n3max=6):
         for _ in range(5):
             with ev:
                 t.decouple(A, r, o)
-        rates[str(n)] = n / (ev.mean_ms() * 1e-3)
-    # the oracle (plain Python sums) on a sample of the same requests, one core
-    from oracle.threebody import ThreeBody as OracleTB
+        ms[n] = ev.mean_ms()
+        rates[str(n)] = n / (ms[n] * 1e-3)
+    # algorithmic bytes of one launch of 1e6 requests: the block elements
+    # (4 B each), the request (24 B) and the result (4 B)
+    alg = 10 * (4 * int(elems.sum()) + 28 * len(req))
+    res = {"workload": "three-body decoupling, shells 0..%d, triples inside %d, random requests (1e5 distinct)"
+           % (n1max, n3max), "n_coupled": t.n_coupled, "requests_per_s_by_chunk": rates,
+           "block_elements_per_request": float(elems.mean()),
+           "ms_per_launch_1e6": ms[1000000], "alg_GBps_1e6": alg / (ms[1000000] * 1e-3) / 1e9}
+    if with_oracle:
+        # the oracle (plain Python sums) on a sample of the same requests, one core
+        from oracle.threebody import ThreeBody as OracleTB
 
-    o3 = OracleTB(n1max, n3max)
-    t0 = time.perf_counter()
-    k = 0
-    while time.perf_counter() - t0 < 5.0 and k < len(req):
-        o3.element(req[k], lambda *key: 1.0)
-        k += 1
-    cpu = k / (time.perf_counter() - t0)
+        o3 = OracleTB(n1max, n3max)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 5.0 and k < len(req):
+            o3.element(req[k], lambda *key: 1.0)
+            k += 1
+        res.update({"cpu_oracle_requests_per_s": k / (time.perf_counter() - t0), "cpu_oracle_cores": 1,
+                    "cpu_oracle_sample": "first %d requests" % k})
     t.free()
-    return {"workload": "three-body decoupling, shells 0..%d, triples inside %d" % (n1max, n3max),
-            "n_coupled": t.n_coupled, "requests_per_s_by_chunk": rates,
-            "cpu_oracle_requests_per_s": cpu, "cpu_oracle_cores": 1, "cpu_oracle_sample": k}
+    return res
 
 
 def run_batched(ci, torch, steps, warmup):
@@ -259,6 +293,9 @@ def main():
     ap.add_argument("--workload", default="li6_nmax6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-step", action="store_true",
+                    help="run only the timed construction steps (no ceiling probes, Lanczos, three-body or "
+                         "batched sections): for counter and trace runs of the step's kernels")
     ap.add_argument("--tuning", default=None, metavar="W,G,R,N,P",
                     help="fixed launch shapes row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent instead "
                          "of the autotuner (for profiling runs)")
@@ -392,6 +429,9 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if args.only_step:
+        print(json.dumps(res), flush=True)
+        return
     # measured machine ceilings (streaming stores; XOR + popcount issue rate)
     ceil = ci.ci_probe_ceilings(1024)
     res["measured_ceilings"] = {
@@ -404,7 +444,7 @@ def main():
     log("lanczos")
     res["lanczos"] = run_lanczos(ci, torch, prob, w["tbme_seed"])
     log("three-body")
-    res["threebody"] = run_threebody(ci, torch)
+    res["threebody"] = run_threebody(ci, torch, not args.no_cpu_baseline)
     if not args.no_batched:
         log("batched")
         res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)

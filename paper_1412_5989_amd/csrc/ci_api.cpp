@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ci_internal.h"
+#include "threebody.h"
 
 namespace ci {
 hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
@@ -33,10 +34,6 @@ hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hi
 hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps, double* steps_per_s);
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
-hipError_t threebody_upload(ThreeBodyHost& h);
-void threebody_release(ThreeBodyHost& h);
-hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, float* out,
-                           hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);

@@ -134,33 +134,6 @@ struct PartnerArgs {
     int32_t nsd, nk, W;
 };
 
-// threebody.hip: decoupling of a coupled-JT three-body interaction to m-scheme.
-struct ThreeBodyDev {
-    int32_t nsps, nlj, ntrip;
-    const int32_t* orb_alpha;  // [nsps] oscillator orbital (n l j) of each m-orbit
-    const int32_t* orb_m2;     // [nsps]
-    const int32_t* nlj_j2;     // [nlj]
-    const int32_t* nlj_l;      // [nlj]
-    const int32_t* tidx;       // [nlj^3] triple index, or -1 beyond n3max
-    const int32_t* trip;       // [ntrip][3] orbitals of each triple
-    const int64_t* block_off;  // [ntrip^2] first element of a triple pair, or -1 (parity differs)
-    const double* fact;        // factorials
-};
-
-struct ThreeBodyHost {
-    int n1max = 0, n3max = 0;
-    std::vector<int32_t> nlj_N, nlj_l, nlj_j2;  // oscillator orbitals (n l j)
-    std::vector<int32_t> orb_alpha, orb_m2;     // m-orbits of one species
-    std::vector<int32_t> tidx, trip;            // triples
-    std::vector<int64_t> block_off;             // [ntrip^2]
-    int64_t n_coupled = 0;
-    void* arena = nullptr;
-    ThreeBodyDev dev{};
-};
-
-int threebody_plan(int n1max, int n3max, ThreeBodyHost& h, std::string& err);
-void threebody_keys(const ThreeBodyHost& h, int32_t* keys);
-
 // host_basis.cpp
 int validate_problem(const ci_problem& p, std::string& err);
 // Host tables: orbits, species determinants, keys, blocks, table sectors and

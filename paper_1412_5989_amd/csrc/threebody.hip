@@ -16,6 +16,8 @@
 // Clebsch-Gordan coefficients of bra and ket times the coupled element; one
 // request per lane (paper Sec. 3.2: one element per thread; the loop bounds
 // depend on the request).  FP32 input, FP64 sums, FP32 output.
+#include "threebody.h"
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,61 +32,132 @@ namespace ci {
 
 namespace {
 
+__host__ __device__ __forceinline__ int iabs(int x) { return x < 0 ? -x : x; }
+
 __host__ __device__ __forceinline__ bool triangle2(int a2, int b2, int c2)
 {
-    const int d = a2 > b2 ? a2 - b2 : b2 - a2;
-    return d <= c2 && c2 <= a2 + b2 && ((a2 + b2 + c2) & 1) == 0;
+    return iabs(a2 - b2) <= c2 && c2 <= a2 + b2 && ((a2 + b2 + c2) & 1) == 0;
 }
 
-// <j1 m1 j2 m2 | J M> (all arguments doubled) by the Racah formula; fact[n] = n!
-__host__ __device__ double cg2(const double* fact, int j1, int m1, int j2, int m2, int J, int M)
+// Range of the intermediate J_ab (doubled, step 2) of a triple with orbit
+// spins ja, jb, jc coupled to J: J_ab runs over [|ja - jb|, ja + jb] and must
+// close a triangle with jc and J; returns the count, *lo the first value.
+__host__ __device__ __forceinline__ int jab_range(int ja, int jb, int jc, int J, int* lo)
 {
-    if (m1 + m2 != M) return 0.0;
-    if (m1 > j1 || -m1 > j1 || m2 > j2 || -m2 > j2 || M > J || -M > J) return 0.0;
-    if (((j1 + m1) & 1) || ((j2 + m2) & 1) || ((J + M) & 1) || !triangle2(j1, j2, J)) return 0.0;
-    const int a = (j1 + j2 - J) / 2, b = (j1 - j2 + J) / 2, c = (-j1 + j2 + J) / 2, d = (j1 + j2 + J) / 2 + 1;
-    const double pre = sqrt((double)(J + 1) * fact[a] * fact[b] * fact[c] / fact[d] * fact[(J + M) / 2] *
-                            fact[(J - M) / 2] * fact[(j1 - m1) / 2] * fact[(j1 + m1) / 2] * fact[(j2 - m2) / 2] *
-                            fact[(j2 + m2) / 2]);
-    const int e1 = (j1 - m1) / 2, e2 = (j2 + m2) / 2, e3 = (J - j2 + m1) / 2, e4 = (J - j1 - m2) / 2;
-    int kmin = 0;
-    if (-e3 > kmin) kmin = -e3;
-    if (-e4 > kmin) kmin = -e4;
-    int kmax = a;
-    if (e1 < kmax) kmax = e1;
-    if (e2 < kmax) kmax = e2;
-    double s = 0.0;
-    for (int k = kmin; k <= kmax; k++) {
-        const double t = 1.0 / (fact[k] * fact[a - k] * fact[e1 - k] * fact[e2 - k] * fact[e3 + k] * fact[e4 + k]);
-        s += (k & 1) ? -t : t;
-    }
-    return pre * s;
+    const int l = max(iabs(ja - jb), iabs(J - jc)), h = min(ja + jb, J + jc);
+    *lo = l;
+    return h >= l ? (h - l) / 2 + 1 : 0;
 }
 
-// number of channels (J_ab, T_ab) of a triple with orbit spins ja, jb, jc
-// (doubled) coupled to (J, T) (doubled)
+// (J_ab, T_ab) channels of the triple coupled to (J, T): T_ab in {0, 1} for
+// T = 1/2 and T_ab = 1 for T = 3/2, J_ab in its range, J_ab-major.
 __host__ __device__ __forceinline__ int n_channels(int ja, int jb, int jc, int J, int T)
 {
-    int n = 0;
-    const int lo = ja > jb ? ja - jb : jb - ja;
-    for (int jab = lo; jab <= ja + jb; jab += 2)
-        if (triangle2(jab, jc, J))
-            for (int tab = 0; tab <= 2; tab += 2)
-                if (triangle2(tab, 1, T)) n++;
-    return n;
+    int lo;
+    return jab_range(ja, jb, jc, J, &lo) * (T == 1 ? 2 : 1);
 }
 
-constexpr int kFact = 96;  // n! up to 95!, enough for n1max <= 12
-
-}  // namespace
-
-namespace {
-
-__global__ void __launch_bounds__(256) decouple_kernel(ThreeBodyDev T, const float* __restrict__ A,
-                                                       const int32_t* __restrict__ req, int64_t n,
-                                                       float* __restrict__ out)
+// <j1 m1 j2 m2 | J M> (doubled arguments) by the Racah formula, in long
+// double; host only, for the tables.
+double racah_cg(int j1, int m1, int j2, int m2, int J, int M)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m1 + m2 != M || iabs(m1) > j1 || iabs(m2) > j2 || iabs(M) > J) return 0.0;
+    if (((j1 + m1) & 1) || ((j2 + m2) & 1) || ((J + M) & 1) || !triangle2(j1, j2, J)) return 0.0;
+    static std::vector<long double> f;
+    if (f.empty()) {
+        f.assign(200, 1.0L);
+        for (int k = 1; k < 200; k++) f[k] = f[k - 1] * k;
+    }
+    const int a = (j1 + j2 - J) / 2, b = (j1 - j2 + J) / 2, c = (-j1 + j2 + J) / 2, d = (j1 + j2 + J) / 2 + 1;
+    const long double pre = sqrtl((long double)(J + 1) * f[a] * f[b] * f[c] / f[d] * f[(J + M) / 2] *
+                                  f[(J - M) / 2] * f[(j1 - m1) / 2] * f[(j1 + m1) / 2] * f[(j2 - m2) / 2] *
+                                  f[(j2 + m2) / 2]);
+    const int e1 = (j1 - m1) / 2, e2 = (j2 + m2) / 2, e3 = (J - j2 + m1) / 2, e4 = (J - j1 - m2) / 2;
+    const int kmin = std::max({0, -e3, -e4}), kmax = std::min({a, e1, e2});
+    long double sum = 0.0L;
+    for (int k = kmin; k <= kmax; k++) {
+        const long double t = 1.0L / (f[k] * f[a - k] * f[e1 - k] * f[e2 - k] * f[e3 + k] * f[e4 + k]);
+        sum += (k & 1) ? -t : t;
+    }
+    return (double)(pre * sum);
+}
+
+// table entry counts of one (j1, j2) pair
+int cg_block(int j1, int j2) { return (j1 + 1) * (j2 + 1) * (std::min(j1, j2) + 1); }
+
+void build_cg_tables(int nj, std::vector<int32_t>& off1, std::vector<float>& cg1, std::vector<int32_t>& off2,
+                     std::vector<float>& cg2)
+{
+    const int jmax = 2 * nj - 1;
+    off1.assign((size_t)nj * nj, 0);
+    cg1.clear();
+    for (int a = 0; a < nj; a++)
+        for (int b = 0; b < nj; b++) {
+            const int j1 = 2 * a + 1, j2 = 2 * b + 1, nJ = std::min(j1, j2) + 1;
+            off1[(size_t)a * nj + b] = (int32_t)cg1.size();
+            for (int m1 = -j1; m1 <= j1; m1 += 2)
+                for (int m2 = -j2; m2 <= j2; m2 += 2)
+                    for (int i = 0; i < nJ; i++)
+                        cg1.push_back((float)racah_cg(j1, m1, j2, m2, iabs(j1 - j2) + 2 * i, m1 + m2));
+        }
+    off2.assign((size_t)(jmax + 1) * nj, 0);
+    cg2.clear();
+    for (int A = 0; A <= jmax; A++)
+        for (int c = 0; c < nj; c++) {
+            const int J12 = 2 * A, j3 = 2 * c + 1, nJ = std::min(J12, j3) + 1;
+            off2[(size_t)A * nj + c] = (int32_t)cg2.size();
+            for (int M12 = -J12; M12 <= J12; M12 += 2)
+                for (int m3 = -j3; m3 <= j3; m3 += 2)
+                    for (int i = 0; i < nJ; i++)
+                        cg2.push_back((float)racah_cg(J12, M12, j3, m3, iabs(J12 - j3) + 2 * i, M12 + m3));
+        }
+}
+
+// <j1 m1 j2 m2 | J, m1 + m2> for odd j1, j2; J must close the triangle and
+// |m1 + m2| <= J must hold (the table index assumes both).
+__device__ __forceinline__ float cg_first(const ThreeBodyDev& T, int j1, int m1, int j2, int m2, int J)
+{
+    const int base = T.cg1_off[((j1 - 1) >> 1) * T.nj + ((j2 - 1) >> 1)];
+    return T.cg1[base + (((m1 + j1) >> 1) * (j2 + 1) + ((m2 + j2) >> 1)) * (min(j1, j2) + 1) + ((J - iabs(j1 - j2)) >> 1)];
+}
+
+// <J12 M12 j3 m3 | J, M12 + m3> for even J12, odd j3; |M12| <= J12 and the
+// triangle (J12, j3, J) must hold.
+__device__ __forceinline__ float cg_second(const ThreeBodyDev& T, int J12, int M12, int j3, int m3, int J)
+{
+    const int base = T.cg2_off[(J12 >> 1) * T.nj + ((j3 - 1) >> 1)];
+    return T.cg2[base + (((M12 + J12) >> 1) * (j3 + 1) + ((m3 + j3) >> 1)) * (min(J12, j3) + 1) +
+                 ((J - iabs(J12 - j3)) >> 1)];
+}
+
+// Isospin part of a triple's coefficient: <1/2 t1 1/2 t2 | T_ab, t1 + t2>
+// <T_ab, t1 + t2, 1/2 t3 | T, MT> for (T, T_ab) = (1/2, 0), (1/2, 1), (3/2, 1).
+__device__ __forceinline__ void iso_coeffs(const ThreeBodyDev& T, int t1, int t2, int t3, float c[3])
+{
+    const int MTab = t1 + t2;
+    const float c0 = MTab == 0 ? cg_first(T, 1, t1, 1, t2, 0) * cg_second(T, 0, 0, 1, t3, 1) : 0.0f;
+    const float c1 = cg_first(T, 1, t1, 1, t2, 2);
+    const int MT = MTab + t3;
+    c[0] = (MT == 1 || MT == -1) ? c0 : 0.0f;
+    c[1] = (MT == 1 || MT == -1) ? c1 * cg_second(T, 2, MTab, 1, t3, 1) : 0.0f;
+    c[2] = c1 * cg_second(T, 2, MTab, 1, t3, 3);
+}
+
+constexpr int kDecoupleThreads = 64;
+
+// One request per lane (paper Sec. 3.2: the loop bounds depend on the
+// request).  Per (J, T) block the bra coefficients that do not vanish are
+// compacted into this lane's LDS column (value, row); the ket loop then reads
+// only rows and columns with nonzero coefficients.
+__global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev T, const float* __restrict__ A,
+                                                                    const int32_t* __restrict__ req, int64_t n,
+                                                                    float* __restrict__ out, int max_rows)
+{
+    extern __shared__ unsigned char smem[];
+    float* cb = (float*)smem;                                          // [max_rows][kDecoupleThreads]
+    unsigned char* rb = smem + (size_t)max_rows * kDecoupleThreads * 4;  // [max_rows][kDecoupleThreads]
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * kDecoupleThreads + lane;
     if (r >= n) return;
     int o[6];
     bool ok = true;
@@ -109,47 +182,57 @@ __global__ void __launch_bounds__(256) decouple_kernel(ThreeBodyDev T, const flo
         const int tb = T.tidx[al[0] * n2 + al[1] * T.nlj + al[2]];
         const int tk = T.tidx[al[3] * n2 + al[4] * T.nlj + al[5]];
         if (M == m[3] + m[4] + m[5] && MT == tz[3] + tz[4] + tz[5] && parb == park && tb >= 0 && tk >= 0) {
-            int64_t pos = T.block_off[(int64_t)tb * T.ntrip + tk];
+            const float* blk = A + T.block_off[(int64_t)tb * T.ntrip + tk];
+            float ib[3], ik[3];
+            iso_coeffs(T, tz[0], tz[1], tz[2], ib);
+            iso_coeffs(T, tz[3], tz[4], tz[5], ik);
             const int Jmax = min(j[0] + j[1] + j[2], j[3] + j[4] + j[5]);
-            const int Mab = m[0] + m[1], Mde = m[3] + m[4], MTab = tz[0] + tz[1], MTde = tz[3] + tz[4];
-            for (int J = 1; J <= Jmax && pos >= 0; J += 2)
+            const int Mab = m[0] + m[1], Mde = m[3] + m[4];
+            for (int J = 1; J <= Jmax; J += 2) {
+                int lob, lok;
+                const int nja = jab_range(j[0], j[1], j[2], J, &lob), njd = jab_range(j[3], j[4], j[5], J, &lok);
+                if (nja == 0 || njd == 0) continue;
+                const bool mok = M <= J && -M <= J;
                 for (int TT = 1; TT <= 3; TT += 2) {
-                    const int nb = n_channels(j[0], j[1], j[2], J, TT), nk = n_channels(j[3], j[4], j[5], J, TT);
-                    if (nb == 0 || nk == 0) continue;
-                    if (M <= J && -M <= J && MT <= TT && -MT <= TT) {
-                        // bra channels in storage order: J_ab ascending, then T_ab
-                        int ib = 0;
-                        const int lob = abs(j[0] - j[1]);
-                        for (int jab = lob; jab <= j[0] + j[1]; jab += 2) {
-                            if (!triangle2(jab, j[2], J)) continue;
-                            const double cj = cg2(T.fact, j[0], m[0], j[1], m[1], jab, Mab) *
-                                              cg2(T.fact, jab, Mab, j[2], m[2], J, M);
-                            for (int tab = 0; tab <= 2; tab += 2) {
-                                if (!triangle2(tab, 1, TT)) continue;
-                                const double cb = cj * cg2(T.fact, 1, tz[0], 1, tz[1], tab, MTab) *
-                                                  cg2(T.fact, tab, MTab, 1, tz[2], TT, MT);
-                                if (cb != 0.0) {
-                                    int ik = 0;
-                                    const int lok = abs(j[3] - j[4]);
-                                    for (int jde = lok; jde <= j[3] + j[4]; jde += 2) {
-                                        if (!triangle2(jde, j[5], J)) continue;
-                                        const double ck = cg2(T.fact, j[3], m[3], j[4], m[4], jde, Mde) *
-                                                          cg2(T.fact, jde, Mde, j[5], m[5], J, M);
-                                        for (int tde = 0; tde <= 2; tde += 2) {
-                                            if (!triangle2(tde, 1, TT)) continue;
-                                            const double c = ck * cg2(T.fact, 1, tz[3], 1, tz[4], tde, MTde) *
-                                                             cg2(T.fact, tde, MTde, 1, tz[5], TT, MT);
-                                            if (c != 0.0) sum += cb * c * (double)A[pos + (int64_t)ib * nk + ik];
-                                            ik++;
-                                        }
-                                    }
+                    const int nt = TT == 1 ? 2 : 1, nk = njd * nt;
+                    if (mok && (MT <= TT && -MT <= TT)) {
+                        // bra rows with a nonzero coefficient, compacted
+                        int nz = 0;
+                        for (int a = 0; a < nja; a++) {
+                            const int jab = lob + 2 * a;
+                            if (Mab > jab || -Mab > jab) continue;
+                            const float cj = cg_first(T, j[0], m[0], j[1], m[1], jab) *
+                                             cg_second(T, jab, Mab, j[2], m[2], J);
+                            for (int t = 0; t < nt; t++) {
+                                const float c = cj * ib[TT == 1 ? t : 2];
+                                if (c != 0.0f) {
+                                    cb[nz * kDecoupleThreads + lane] = c;
+                                    rb[nz * kDecoupleThreads + lane] = (unsigned char)(a * nt + t);
+                                    nz++;
                                 }
-                                ib++;
                             }
                         }
+                        if (nz > 0)
+                            for (int d = 0; d < njd; d++) {
+                                const int jde = lok + 2 * d;
+                                if (Mde > jde || -Mde > jde) continue;
+                                const float cj = cg_first(T, j[3], m[3], j[4], m[4], jde) *
+                                                 cg_second(T, jde, Mde, j[5], m[5], J);
+                                for (int t = 0; t < nt; t++) {
+                                    const float c = cj * ik[TT == 1 ? t : 2];
+                                    if (c == 0.0f) continue;
+                                    const float* col = blk + d * nt + t;
+                                    double acc = 0.0;
+                                    for (int i = 0; i < nz; i++)
+                                        acc += (double)cb[i * kDecoupleThreads + lane] *
+                                               (double)col[(int)rb[i * kDecoupleThreads + lane] * nk];
+                                    sum += (double)c * acc;
+                                }
+                            }
                     }
-                    pos += (int64_t)nb * nk;
+                    blk += (int64_t)nja * nt * nk;
                 }
+            }
         }
     }
     out[r] = (float)sum;
@@ -259,48 +342,50 @@ void threebody_keys(const ThreeBodyHost& h, int32_t* keys)
         }
 }
 
-// Device tables of the layout: one allocation, one copy.
+// Device tables of the layout and the coefficient tables: built contiguously
+// on the host and moved with one allocation and one copy (paper Sec. 3.3).
 hipError_t threebody_upload(ThreeBodyHost& h)
 {
-    std::vector<double> fact(kFact, 1.0);
-    for (int k = 1; k < kFact; k++) fact[k] = fact[k - 1] * k;
-    auto bytes = [](size_t n, size_t s) { return (n * s + 255) / 256 * 256; };
-    const size_t b0 = bytes(h.orb_alpha.size(), 4), b1 = bytes(h.orb_m2.size(), 4), b2 = bytes(h.nlj_j2.size(), 4),
-                 b3 = bytes(h.nlj_l.size(), 4), b4 = bytes(h.tidx.size(), 4), b5 = bytes(h.trip.size(), 4),
-                 b6 = bytes(h.block_off.size(), 8), b7 = bytes(fact.size(), 8);
-    const size_t total = b0 + b1 + b2 + b3 + b4 + b5 + b6 + b7;
-    std::vector<char> mirror(total, 0);
-    size_t off = 0;
-    auto put = [&](const void* src, size_t n, size_t b) {
-        std::memcpy(mirror.data() + off, src, n);
-        const size_t o = off;
-        off += b;
+    const int nj = h.n1max + 1;
+    std::vector<int32_t> off1, off2;
+    std::vector<float> cg1, cg2;
+    build_cg_tables(nj, off1, cg1, off2, cg2);
+    std::vector<char> mirror;
+    auto put = [&](const void* src, size_t n) {
+        const size_t o = mirror.size();
+        mirror.resize(o + (n + 255) / 256 * 256, 0);
+        std::memcpy(mirror.data() + o, src, n);
         return o;
     };
-    const size_t o0 = put(h.orb_alpha.data(), h.orb_alpha.size() * 4, b0);
-    const size_t o1 = put(h.orb_m2.data(), h.orb_m2.size() * 4, b1);
-    const size_t o2 = put(h.nlj_j2.data(), h.nlj_j2.size() * 4, b2);
-    const size_t o3 = put(h.nlj_l.data(), h.nlj_l.size() * 4, b3);
-    const size_t o4 = put(h.tidx.data(), h.tidx.size() * 4, b4);
-    const size_t o5 = put(h.trip.data(), h.trip.size() * 4, b5);
-    const size_t o6 = put(h.block_off.data(), h.block_off.size() * 8, b6);
-    const size_t o7 = put(fact.data(), fact.size() * 8, b7);
-    hipError_t e = hipMalloc(&h.arena, total);
+    const size_t o0 = put(h.orb_alpha.data(), h.orb_alpha.size() * 4);
+    const size_t o1 = put(h.orb_m2.data(), h.orb_m2.size() * 4);
+    const size_t o2 = put(h.nlj_j2.data(), h.nlj_j2.size() * 4);
+    const size_t o3 = put(h.nlj_l.data(), h.nlj_l.size() * 4);
+    const size_t o4 = put(h.tidx.data(), h.tidx.size() * 4);
+    const size_t o5 = put(h.block_off.data(), h.block_off.size() * 8);
+    const size_t o6 = put(off1.data(), off1.size() * 4);
+    const size_t o7 = put(off2.data(), off2.size() * 4);
+    const size_t o8 = put(cg1.data(), cg1.size() * 4);
+    const size_t o9 = put(cg2.data(), cg2.size() * 4);
+    hipError_t e = hipMalloc(&h.arena, mirror.size());
     if (e != hipSuccess) return e;
-    e = hipMemcpy(h.arena, mirror.data(), total, hipMemcpyHostToDevice);
+    e = hipMemcpy(h.arena, mirror.data(), mirror.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
     char* d = (char*)h.arena;
     h.dev.nsps = (int32_t)h.orb_alpha.size();
     h.dev.nlj = (int32_t)h.nlj_j2.size();
     h.dev.ntrip = (int32_t)(h.trip.size() / 3);
+    h.dev.nj = nj;
     h.dev.orb_alpha = (const int32_t*)(d + o0);
     h.dev.orb_m2 = (const int32_t*)(d + o1);
     h.dev.nlj_j2 = (const int32_t*)(d + o2);
     h.dev.nlj_l = (const int32_t*)(d + o3);
     h.dev.tidx = (const int32_t*)(d + o4);
-    h.dev.trip = (const int32_t*)(d + o5);
-    h.dev.block_off = (const int64_t*)(d + o6);
-    h.dev.fact = (const double*)(d + o7);
+    h.dev.block_off = (const int64_t*)(d + o5);
+    h.dev.cg1_off = (const int32_t*)(d + o6);
+    h.dev.cg2_off = (const int32_t*)(d + o7);
+    h.dev.cg1 = (const float*)(d + o8);
+    h.dev.cg2 = (const float*)(d + o9);
     return hipSuccess;
 }
 
@@ -313,9 +398,12 @@ void threebody_release(ThreeBodyHost& h)
 hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, float* out,
                            hipStream_t s)
 {
-    if (n > 0)
-        hipLaunchKernelGGL(decouple_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h.dev, A, req, n,
-                           out);
+    if (n <= 0) return hipSuccess;
+    // rows of one (J, T) block: at most (min(j_a, j_b) + 1) J_ab values times two T_ab
+    const int max_rows = 2 * (2 * h.n1max + 2);
+    const size_t lds = (size_t)max_rows * kDecoupleThreads * 5;
+    hipLaunchKernelGGL(decouple_kernel, dim3((unsigned)((n + kDecoupleThreads - 1) / kDecoupleThreads)),
+                       dim3(kDecoupleThreads), lds, s, h.dev, A, req, n, out, max_rows);
     return hipGetLastError();
 }
 
