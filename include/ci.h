@@ -250,9 +250,17 @@ int ci_threebody_keys(const ci_threebody* t, int32_t* keys, int64_t cap);
  * triples [n_triples][3] = orbitals (a, b, c). */
 int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, int32_t* triples);
 /* out[r] (device FP32) = element of request r (device int32 [n][6]); one
- * request per lane, FP64 sums.  Asynchronous. */
+ * request per lane (paper Sec. 3.2), FP64 sums.  work: null, or device memory
+ * of ci_threebody_work_bytes(n) bytes (caller owned, no initial contents):
+ * with it the requests are first grouped by an estimate of their cost and
+ * the most expensive run first, so that the lanes of a wavefront run loops of
+ * similar length; each result is the same either way (one lane sums one
+ * request in a fixed order).  Asynchronous on stream; calls that share a work
+ * buffer must be ordered.  CI_EINVAL for null pointers or n < 0, with work
+ * for n > 2^31 - 1; CI_ESPACE for a short work buffer. */
+size_t ci_threebody_work_bytes(int64_t n);
 int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,
-                          float* out, ci_stream stream);
+                          float* out, void* work, size_t work_bytes, ci_stream stream);
 
 /* Machine ceilings measured on the current device (the roofline of the
  * construction kernels): streaming-store bandwidth over buf (device, caller

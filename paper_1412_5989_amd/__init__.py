@@ -71,7 +71,7 @@ EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "
            "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
-           "ci_threebody_orbitals", "ci_threebody_decouple",
+           "ci_threebody_orbitals", "ci_threebody_decouple", "ci_threebody_work_bytes",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
 _lib = None
@@ -114,7 +114,9 @@ def load_library():
     L.ci_threebody_info.argtypes = [vp, P(i64), P(i32), P(i32), P(i32)]
     L.ci_threebody_keys.argtypes = [vp, vp, i64]
     L.ci_threebody_orbitals.argtypes = [vp, vp, vp, vp]
-    L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.ci_threebody_work_bytes.argtypes = [i64]
+    L.ci_threebody_work_bytes.restype = sz
     L.ci_vjp_work_bytes.argtypes = [vp]
     L.ci_vjp_work_bytes.restype = sz
     L.ci_basis_count.argtypes = [vp]
@@ -123,7 +125,7 @@ def load_library():
     L.ci_basis_states.argtypes = [vp, i32, vp, vp]
     for name in EXPORTS:
         if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count",
-                        "ci_lanczos_work_bytes", "ci_threebody_free"):
+                        "ci_lanczos_work_bytes", "ci_threebody_free", "ci_threebody_work_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -431,8 +433,14 @@ class ThreeBody:
         _check(load_library().ci_threebody_keys(self._h, out.ctypes.data_as(ctypes.c_void_p), self.n_coupled))
         return out[: self.n_coupled]
 
-    def decouple(self, coupled, requests, out=None, stream=None):
-        """m-scheme elements (float32 device tensor) of requests (int32 [n, 6] device tensor)."""
+    # below this many requests the cost order (four small launches) does not pay
+    ORDER_MIN = 1 << 16
+
+    def decouple(self, coupled, requests, out=None, order="auto", work=None, stream=None):
+        """m-scheme elements (float32 device tensor) of requests (int32 [n, 6] device tensor).
+        order: True to group the requests by cost first (a work buffer of
+        ci_threebody_work_bytes(n) bytes, `work` or one the handle keeps),
+        False for the given order, "auto" for True from ORDER_MIN requests."""
         torch = _torch()
         _check_tensor(coupled, torch.float32, self.n_coupled, "coupled")
         if requests.dtype != torch.int32 or not requests.is_cuda or not requests.is_contiguous():
@@ -441,8 +449,21 @@ class ThreeBody:
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=coupled.device)
         _check_tensor(out, torch.float32, n, "out")
-        _check(load_library().ci_threebody_decouple(self._h, _ptr(coupled), _ptr(requests), n, _ptr(out),
-                                                    _stream_ptr(stream)))
+        L = load_library()
+        if order == "auto":
+            order = n >= self.ORDER_MIN
+        wptr, wbytes = None, 0
+        if order:
+            need = int(L.ci_threebody_work_bytes(n))
+            if work is None:
+                if getattr(self, "_work", None) is None or self._work.numel() < need:
+                    self._work = torch.empty(need, dtype=torch.uint8, device=coupled.device)
+                work = self._work
+            if not work.is_cuda or work.numel() * work.element_size() < need:
+                raise ValueError("work must be a CUDA tensor of at least %d bytes" % need)
+            wptr, wbytes = _ptr(work), work.numel() * work.element_size()
+        _check(L.ci_threebody_decouple(self._h, _ptr(coupled), _ptr(requests), n, _ptr(out), wptr, wbytes,
+                                       _stream_ptr(stream)))
         return out
 
     def free(self):

@@ -909,11 +909,16 @@ int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, in
     return CI_OK;
 }
 
+size_t ci_threebody_work_bytes(int64_t n) { return decouple_work_bytes(n); }
+
 int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,
-                          float* out, ci_stream stream)
+                          float* out, void* work, size_t work_bytes, ci_stream stream)
 {
     if (!t || n < 0 || (n > 0 && (!coupled || !requests || !out))) return fail(CI_EINVAL, "null pointer");
-    hipError_t e = launch_decouple(t->h, coupled, requests, n, out, (hipStream_t)stream);
+    if (work && n > 0x7fffffffLL) return fail(CI_EINVAL, "the cost order takes at most 2^31 - 1 requests");
+    if (work && work_bytes < decouple_work_bytes(n))
+        return fail(CI_ESPACE, "work needs " + std::to_string(decouple_work_bytes(n)) + " bytes");
+    hipError_t e = launch_decouple(t->h, coupled, requests, n, work, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "decouple launch");
     return CI_OK;
 }

@@ -22,10 +22,7 @@ namespace ci {
 // All angular momenta doubled; FP32 values of the Racah formula.
 struct ThreeBodyDev {
     int32_t nsps, nlj, ntrip, nj;  // nj = number of odd j <= j2max = 2 n1max + 1
-    const int32_t* orb_alpha;      // [nsps] oscillator orbital (n l j) of each m-orbit
-    const int32_t* orb_m2;         // [nsps]
-    const int32_t* nlj_j2;         // [nlj]
-    const int32_t* nlj_l;          // [nlj]
+    const uint32_t* orb;           // [nsps] orbital (n l j) | 2j << 8 | (2m + 64) << 16 | l << 24
     const int32_t* tidx;           // [nlj^3] triple index, or -1 beyond n3max
     const int64_t* block_off;      // [ntrip^2] first element of a triple pair, or -1 (parity differs)
     const int32_t* cg1_off;        // [nj][nj]
@@ -52,7 +49,10 @@ void threebody_keys(const ThreeBodyHost& h, int32_t* keys);
 // Device tables (one allocation, one copy).
 hipError_t threebody_upload(ThreeBodyHost& h);
 void threebody_release(ThreeBodyHost& h);
-hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, float* out,
-                           hipStream_t s);
+// work: null (requests in the given order) or decouple_work_bytes(n) bytes of
+// device memory for the cost order.
+size_t decouple_work_bytes(int64_t n);
+hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, void* work,
+                           float* out, hipStream_t s);
 
 }  // namespace ci

@@ -113,52 +113,76 @@ void build_cg_tables(int nj, std::vector<int32_t>& off1, std::vector<float>& cg1
         }
 }
 
+// Coefficient lookups; the offset tables of both coupling steps sit in LDS
+// (off1: [nj][nj], off2: [2 nj][nj]).
+struct CgView {
+    const int* off1;
+    const int* off2;
+    const float* cg1;
+    const float* cg2;
+    int nj;
+};
+
 // <j1 m1 j2 m2 | J, m1 + m2> for odd j1, j2; J must close the triangle and
 // |m1 + m2| <= J must hold (the table index assumes both).
-__device__ __forceinline__ float cg_first(const ThreeBodyDev& T, int j1, int m1, int j2, int m2, int J)
+__device__ __forceinline__ float cg_first(const CgView& C, int j1, int m1, int j2, int m2, int J)
 {
-    const int base = T.cg1_off[((j1 - 1) >> 1) * T.nj + ((j2 - 1) >> 1)];
-    return T.cg1[base + (((m1 + j1) >> 1) * (j2 + 1) + ((m2 + j2) >> 1)) * (min(j1, j2) + 1) + ((J - iabs(j1 - j2)) >> 1)];
+    const int base = C.off1[((j1 - 1) >> 1) * C.nj + ((j2 - 1) >> 1)];
+    return C.cg1[base + (((m1 + j1) >> 1) * (j2 + 1) + ((m2 + j2) >> 1)) * (min(j1, j2) + 1) + ((J - iabs(j1 - j2)) >> 1)];
 }
 
 // <J12 M12 j3 m3 | J, M12 + m3> for even J12, odd j3; |M12| <= J12 and the
 // triangle (J12, j3, J) must hold.
-__device__ __forceinline__ float cg_second(const ThreeBodyDev& T, int J12, int M12, int j3, int m3, int J)
+__device__ __forceinline__ float cg_second(const CgView& C, int J12, int M12, int j3, int m3, int J)
 {
-    const int base = T.cg2_off[(J12 >> 1) * T.nj + ((j3 - 1) >> 1)];
-    return T.cg2[base + (((M12 + J12) >> 1) * (j3 + 1) + ((m3 + j3) >> 1)) * (min(J12, j3) + 1) +
+    const int base = C.off2[(J12 >> 1) * C.nj + ((j3 - 1) >> 1)];
+    return C.cg2[base + (((M12 + J12) >> 1) * (j3 + 1) + ((m3 + j3) >> 1)) * (min(J12, j3) + 1) +
                  ((J - iabs(J12 - j3)) >> 1)];
 }
 
 // Isospin part of a triple's coefficient: <1/2 t1 1/2 t2 | T_ab, t1 + t2>
 // <T_ab, t1 + t2, 1/2 t3 | T, MT> for (T, T_ab) = (1/2, 0), (1/2, 1), (3/2, 1).
-__device__ __forceinline__ void iso_coeffs(const ThreeBodyDev& T, int t1, int t2, int t3, float c[3])
+__device__ __forceinline__ void iso_coeffs(const CgView& C, int t1, int t2, int t3, float c[3])
 {
     const int MTab = t1 + t2;
-    const float c0 = MTab == 0 ? cg_first(T, 1, t1, 1, t2, 0) * cg_second(T, 0, 0, 1, t3, 1) : 0.0f;
-    const float c1 = cg_first(T, 1, t1, 1, t2, 2);
+    const float c0 = MTab == 0 ? cg_first(C, 1, t1, 1, t2, 0) * cg_second(C, 0, 0, 1, t3, 1) : 0.0f;
+    const float c1 = cg_first(C, 1, t1, 1, t2, 2);
     const int MT = MTab + t3;
     c[0] = (MT == 1 || MT == -1) ? c0 : 0.0f;
-    c[1] = (MT == 1 || MT == -1) ? c1 * cg_second(T, 2, MTab, 1, t3, 1) : 0.0f;
-    c[2] = c1 * cg_second(T, 2, MTab, 1, t3, 3);
+    c[1] = (MT == 1 || MT == -1) ? c1 * cg_second(C, 2, MTab, 1, t3, 1) : 0.0f;
+    c[2] = c1 * cg_second(C, 2, MTab, 1, t3, 3);
 }
 
 constexpr int kDecoupleThreads = 64;
+constexpr int kBraRows = 16;  // compacted bra rows per pass over the ket columns
+
+__host__ __device__ constexpr size_t decouple_lds_bytes(int nj)
+{
+    return (size_t)kBraRows * kDecoupleThreads * 5 + (size_t)3 * nj * nj * 4;
+}
 
 // One request per lane (paper Sec. 3.2: the loop bounds depend on the
 // request).  Per (J, T) block the bra coefficients that do not vanish are
-// compacted into this lane's LDS column (value, row); the ket loop then reads
-// only rows and columns with nonzero coefficients.
-__global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev T, const float* __restrict__ A,
+// compacted into this lane's LDS column (value, row), up to kBraRows at a
+// time; the ket loop then reads only rows and columns with nonzero
+// coefficients.  With an order, lane r works on request order[r].
+__global__ void __launch_bounds__(kDecoupleThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) decouple_kernel(ThreeBodyDev T, const float* __restrict__ A,
                                                                     const int32_t* __restrict__ req, int64_t n,
-                                                                    float* __restrict__ out, int max_rows)
+                                                                    const int32_t* __restrict__ order,
+                                                                    float* __restrict__ out)
 {
     extern __shared__ unsigned char smem[];
-    float* cb = (float*)smem;                                          // [max_rows][kDecoupleThreads]
-    unsigned char* rb = smem + (size_t)max_rows * kDecoupleThreads * 4;  // [max_rows][kDecoupleThreads]
+    float* cb = (float*)smem;                                            // [kBraRows][kDecoupleThreads]
+    unsigned char* rb = smem + (size_t)kBraRows * kDecoupleThreads * 4;  // [kBraRows][kDecoupleThreads]
+    int* offs = (int*)(smem + (size_t)kBraRows * kDecoupleThreads * 5);
     const int lane = threadIdx.x;
-    const int64_t r = (int64_t)blockIdx.x * kDecoupleThreads + lane;
-    if (r >= n) return;
+    const int nj = T.nj, n1 = nj * nj;
+    for (int i = lane; i < 3 * n1; i += kDecoupleThreads) offs[i] = i < n1 ? T.cg1_off[i] : T.cg2_off[i - n1];
+    __syncthreads();
+    const CgView C{offs, offs + n1, T.cg1, T.cg2, nj};
+    const int64_t g = (int64_t)blockIdx.x * kDecoupleThreads + lane;
+    if (g >= n) return;
+    const int64_t r = order ? (int64_t)order[g] : g;
     int o[6];
     bool ok = true;
     for (int k = 0; k < 6; k++) {
@@ -167,25 +191,27 @@ __global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev
     }
     double sum = 0.0;
     if (ok) {
-        int al[6], m[6], tz[6], j[6];
+        int al[6], m[6], tz[6], j[6], l[6];
         for (int k = 0; k < 6; k++) {
-            const int s = o[k] >= T.nsps, q = o[k] - s * T.nsps;
-            al[k] = T.orb_alpha[q];
-            m[k] = T.orb_m2[q];
+            const int s = o[k] >= T.nsps;
+            const uint32_t w = T.orb[o[k] - s * T.nsps];
+            al[k] = (int)(w & 0xff);
+            j[k] = (int)((w >> 8) & 0xff);
+            m[k] = (int)((w >> 16) & 0xff) - 64;
+            l[k] = (int)(w >> 24);
             tz[k] = s ? -1 : 1;
-            j[k] = T.nlj_j2[al[k]];
         }
         const int M = m[0] + m[1] + m[2], MT = tz[0] + tz[1] + tz[2];
-        const int parb = (T.nlj_l[al[0]] + T.nlj_l[al[1]] + T.nlj_l[al[2]]) & 1;
-        const int park = (T.nlj_l[al[3]] + T.nlj_l[al[4]] + T.nlj_l[al[5]]) & 1;
+        const int parb = (l[0] + l[1] + l[2]) & 1;
+        const int park = (l[3] + l[4] + l[5]) & 1;
         const int n2 = T.nlj * T.nlj;
         const int tb = T.tidx[al[0] * n2 + al[1] * T.nlj + al[2]];
         const int tk = T.tidx[al[3] * n2 + al[4] * T.nlj + al[5]];
         if (M == m[3] + m[4] + m[5] && MT == tz[3] + tz[4] + tz[5] && parb == park && tb >= 0 && tk >= 0) {
             const float* blk = A + T.block_off[(int64_t)tb * T.ntrip + tk];
             float ib[3], ik[3];
-            iso_coeffs(T, tz[0], tz[1], tz[2], ib);
-            iso_coeffs(T, tz[3], tz[4], tz[5], ik);
+            iso_coeffs(C, tz[0], tz[1], tz[2], ib);
+            iso_coeffs(C, tz[3], tz[4], tz[5], ik);
             const int Jmax = min(j[0] + j[1] + j[2], j[3] + j[4] + j[5]);
             const int Mab = m[0] + m[1], Mde = m[3] + m[4];
             for (int J = 1; J <= Jmax; J += 2) {
@@ -196,28 +222,14 @@ __global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev
                 for (int TT = 1; TT <= 3; TT += 2) {
                     const int nt = TT == 1 ? 2 : 1, nk = njd * nt;
                     if (mok && (MT <= TT && -MT <= TT)) {
-                        // bra rows with a nonzero coefficient, compacted
-                        int nz = 0;
-                        for (int a = 0; a < nja; a++) {
-                            const int jab = lob + 2 * a;
-                            if (Mab > jab || -Mab > jab) continue;
-                            const float cj = cg_first(T, j[0], m[0], j[1], m[1], jab) *
-                                             cg_second(T, jab, Mab, j[2], m[2], J);
-                            for (int t = 0; t < nt; t++) {
-                                const float c = cj * ib[TT == 1 ? t : 2];
-                                if (c != 0.0f) {
-                                    cb[nz * kDecoupleThreads + lane] = c;
-                                    rb[nz * kDecoupleThreads + lane] = (unsigned char)(a * nt + t);
-                                    nz++;
-                                }
-                            }
-                        }
-                        if (nz > 0)
+                        // sum over the nonzero ket columns of the compacted bra rows
+                        auto ket_pass = [&](int nz) {
+                            double part = 0.0;
                             for (int d = 0; d < njd; d++) {
                                 const int jde = lok + 2 * d;
                                 if (Mde > jde || -Mde > jde) continue;
-                                const float cj = cg_first(T, j[3], m[3], j[4], m[4], jde) *
-                                                 cg_second(T, jde, Mde, j[5], m[5], J);
+                                const float cj = cg_first(C, j[3], m[3], j[4], m[4], jde) *
+                                                 cg_second(C, jde, Mde, j[5], m[5], J);
                                 for (int t = 0; t < nt; t++) {
                                     const float c = cj * ik[TT == 1 ? t : 2];
                                     if (c == 0.0f) continue;
@@ -226,9 +238,29 @@ __global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev
                                     for (int i = 0; i < nz; i++)
                                         acc += (double)cb[i * kDecoupleThreads + lane] *
                                                (double)col[(int)rb[i * kDecoupleThreads + lane] * nk];
-                                    sum += (double)c * acc;
+                                    part += (double)c * acc;
                                 }
                             }
+                            return part;
+                        };
+                        int nz = 0;
+                        for (int a = 0; a < nja; a++) {
+                            const int jab = lob + 2 * a;
+                            if (Mab > jab || -Mab > jab) continue;
+                            const float cj = cg_first(C, j[0], m[0], j[1], m[1], jab) *
+                                             cg_second(C, jab, Mab, j[2], m[2], J);
+                            for (int t = 0; t < nt; t++) {
+                                const float c = cj * ib[TT == 1 ? t : 2];
+                                if (c == 0.0f) continue;
+                                cb[nz * kDecoupleThreads + lane] = c;
+                                rb[nz * kDecoupleThreads + lane] = (unsigned char)(a * nt + t);
+                                if (++nz == kBraRows) {
+                                    sum += ket_pass(nz);
+                                    nz = 0;
+                                }
+                            }
+                        }
+                        if (nz > 0) sum += ket_pass(nz);
                     }
                     blk += (int64_t)nja * nt * nk;
                 }
@@ -236,6 +268,154 @@ __global__ void __launch_bounds__(kDecoupleThreads) decouple_kernel(ThreeBodyDev
         }
     }
     out[r] = (float)sum;
+}
+
+// ------------------------------------------------------------ request order
+//
+// Requests differ in cost by two orders of magnitude, and a wavefront runs as
+// long as its slowest lane.  An optional counting sort groups them by an
+// estimate of their cost (the elements of the (J, T) blocks they read, in
+// quarter-octave bins) and hands out the most expensive first.
+
+constexpr int kCostBins = 64;
+constexpr int kCostReplicas = 32;  // counters per bin, by workgroup, so that few workgroups share one
+constexpr int kCounters = kCostBins * kCostReplicas;
+constexpr int kOrderThreads = 256;
+constexpr int kOrderPerThread = 4;
+constexpr int kOrderPerBlock = kOrderThreads * kOrderPerThread;
+
+// bin of a request from its six orbits' packed words (w[k] = 0 marks an
+// index outside [0, 2 n_sps), which costs nothing); tz from the species
+__device__ __forceinline__ int cost_bin(const uint32_t w[6], const int tz[6])
+{
+    int j[6], m[6];
+    for (int k = 0; k < 6; k++) {
+        if (w[k] == 0u) return 0;
+        j[k] = (int)((w[k] >> 8) & 0xff);
+        m[k] = (int)((w[k] >> 16) & 0xff) - 64;
+    }
+    const int M = iabs(m[0] + m[1] + m[2]), MT = iabs(tz[0] + tz[1] + tz[2]);
+    const int Jmax = min(j[0] + j[1] + j[2], j[3] + j[4] + j[5]);
+    unsigned cost = 0;
+    for (int J = M | 1; J <= Jmax; J += 2) {
+        int lo;
+        const unsigned e = (unsigned)(jab_range(j[0], j[1], j[2], J, &lo) * jab_range(j[3], j[4], j[5], J, &lo));
+        cost += e + (MT <= 1 ? 4 * e : 0);
+    }
+    const unsigned x = cost + 1;
+    const int ex = 31 - __builtin_clz(x);
+    const int frac = ex >= 2 ? (int)((x >> (ex - 2)) & 3) : (int)((x << (2 - ex)) & 3);
+    return min(kCostBins - 1, 4 * ex + frac);
+}
+
+// counters: [kCostBins][kCostReplicas] counts, then the same layout of cursors
+__global__ void __launch_bounds__(1024) order_clear(uint32_t* counters)
+{
+    for (int i = threadIdx.x; i < kCounters; i += 1024) counters[i] = 0;
+}
+
+__global__ void __launch_bounds__(kOrderThreads) order_histogram(ThreeBodyDev T, const int32_t* __restrict__ req,
+                                                                 int64_t n, uint8_t* __restrict__ bin,
+                                                                 uint32_t* __restrict__ counts)
+{
+    __shared__ uint32_t h[kCostBins];
+    if (threadIdx.x < kCostBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t g0 = (int64_t)blockIdx.x * kOrderPerBlock + threadIdx.x;
+    // all loads of the thread's requests first, so that their latencies overlap
+    int32_t o[kOrderPerThread][6];
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++) {
+        const int64_t g = g0 + u * kOrderThreads;
+#pragma unroll
+        for (int k = 0; k < 6; k++) o[u][k] = g < n ? req[g * 6 + k] : -1;
+    }
+    uint32_t w[kOrderPerThread][6];
+    int tz[kOrderPerThread][6];
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++)
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const int x = o[u][k], s = x >= T.nsps;
+            const bool in = x >= 0 && x < 2 * T.nsps;
+            w[u][k] = in ? T.orb[x - s * T.nsps] : 0u;  // a packed word is never 0 (2m + 64 > 0)
+            tz[u][k] = s ? -1 : 1;
+        }
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++) {
+        const int64_t g = g0 + u * kOrderThreads;
+        if (g < n) {
+            const int b = cost_bin(w[u], tz[u]);
+            bin[g] = (uint8_t)b;
+            atomicAdd(&h[b], 1u);
+        }
+    }
+    __syncthreads();
+    const int rep = blockIdx.x % kCostReplicas;
+    if (threadIdx.x < kCostBins && h[threadIdx.x])
+        atomicAdd(&counts[threadIdx.x * kCostReplicas + rep], h[threadIdx.x]);
+}
+
+// cursors in the order (bin descending, replica ascending): exclusive sums of
+// the counts, one workgroup, eight counters per thread
+__global__ void __launch_bounds__(256) order_starts(uint32_t* counters)
+{
+    constexpr int kPer = kCounters / 256;
+    __shared__ uint32_t part[256];
+    const int t = threadIdx.x;
+    uint32_t v[kPer], run = 0;
+    for (int i = 0; i < kPer; i++) {
+        const int q = t * kPer + i;  // position in the output order
+        const int b = kCostBins - 1 - q / kCostReplicas, rep = q % kCostReplicas;
+        v[i] = counters[b * kCostReplicas + rep];
+        run += v[i];
+    }
+    part[t] = run;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t x = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    run = part[t] - run;  // exclusive prefix of this thread's first counter
+    for (int i = 0; i < kPer; i++) {
+        const int q = t * kPer + i;
+        const int b = kCostBins - 1 - q / kCostReplicas, rep = q % kCostReplicas;
+        counters[kCounters + b * kCostReplicas + rep] = run;
+        run += v[i];
+    }
+}
+
+__global__ void __launch_bounds__(kOrderThreads) order_scatter(const uint8_t* __restrict__ bin, int64_t n,
+                                                               uint32_t* __restrict__ cursor,
+                                                               int32_t* __restrict__ order)
+{
+    __shared__ uint32_t h[kCostBins];
+    __shared__ uint32_t base[kCostBins];
+    if (threadIdx.x < kCostBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t g0 = (int64_t)blockIdx.x * kOrderPerBlock + threadIdx.x;
+    int b[kOrderPerThread];
+    uint32_t rank[kOrderPerThread];
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++) {
+        const int64_t g = g0 + u * kOrderThreads;
+        b[u] = g < n ? bin[g] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++)
+        rank[u] = g0 + u * kOrderThreads < n ? atomicAdd(&h[b[u]], 1u) : 0u;
+    __syncthreads();
+    const int rep = blockIdx.x % kCostReplicas;
+    if (threadIdx.x < kCostBins && h[threadIdx.x])
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x * kCostReplicas + rep], h[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kOrderPerThread; u++) {
+        const int64_t g = g0 + u * kOrderThreads;
+        if (g < n) order[base[b[u]] + rank[u]] = (int32_t)g;
+    }
 }
 
 }  // namespace
@@ -357,10 +537,13 @@ hipError_t threebody_upload(ThreeBodyHost& h)
         std::memcpy(mirror.data() + o, src, n);
         return o;
     };
-    const size_t o0 = put(h.orb_alpha.data(), h.orb_alpha.size() * 4);
-    const size_t o1 = put(h.orb_m2.data(), h.orb_m2.size() * 4);
-    const size_t o2 = put(h.nlj_j2.data(), h.nlj_j2.size() * 4);
-    const size_t o3 = put(h.nlj_l.data(), h.nlj_l.size() * 4);
+    std::vector<uint32_t> orb(h.orb_alpha.size());
+    for (size_t q = 0; q < orb.size(); q++) {
+        const int a = h.orb_alpha[q];
+        orb[q] = (uint32_t)a | (uint32_t)h.nlj_j2[a] << 8 | (uint32_t)(h.orb_m2[q] + 64) << 16 |
+                 (uint32_t)h.nlj_l[a] << 24;
+    }
+    const size_t o0 = put(orb.data(), orb.size() * 4);
     const size_t o4 = put(h.tidx.data(), h.tidx.size() * 4);
     const size_t o5 = put(h.block_off.data(), h.block_off.size() * 8);
     const size_t o6 = put(off1.data(), off1.size() * 4);
@@ -376,10 +559,7 @@ hipError_t threebody_upload(ThreeBodyHost& h)
     h.dev.nlj = (int32_t)h.nlj_j2.size();
     h.dev.ntrip = (int32_t)(h.trip.size() / 3);
     h.dev.nj = nj;
-    h.dev.orb_alpha = (const int32_t*)(d + o0);
-    h.dev.orb_m2 = (const int32_t*)(d + o1);
-    h.dev.nlj_j2 = (const int32_t*)(d + o2);
-    h.dev.nlj_l = (const int32_t*)(d + o3);
+    h.dev.orb = (const uint32_t*)(d + o0);
     h.dev.tidx = (const int32_t*)(d + o4);
     h.dev.block_off = (const int64_t*)(d + o5);
     h.dev.cg1_off = (const int32_t*)(d + o6);
@@ -395,15 +575,31 @@ void threebody_release(ThreeBodyHost& h)
     h.arena = nullptr;
 }
 
-hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, float* out,
-                           hipStream_t s)
+size_t decouple_work_bytes(int64_t n)
+{
+    if (n <= 0) return 0;
+    return (size_t)2 * kCounters * 4 + (size_t)(n + 255) / 256 * 256 + (size_t)n * 4;
+}
+
+hipError_t launch_decouple(const ThreeBodyHost& h, const float* A, const int32_t* req, int64_t n, void* work,
+                           float* out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    // rows of one (J, T) block: at most (min(j_a, j_b) + 1) J_ab values times two T_ab
-    const int max_rows = 2 * (2 * h.n1max + 2);
-    const size_t lds = (size_t)max_rows * kDecoupleThreads * 5;
+    const int32_t* order = nullptr;
+    if (work) {
+        uint32_t* counters = (uint32_t*)work;  // [2][kCostBins][kCostReplicas]: counts, then cursors
+        uint8_t* bin = (uint8_t*)work + (size_t)2 * kCounters * 4;
+        int32_t* ord = (int32_t*)(bin + (size_t)(n + 255) / 256 * 256);
+        const unsigned blocks = (unsigned)((n + kOrderPerBlock - 1) / kOrderPerBlock);
+        hipLaunchKernelGGL(order_clear, dim3(1), dim3(1024), 0, s, counters);
+        hipLaunchKernelGGL(order_histogram, dim3(blocks), dim3(kOrderThreads), 0, s, h.dev, req, n, bin, counters);
+        hipLaunchKernelGGL(order_starts, dim3(1), dim3(256), 0, s, counters);
+        hipLaunchKernelGGL(order_scatter, dim3(blocks), dim3(kOrderThreads), 0, s, bin, n, counters + kCounters,
+                           ord);
+        order = ord;
+    }
     hipLaunchKernelGGL(decouple_kernel, dim3((unsigned)((n + kDecoupleThreads - 1) / kDecoupleThreads)),
-                       dim3(kDecoupleThreads), lds, s, h.dev, A, req, n, out, max_rows);
+                       dim3(kDecoupleThreads), decouple_lds_bytes(h.dev.nj), s, h.dev, A, req, n, order, out);
     return hipGetLastError();
 }
 

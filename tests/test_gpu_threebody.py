@@ -42,17 +42,19 @@ def coupled_input(t, seed):
                                k[:, 7]).astype(np.float32)
 
 
+@pytest.mark.parametrize("order", [False, True])
 @pytest.mark.parametrize("n1,n3,nreq", [(2, 2, 600), (3, 3, 600), (4, 4, 800)])
-def test_decouple_matches_oracle(ci, n1, n3, nreq):
+def test_decouple_matches_oracle(ci, n1, n3, nreq, order):
     import torch
 
     t = ci.ThreeBody(n1, n3)
-    say("three-body", n1, n3, "coupled", t.n_coupled, "triples", t.n_triples)
+    say("three-body", n1, n3, "coupled", t.n_coupled, "triples", t.n_triples, "cost order", order)
     A = coupled_input(t, 50 + n1)
     req = si.requests_3b(60 + n1, nreq, n1, n3, mismatched=40)
     bad = np.array([[-1, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 2 * t.n_sps]], np.int32)
     req = np.concatenate([req, bad])
-    out = t.decouple(torch.from_numpy(A).cuda(), torch.from_numpy(req).cuda()).cpu().numpy().astype(np.float64)
+    out = t.decouple(torch.from_numpy(A).cuda(), torch.from_numpy(req).cuda(),
+                     order=order).cpu().numpy().astype(np.float64)
     o = OracleTB(n1, n3)
 
     def val(*key):
@@ -100,3 +102,23 @@ def test_decouple_workload_sampled(ci):
     ref = np.array([o.element(req[i], val) for i in pick])
     say("workload max err / scale", np.abs(out[pick] - ref).max() / np.abs(ref).max())
     assert np.abs(out[pick] - ref).max() <= TOL * np.abs(ref).max()
+
+
+def test_cost_order_gives_the_same_bits(ci):
+    # each request is summed by one lane in a fixed order, so grouping the
+    # requests by cost changes no bit of any result; ragged n, repeated calls
+    # on one work buffer with a smaller n second
+    import torch
+
+    t = ci.ThreeBody(6, 6)
+    A = torch.from_numpy(np.random.default_rng(3).standard_normal(t.n_coupled).astype(np.float32)).cuda()
+    req = torch.from_numpy(si.requests_3b(67, 150001, 6, 6, mismatched=1000)).cuda()
+    ref = t.decouple(A, req, order=False)
+    work = torch.empty(ci.load_library().ci_threebody_work_bytes(150001), dtype=torch.uint8, device="cuda")
+    for n in (150001, 70001, 1, 0):
+        got = t.decouple(A, req[:n], order=True, work=work)
+        torch.cuda.synchronize()
+        say("cost order n", n)
+        assert torch.equal(got, ref[:n])
+    with pytest.raises(ValueError):
+        t.decouple(A, req, order=True, work=work[:100])

@@ -4,6 +4,7 @@ The library loads, exports every symbol include/ci.h declares, and its host
 planning (basis sizes, two-body key list) equals the oracle's; validation
 errors are raised before any device call.
 """
+import ctypes
 import os
 import re
 
@@ -143,3 +144,16 @@ def test_threebody_plan_validation():
         with pytest.raises(ci.CIError) as e:
             ci.ci_threebody_plan(*bad)
         assert e.value.code == ci.CI_EINVAL
+
+
+def test_threebody_decouple_argument_errors():
+    # rejected before any device call: null handle / pointers, negative n
+    L = ci.load_library()
+    vp = ctypes.c_void_p
+    assert L.ci_threebody_decouple(None, None, None, 0, None, None, 0, None) == ci.CI_EINVAL
+    assert L.ci_threebody_decouple(vp(1), None, None, -1, None, None, 0, None) == ci.CI_EINVAL
+    assert L.ci_threebody_decouple(vp(1), None, None, 5, None, None, 0, None) == ci.CI_EINVAL
+    # the cost order's work buffer: counters, one byte and one int32 per request
+    assert L.ci_threebody_work_bytes(0) == 0
+    for n in (1, 255, 256, 1000, 1 << 20):
+        assert L.ci_threebody_work_bytes(n) >= 5 * n
