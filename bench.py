@@ -121,6 +121,18 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
     }
 
 
+def copy_calibration(torch, mib):
+    """A plain device-to-device copy of known size, three times (to scale
+    hardware byte counters under rocprofv3)."""
+    if mib > 0:
+        src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def run_lanczos(ci, torch, prob, tbme_seed):
     """The step after construction: full symmetric CSR, H x, lowest eigenpair."""
     import seeded_inputs as si
@@ -295,6 +307,8 @@ def main():
     ap.add_argument("--workload", default="li6_nmax6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-threebody", action="store_true",
+                    help="run only the three-body decoupling section (for counter and trace runs of its kernels)")
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed construction steps (no ceiling probes, Lanczos, three-body or "
                          "batched sections): for counter and trace runs of the step's kernels")
@@ -315,6 +329,11 @@ def main():
     import seeded_inputs as si
 
     ci = ensure_library()
+    if args.only_threebody:
+        res = {"threebody": run_threebody(ci, torch, not args.no_cpu_baseline)}
+        copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(res), flush=True)
+        return
     w = si.WORKLOADS[args.workload]
     prob = w["problem"]
     stream = torch.cuda.current_stream()
@@ -386,13 +405,7 @@ def main():
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / args.steps
 
-    if args.copy_calibration > 0:
-        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(torch, args.copy_calibration)
 
     fill_ms = ev_fill.mean_ms()
     vjp_ms = ev_vjp.mean_ms()

@@ -433,8 +433,8 @@ class ThreeBody:
         _check(load_library().ci_threebody_keys(self._h, out.ctypes.data_as(ctypes.c_void_p), self.n_coupled))
         return out[: self.n_coupled]
 
-    # below this many requests the cost order (four small launches) does not pay
-    ORDER_MIN = 1 << 16
+    # below this many requests the cost order (four small launches, ~40 us) does not pay
+    ORDER_MIN = 1 << 19
 
     def decouple(self, coupled, requests, out=None, order="auto", work=None, stream=None):
         """m-scheme elements (float32 device tensor) of requests (int32 [n, 6] device tensor).
