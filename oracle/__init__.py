@@ -68,6 +68,13 @@ def _load():
     L.orc_element.restype = dbl
     L.orc_element.argtypes = [vp, i64, i64]
     L.orc_grad_rows.argtypes = [vp, vp, i64, vp, vp]
+    L.orc_set_v3.argtypes = [vp, i32, ctypes.c_uint64, dbl]
+    L.orc_v3.restype = dbl
+    L.orc_v3.argtypes = [vp, i32, i32, i32, i32, i32, i32]
+    L.orc_row_counts3.argtypes = [vp, vp, i64, vp]
+    L.orc_rows3.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.orc_element3.restype = dbl
+    L.orc_element3.argtypes = [vp, i64, i64]
     _lib = L
     return L
 
@@ -201,6 +208,52 @@ class Oracle:
             _load().orc_rows_full(self._h, _ptr(rows), len(rows), _ptr(offs), _ptr(cols),
                                   _ptr(vals) if values else None)
         return counts, cols[:tot], (vals[:tot] if values else None)
+
+    # ---- three-body term (d <= 3 structure)
+    V3_NONE, V3_SYNTHETIC, V3_IDENTITY = 0, 1, 2
+
+    def set_v3(self, kind: int, seed: int = 0, scale: float = 1.0) -> None:
+        """Three-body interaction: none, synthetic (splitmix64 of the triple pair,
+        uniform in [-scale, scale)), or identity (scale on equal triples)."""
+        _load().orc_set_v3(self._h, int(kind), int(seed) & ((1 << 64) - 1), float(scale))
+
+    def v3(self, a, b, c, d, e, f) -> float:
+        return _load().orc_v3(self._h, a, b, c, d, e, f)
+
+    def row_counts3(self, rows) -> np.ndarray:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros(len(rows), np.int64)
+        if len(rows):
+            _load().orc_row_counts3(self._h, _ptr(rows), len(rows), _ptr(out))
+        return out
+
+    def rows3(self, rows, values: bool = True):
+        """Like rows(), with the three-body term: columns j >= i with at most
+        three nucleons different."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        counts = self.row_counts3(rows)
+        offs = np.zeros(len(rows), np.int64)
+        if len(rows):
+            offs[1:] = np.cumsum(counts)[:-1]
+        tot = int(counts.sum())
+        cols = np.zeros(max(tot, 1), np.int32)
+        vals = np.zeros(max(tot, 1), np.float64) if values else None
+        if len(rows):
+            _load().orc_rows3(self._h, _ptr(rows), len(rows), _ptr(offs), _ptr(cols),
+                              _ptr(vals) if values else None)
+        return counts, cols[:tot], (vals[:tot] if values else None)
+
+    def element3(self, i: int, j: int) -> float:
+        return _load().orc_element3(self._h, int(i), int(j))
+
+    def dense3(self) -> np.ndarray:
+        """Dense symmetric H with the three-body term (small bases only)."""
+        counts, cols, vals = self.rows3(np.arange(self.dim))
+        H = np.zeros((self.dim, self.dim))
+        rows = np.repeat(np.arange(self.dim), counts)
+        H[rows, cols] = vals
+        H[cols, rows] = vals
+        return H
 
     def csr(self, values: bool = True):
         """Full upper-triangle CSR (row_ptr int64[D+1], col int32, val float64)."""

@@ -186,3 +186,45 @@ def hamiltonian(basis: BruteBasis, keys: np.ndarray, values: np.ndarray, kinetic
                     continue  # leaves the truncated space
                 H[i, j] += s1 * s2 * s3 * s4 * v
     return H
+
+
+def hamiltonian3(basis: BruteBasis, v3) -> np.ndarray:
+    """Dense <Phi_i|H3|Phi_j> by operator application, for
+
+        H3 = sum_{a<b<c, d<e<f} V_{abc,def} a+_a a+_b a+_c a_f a_e a_d
+
+    with v3(a, b, c, d, e, f) the element for ascending triples.  Each term
+    removes d, e, f from |Phi_j> (in that order) and creates c, b, a, with the
+    fermion sign of every step; created triples are drawn from those with the
+    removed triple's species content, total 2m and parity (any other triple
+    leaves the basis)."""
+    D = basis.dim
+    H = np.zeros((D, D))
+    norb = 2 * basis.nsps
+
+    def label(t):
+        occ = [basis.orb[o % basis.nsps] for o in t]
+        return (sum(1 for o in t if o < basis.nsps), sum(x[4] for x in occ), sum(x[2] for x in occ) % 2)
+
+    by_label = {}
+    for t in itertools.combinations(range(norb), 3):
+        by_label.setdefault(label(t), []).append(t)
+    for j, phi in enumerate(basis.states):
+        for d, e, f in itertools.combinations(phi, 3):
+            x, s1 = _annihilate(phi, d)
+            x, s2 = _annihilate(x, e)
+            x, s3 = _annihilate(x, f)
+            for a, b, c in by_label[label((d, e, f))]:
+                y, t1 = _create(x, c)
+                if y is None:
+                    continue
+                y, t2 = _create(y, b)
+                if y is None:
+                    continue
+                y, t3 = _create(y, a)
+                if y is None:
+                    continue
+                i = basis.index.get(y)
+                if i is not None:
+                    H[i, j] += s1 * s2 * s3 * t1 * t2 * t3 * v3(a, b, c, d, e, f)
+    return H

@@ -64,6 +64,10 @@ typedef struct {
     uint64_t* skey;    /* sorted packed keys */
     int64_t* sidx;     /* table index of each sorted key */
     double* V;         /* FP64 values in table order (may be NULL = all zero) */
+    /* three-body interaction: kind 0 none, 1 synthetic, 2 identity */
+    int v3_kind;
+    uint64_t v3_seed;
+    double v3_scale;
 } orc_ctx;
 
 /* ---------------------------------------------------------------- orbits */
@@ -549,6 +553,98 @@ static double element(const orc_ctx* c, int64_t i, int64_t j, double* g, double 
     return sg * Vget(c, p[0], p[1], h[0], h[1]);
 }
 
+/* ------------------------------------------------ three-body term (d <= 3)
+ *
+ * H3 = sum_{a<b<c, d<e<f} V_{abc,def} a+_a a+_b a+_c a_f a_e a_d with V
+ * antisymmetric in each triple.  Between determinants that differ in d <= 3
+ * nucleons (particles p in Phi_i, holes h in Phi_j, spectators T = the
+ * orbits both hold) the Slater-Condon rules give
+ *   d = 0: sum over occupied a<b<c of V_{abc,abc}
+ *   d = 1: phase * sum over spectators k<l of V_{pkl,hkl}
+ *   d = 2: phase * sum over spectators k of V_{p1 p2 k, h1 h2 k}
+ *   d = 3: phase * V_{p1 p2 p3, h1 h2 h3}
+ * with the same fermion phase as the one- and two-body moves: the holes
+ * removed from Phi_j in ascending order, the particles added in descending
+ * order.  The paper's three-body elements come from its decoupling (Sec. 3);
+ * here the interaction is synthetic:
+ *   kind 1: for ascending triples, the (x+1)-th output of the splitmix64
+ *           generator (Steele, Lea & Flood 2014) started at `seed`, with
+ *           x = min(kb, kk) << 27 | max(kb, kk), k = (a*512 + b)*512 + c for
+ *           each triple, mapped to scale * (2u - 1), u = top 53 bits / 2^53
+ *           (symmetric under bra <-> ket, so H stays symmetric);
+ *   kind 2: scale when the two triples are equal, else 0 (then
+ *           H3 = scale * A(A-1)(A-2)/6 on every A-nucleon state). */
+
+static uint64_t splitmix64_at(uint64_t state, uint64_t k)
+{
+    uint64_t z = state + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double v3_sorted(const orc_ctx* c, int a, int b, int cc, int d, int e, int f)
+{
+    if (c->v3_kind == 2) return (a == d && b == e && cc == f) ? c->v3_scale : 0.0;
+    uint64_t kb = ((uint64_t)a * 512 + (uint64_t)b) * 512 + (uint64_t)cc;
+    uint64_t kk = ((uint64_t)d * 512 + (uint64_t)e) * 512 + (uint64_t)f;
+    uint64_t lo = kb < kk ? kb : kk, hi = kb < kk ? kk : kb;
+    uint64_t z = splitmix64_at(c->v3_seed, ((lo << 27) | hi) + 1);
+    return c->v3_scale * (2.0 * ((double)(z >> 11) / 9007199254740992.0) - 1.0);
+}
+
+/* V_{abc,def} for triples in any order: each triple is sorted and every
+ * transposition flips the sign; a repeated orbit gives 0. */
+static double v3_any(const orc_ctx* c, int a, int b, int cc, int d, int e, int f)
+{
+    int x[3] = {a, b, cc}, y[3] = {d, e, f}, sg = 1;
+    for (int r = 0; r < 2; r++)
+        for (int q = 0; q < 2 - r; q++) {
+            if (x[q] > x[q + 1]) { int t = x[q]; x[q] = x[q + 1]; x[q + 1] = t; sg = -sg; }
+            if (y[q] > y[q + 1]) { int t = y[q]; y[q] = y[q + 1]; y[q + 1] = t; sg = -sg; }
+        }
+    if (x[0] == x[1] || x[1] == x[2] || y[0] == y[1] || y[1] == y[2]) return 0.0;
+    return sg * v3_sorted(c, x[0], x[1], x[2], y[0], y[1], y[2]);
+}
+
+/* <Phi_i|H|Phi_j> with the three-body term, any i, j (0 beyond d = 3) */
+static double element3(const orc_ctx* c, int64_t i, int64_t j)
+{
+    int oi[2 * 64 * ORC_MAXW], oj[2 * 64 * ORC_MAXW], T[2 * 64 * ORC_MAXW];
+    int ni = occupied(c, i, oi), nj = occupied(c, j, oj);
+    int h[3], p[3], nh = 0, np = 0, nt = 0;
+    for (int t = 0; t < nj; t++)
+        if (!in_list(oi, ni, oj[t])) {
+            if (nh == 3) return 0.0;
+            h[nh++] = oj[t];
+        }
+    for (int t = 0; t < ni; t++)
+        if (!in_list(oj, nj, oi[t])) p[np++] = oi[t];
+    double v = nh <= 2 ? element(c, i, j, NULL, 0.0) : 0.0;
+    if (c->v3_kind == 0) return v;
+    double w = 0.0;
+    if (nh == 0) {
+        for (int a = 0; a < ni; a++)
+            for (int b = a + 1; b < ni; b++)
+                for (int q = b + 1; q < ni; q++) w += v3_sorted(c, oi[a], oi[b], oi[q], oi[a], oi[b], oi[q]);
+        return v + w;
+    }
+    for (int t = 0; t < nj; t++)
+        if (!in_list(h, nh, oj[t])) T[nt++] = oj[t];
+    int e = -nh * (nh - 1) / 2;
+    for (int k = 0; k < nh; k++) e += count_below(oj, nj, h[k]) + count_below(T, nt, p[k]);
+    double sg = (e % 2 != 0) ? -1.0 : 1.0;
+    if (nh == 1) {
+        for (int a = 0; a < nt; a++)
+            for (int b = a + 1; b < nt; b++) w += v3_any(c, p[0], T[a], T[b], h[0], T[a], T[b]);
+    } else if (nh == 2) {
+        for (int a = 0; a < nt; a++) w += v3_any(c, p[0], p[1], T[a], h[0], h[1], T[a]);
+    } else {
+        w = v3_sorted(c, p[0], p[1], p[2], h[0], h[1], h[2]);
+    }
+    return v + sg * w;
+}
+
 /* ------------------------------------------------------------- public */
 
 static void ctx_free(orc_ctx* c)
@@ -752,3 +848,50 @@ void orc_grad_rows(void* h, const int64_t* rows, int64_t nrows, const double* G,
         }
     }
 }
+
+/* ------------------------------------------- three-body term: public */
+
+void orc_set_v3(void* h, int kind, uint64_t seed, double scale)
+{
+    orc_ctx* c = (orc_ctx*)h;
+    c->v3_kind = kind;
+    c->v3_seed = seed;
+    c->v3_scale = scale;
+}
+
+double orc_v3(void* h, int a, int b, int cc, int d, int e, int f)
+{
+    return v3_any((orc_ctx*)h, a, b, cc, d, e, f);
+}
+
+/* Stored entries with the three-body term: columns j >= i with at most three
+ * nucleons different (structural zeros included), ascending. */
+void orc_row_counts3(void* h, const int64_t* rows, int64_t nrows, int64_t* counts)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t n = 0;
+        for (int64_t j = rows[r]; j < c->D; j++)
+            if (ndiff(c, rows[r], j) <= 3) n++;
+        counts[r] = n;
+    }
+}
+
+void orc_rows3(void* h, const int64_t* rows, int64_t nrows, const int64_t* offs, int32_t* cols, double* vals)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t i = rows[r], o = offs[r];
+        for (int64_t j = i; j < c->D; j++) {
+            if (ndiff(c, i, j) > 3) continue;
+            cols[o] = (int32_t)j;
+            if (vals) vals[o] = element3(c, i, j);
+            o++;
+        }
+    }
+}
+
+/* <Phi_i|H|Phi_j> with the three-body term for any i, j (both triangles) */
+double orc_element3(void* h, int64_t i, int64_t j) { return element3((orc_ctx*)h, i, j); }

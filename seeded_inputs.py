@@ -92,6 +92,24 @@ def _mix64(x):
     return x ^ (x >> np.uint64(31))
 
 
+SPLITMIX64_GAMMA = 0x9E3779B97F4A7C15
+
+
+def v3_synthetic(seed, a, b, c, d, e, f, scale=1.0):
+    """Synthetic antisymmetrized m-scheme three-body elements V_{abc,def} for
+    ascending triples of combined orbit indices (arrays): the (x+1)-th output
+    of the splitmix64 generator (Steele, Lea & Flood 2014) started at `seed`,
+    x = min(kb, kk) << 27 | max(kb, kk) with k = (a*512 + b)*512 + c per
+    triple, mapped to scale * (2u - 1), u = top 53 bits / 2^53."""
+    u = np.uint64
+    with np.errstate(over="ignore"):
+        kb = (np.asarray(a, dtype=u) * u(512) + np.asarray(b, dtype=u)) * u(512) + np.asarray(c, dtype=u)
+        kk = (np.asarray(d, dtype=u) * u(512) + np.asarray(e, dtype=u)) * u(512) + np.asarray(f, dtype=u)
+        x = (np.minimum(kb, kk) << u(27)) | np.maximum(kb, kk)
+        z = _mix64(u(int(seed) & ((1 << 64) - 1)) + (x + u(1)) * u(SPLITMIX64_GAMMA))
+    return scale * (2.0 * ((z >> u(11)).astype(np.float64) / float(1 << 53)) - 1.0)
+
+
 def coupled3b_values(seed, bra, ket, J2, T2, Jab2, Tab2, Jde2, Tde2):
     """Synthetic coupled-JT three-body elements, N(0,1), from a counter-based
     hash of the labels (bra, ket: [n, 3] orbital triples; the rest [n] doubled
