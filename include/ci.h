@@ -168,6 +168,40 @@ int ci_hamiltonian_count_full(const ci_basis* b, int64_t* row_ptr, int64_t* nnz,
 int ci_hamiltonian_fill_full(const ci_basis* b, const float* tbme, const int64_t* row_ptr,
                              int32_t* col, float* val, ci_stream stream);
 
+/* ---- Matrix with a three-body term (paper Sec. 2: elements combine kinetic,
+ * two-body and three-body terms; Sec. 4.1: count, then calculate and store
+ * half of the symmetric matrix).  Stored entries: every (i, j), j >= i, whose
+ * states differ in at most three nucleons (structural zeros included),
+ * columns ascending.  Values: the one- and two-body part of
+ * ci_hamiltonian_fill (zero three nucleons apart) plus the three-body part of
+ * H3 = sum_{a<b<c, d<e<f} V_{abc,def} a+_a a+_b a+_c a_f a_e a_d by the
+ * Slater-Condon rules (spectator sums for 0, 1, 2 nucleons apart; the
+ * fermion phase of the other moves: holes removed from the column state in
+ * ascending order, particles added in descending order).  The paper's
+ * three-body elements come from its decoupling (Sec. 3); the interaction here
+ * is synthetic (ci_v3).  Same row_ptr layout and batch conventions as the
+ * two-body passes.  CI_EINVAL for null pointers or an unknown kind;
+ * CI_EUNSUPPORTED when a problem has more than 128 nucleons. */
+#define CI_V3_NONE 0      /* no three-body term (the two-body values on the d <= 3 structure) */
+#define CI_V3_SYNTHETIC 1 /* V_{abc,def} for ascending triples of combined orbits: the (x+1)-th  */
+                          /* output of splitmix64 started at seed, x = min(kb, kk) << 27 |       */
+                          /* max(kb, kk), k = (a*512 + b)*512 + c per triple, mapped to          */
+                          /* scale * (2u - 1) with u = top 53 bits / 2^53 (symmetric in bra/ket) */
+#define CI_V3_IDENTITY 2  /* scale when the two triples are equal, else 0                        */
+typedef struct {
+    int32_t kind;
+    uint64_t seed;
+    double scale; /* MeV */
+} ci_v3;
+
+/* Count pass of the d <= 3 structure: row_ptr (device int64, sum of (D_b + 1)),
+ * nnz (host int64[n_probs]).  Synchronizes the stream. */
+int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
+/* Fill pass: col (device int32), val (device FP32, FP64 sums) at row_ptr's
+ * positions; tbme as for ci_hamiltonian_fill; v3 (host).  Asynchronous. */
+int ci_hamiltonian3_fill(const ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr,
+                         int32_t* col, float* val, ci_stream stream);
+
 /* y = H x for problem `prob` of the handle, H in full CSR form (row_ptr, col,
  * val from ci_hamiltonian_count_full / _fill_full; the problem's own row
  * segment is used).  x, y: device FP64 [D]; FP64 sums in a fixed order per

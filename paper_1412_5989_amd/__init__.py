@@ -56,6 +56,13 @@ class ci_basis_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ci_v3(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("seed", ctypes.c_uint64), ("scale", ctypes.c_double)]
+
+
+CI_V3_NONE, CI_V3_SYNTHETIC, CI_V3_IDENTITY = 0, 1, 2
+
+
 class ci_tuning(ctypes.Structure):
     _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
                 ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32)]
@@ -67,7 +74,7 @@ class ci_tuning(ctypes.Structure):
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
-           "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
+           "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill", "ci_hamiltonian_spmv", "ci_lanczos",
            "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
@@ -115,6 +122,8 @@ def load_library():
     L.ci_threebody_keys.argtypes = [vp, vp, i64]
     L.ci_threebody_orbitals.argtypes = [vp, vp, vp, vp]
     L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
+    L.ci_hamiltonian3_count.argtypes = [vp, vp, vp, vp]
+    L.ci_hamiltonian3_fill.argtypes = [vp, vp, P(ci_v3), vp, vp, vp, vp]
     L.ci_threebody_work_bytes.argtypes = [i64]
     L.ci_threebody_work_bytes.restype = sz
     L.ci_vjp_work_bytes.argtypes = [vp]
@@ -289,6 +298,38 @@ def ci_hamiltonian_fill_full(basis: Basis, tbme, row_ptr, col=None, val=None, st
     _check_tensor(val, torch.float32, tot, "val")
     _check(load_library().ci_hamiltonian_fill_full(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
                                                    _stream_ptr(stream)))
+    return col, val
+
+
+def ci_hamiltonian3_count(basis: Basis, stream=None):
+    """Count pass of the matrix with a three-body term (states at most three
+    nucleons apart, upper triangle): (row_ptr, nnz list per basis)."""
+    torch = _torch()
+    row_ptr = torch.empty(basis.n_rowptr, dtype=torch.int64, device=basis.device)
+    nnz = np.zeros(basis.n_probs, np.int64)
+    _check(load_library().ci_hamiltonian3_count(basis.handle, _ptr(row_ptr), nnz.ctypes.data_as(ctypes.c_void_p),
+                                                _stream_ptr(stream)))
+    basis.nnz3 = [int(x) for x in nnz]
+    return row_ptr, basis.nnz3
+
+
+def ci_hamiltonian3_fill(basis: Basis, tbme, v3, row_ptr, col=None, val=None, stream=None):
+    """Fill pass with the three-body term: (col int32, val float32).
+    v3 = (kind, seed, scale) with kind CI_V3_NONE / CI_V3_SYNTHETIC / CI_V3_IDENTITY."""
+    torch = _torch()
+    tot = sum(basis.nnz3)
+    _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    if col is None:
+        col = torch.empty(tot, dtype=torch.int32, device=basis.device)
+    if val is None:
+        val = torch.empty(tot, dtype=torch.float32, device=basis.device)
+    _check_tensor(col, torch.int32, tot, "col")
+    _check_tensor(val, torch.float32, tot, "val")
+    kind, seed, scale = v3
+    p = ci_v3(int(kind), int(seed) & ((1 << 64) - 1), float(scale))
+    _check(load_library().ci_hamiltonian3_fill(basis.handle, _ptr(tbme), ctypes.byref(p), _ptr(row_ptr), _ptr(col),
+                                               _ptr(val), _stream_ptr(stream)))
     return col, val
 
 

@@ -35,6 +35,9 @@ hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps,
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, int nb, const float* tbme, int v3_kind,
+                          uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val, bool fill,
+                          hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
 }  // namespace ci
@@ -657,6 +660,53 @@ int ci_hamiltonian_fill_full(const ci_basis* b, const float* tbme, const int64_t
                              float* val, ci_stream stream)
 {
     return fill_impl(b, tbme, row_ptr, col, val, 1, (hipStream_t)stream);
+}
+
+static int h3_check(const ci_basis* b)
+{
+    for (const auto& p : b->probs)
+        if (p.Z + p.N > 128) return fail(CI_EUNSUPPORTED, "the three-body term takes at most 128 nucleons");
+    return CI_OK;
+}
+
+static std::vector<int64_t> h3_dims(const ci_basis* b)
+{
+    std::vector<int64_t> d(b->info.size());
+    for (size_t p = 0; p < d.size(); p++) d[p] = b->info[p].dim;
+    return d;
+}
+
+int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
+    if (int rc = h3_check(b)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)b->info.size();
+    const std::vector<int64_t> dims = h3_dims(b);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), n, nullptr, 0, 0, 0.0, row_ptr, nullptr, nullptr, false, s);
+    if (e != hipSuccess) return hip_fail(e, "three-body count launch");
+    e = launch_inclusive_scan(row_ptr, b->n_rowptr, b->d_scan_tmp, s);
+    if (e != hipSuccess) return hip_fail(e, "scan launch");
+    e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
+    if (e != hipSuccess) return hip_fail(e, "nnz launch");
+    e = hipMemcpyAsync(nnz, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(nnz)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(three-body count)");
+    return CI_OK;
+}
+
+int ci_hamiltonian3_fill(const ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr,
+                         int32_t* col, float* val, ci_stream stream)
+{
+    if (!b || !v3 || !row_ptr || !col || !val || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
+    if (int rc = h3_check(b)) return rc;
+    const std::vector<int64_t> dims = h3_dims(b);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), (int)dims.size(), tbme, v3->kind, v3->seed, v3->scale,
+                                  const_cast<int64_t*>(row_ptr), col, val, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "three-body fill launch");
+    return CI_OK;
 }
 
 // Number of adjoint tiles of the handle for shape t (the device computes the

@@ -1,0 +1,385 @@
+// Many-body matrix with a three-body term (paper Sec. 2: the elements are
+// combinations of kinetic, two-body and three-body terms; Sec. 4.1: locate,
+// then calculate and store, half of the symmetric matrix).
+//
+// Stored entries: every pair of basis states i <= j that differ in at most
+// three nucleons, structural zeros included, columns ascending.  Values:
+// one- and two-body part as for the two-body matrix (d <= 2), plus the
+// three-body part by the Slater-Condon rules with particles p (in row i, not
+// in column j), holes h (in j, not in i) and spectators (in both):
+//   d = 0: sum over occupied a < b < c of V_{abc,abc}
+//   d = 1: phase * sum over spectators k < l of V_{pkl,hkl}
+//   d = 2: phase * sum over spectators k of V_{p1 p2 k, h1 h2 k}
+//   d = 3: phase * V_{p1 p2 p3, h1 h2 h3}
+// The phase removes the holes from the column state in ascending order and
+// adds the particles in descending order.  The paper's three-body elements
+// come from its decoupling (Sec. 3); here they are synthetic: the (x+1)-th
+// output of the splitmix64 generator (Steele, Lea & Flood 2014) for the
+// canonical pair of ascending triples, or the identity.
+//
+// Work: one wavefront per row.  The row walks the blocks at and after its
+// own, 64 proton determinants of the block's proton key at a time.  A proton
+// partner three nucleons away leaves only the row's own neutron determinant
+// (one entry); two away, the one-neutron partners of the row's neutron
+// determinant (its partner list); one or zero away, the wavefront scans the
+// neutron key together.  An in-wave prefix sum over the 64 proton lanes
+// places every entry, so columns come out ascending.  Count and fill run the
+// same walk.
+#include <hip/hip_runtime.h>
+
+#include "ci_internal.h"
+
+namespace ci {
+
+namespace {
+
+constexpr int kH3Waves = 4;
+constexpr int kH3MaxA = 128;  // nucleons of a row kept in LDS
+
+struct V3Param {
+    int kind;  // 0 none, 1 synthetic, 2 identity
+    uint64_t seed;
+    double scale;
+};
+
+template <typename T>
+using cptr3 = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr3<T> uni(const T* p)
+{
+    return (cptr3<T>)p;
+}
+
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ BlockInfo load_block(const BlockInfo* blk, int b)
+{
+    const i32x4_t v = *uni((const i32x4_t*)(blk + b));
+    BlockInfo r;
+    r.kp = v.x;
+    r.kn = v.y;
+    r.row0 = v.z;
+    r.nkn = v.w;
+    return r;
+}
+
+__device__ __forceinline__ void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// inclusive prefix sum over the 64 lanes (DPP row shifts, row broadcasts)
+__device__ __forceinline__ int incl_scan64(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+__device__ __forceinline__ int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// k-th output of splitmix64 started at `state`
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t state, uint64_t k)
+{
+    uint64_t z = state + k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// V_{abc,def} for ascending triples of combined orbit indices
+__device__ double v3_sorted(const V3Param& v, int a, int b, int c, int d, int e, int f)
+{
+    if (v.kind == 2) return (a == d && b == e && c == f) ? v.scale : 0.0;
+    const uint64_t kb = ((uint64_t)a * 512 + (uint64_t)b) * 512 + (uint64_t)c;
+    const uint64_t kk = ((uint64_t)d * 512 + (uint64_t)e) * 512 + (uint64_t)f;
+    const uint64_t lo = kb < kk ? kb : kk, hi = kb < kk ? kk : kb;
+    const uint64_t z = splitmix64_at(v.seed, ((lo << 27) | hi) + 1);
+    return v.scale * (2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0);
+}
+
+// V_{abc,def} for triples in any order (distinct orbits): sorted with the
+// sign of both sorting permutations
+__device__ double v3_any(const V3Param& v, int a, int b, int c, int d, int e, int f)
+{
+    bool neg = false;
+    if (a > b) { const int t = a; a = b; b = t; neg = !neg; }
+    if (b > c) { const int t = b; b = c; c = t; neg = !neg; }
+    if (a > b) { const int t = a; a = b; b = t; neg = !neg; }
+    if (d > e) { const int t = d; d = e; e = t; neg = !neg; }
+    if (e > f) { const int t = e; e = f; f = t; neg = !neg; }
+    if (d > e) { const int t = d; d = e; e = t; neg = !neg; }
+    const double x = v3_sorted(v, a, b, c, d, e, f);
+    return neg ? -x : x;
+}
+
+// Two-body element V_{ab,cd} (combined indices, any order; distinct within a
+// pair), 0 when a pair is outside the table.  tb points at this basis' slice.
+__device__ double v2_any(const BasisDev& B, const float* tb, int a, int b, int c, int d)
+{
+    bool neg = false;
+    if (a > b) { const int t = a; a = b; b = t; neg = !neg; }
+    if (c > d) { const int t = c; c = d; d = t; neg = !neg; }
+    const int n = B.nsps;
+    const int cls = (a >= n) + (b >= n);
+    if (cls != (c >= n) + (d >= n)) return 0.0;
+    a -= a >= n ? n : 0;
+    b -= b >= n ? n : 0;
+    c -= c >= n ? n : 0;
+    d -= d >= n ? n : 0;
+    const uint64_t* P = B.pair + (size_t)cls * n * n;
+    const uint64_t e1 = P[a * n + b], e2 = P[c * n + d];
+    const uint32_t l1 = (uint32_t)e1, l2 = (uint32_t)e2;
+    if (e1 == kNoPair64 || e2 == kNoPair64 || (l1 >> 16) != (l2 >> 16)) return 0.0;
+    const bool first = (l1 & 0xffff) <= (l2 & 0xffff);
+    const uint32_t pos = (first ? (uint32_t)(e1 >> 32) : (uint32_t)(e2 >> 32)) + (first ? (l2 & 0xffff) : (l1 & 0xffff));
+    const double x = (double)tb[pos];
+    return neg ? -x : x;
+}
+
+// oscillator kinetic element between species-local orbits p != h of one
+// species: (hw/2) sqrt((n+1)(n+l+3/2)) for radial n, n+1 of the same (l, j, m)
+__device__ double kinetic_pair(const BasisDev& B, int p, int h)
+{
+    const int qp = B.orb_qn[p], qh = B.orb_qn[h];
+    if ((qp >> 8) != (qh >> 8)) return 0.0;
+    const int np = qp & 255, nh = qh & 255, l = (qp >> 8) & 255;
+    const int lo = np < nh ? np : nh, hi = np < nh ? nh : np;
+    if (hi != lo + 1) return 0.0;
+    return 0.5 * B.hw * sqrt((double)(lo + 1) * ((double)lo + l + 1.5));
+}
+
+// occupied orbits of the column state below combined orbit o
+__device__ __forceinline__ int below(const uint64_t* yp, const uint64_t* yn, int W, int n, int Z, int o)
+{
+    const uint64_t* y = o < n ? yp : yn;
+    const int q = o < n ? o : o - n;
+    int c = o < n ? 0 : Z;
+    for (int w = 0; w < W; w++) {
+        if (w < (q >> 6)) c += __popcll(y[w]);
+        else if (w == (q >> 6)) c += __popcll(y[w] & ((1ull << (q & 63)) - 1));
+    }
+    return c;
+}
+
+// <row|H|column> for states at most three nucleons apart: row words xp, xn,
+// column words yp, yn, the row's occupied orbits occ[A] (combined, ascending).
+__device__ double entry_value(const BasisDev& B, const float* tb, const V3Param& v3, const uint64_t* xp,
+                              const uint64_t* xn, const uint64_t* yp, const uint64_t* yn, const int16_t* occ)
+{
+    const int n = B.nsps, W = B.W, A = B.Z + B.NN;
+    int p[3] = {0, 0, 0}, h[3] = {0, 0, 0}, d = 0, dh = 0;
+    for (int s = 0; s < 2; s++)
+        for (int w = 0; w < W; w++) {
+            const uint64_t X = s ? xn[w] : xp[w], Y = s ? yn[w] : yp[w];
+            uint64_t pm = X & ~Y, hm = Y & ~X;
+            while (pm && d < 3) {
+                p[d++] = s * n + w * 64 + __builtin_ctzll(pm);
+                pm &= pm - 1;
+            }
+            while (hm && dh < 3) {
+                h[dh++] = s * n + w * 64 + __builtin_ctzll(hm);
+                hm &= hm - 1;
+            }
+        }
+    double v = 0.0;
+    if (d == 0) {
+        for (int a = 0; a < A; a++) {
+            const int oa = occ[a];
+            v += (B.orb_n[oa < n ? oa : oa - n] + 1.5) * B.hw;
+            for (int b = a + 1; b < A; b++) {
+                v += v2_any(B, tb, oa, occ[b], oa, occ[b]);
+                if (v3.kind)
+                    for (int c = b + 1; c < A; c++) v += v3_sorted(v3, oa, occ[b], occ[c], oa, occ[b], occ[c]);
+            }
+        }
+        return v;
+    }
+    int e = -d * (d - 1) / 2;
+    for (int k = 0; k < d; k++) {
+        e += below(yp, yn, W, n, B.Z, h[k]) + below(yp, yn, W, n, B.Z, p[k]);
+        for (int m = 0; m < d; m++) e -= h[m] < p[k] ? 1 : 0;
+    }
+    auto spectator = [&](int o) { return o != p[0] && (d < 2 || o != p[1]) && (d < 3 || o != p[2]); };
+    if (d == 1) {
+        for (int a = 0; a < A; a++) {
+            const int k = occ[a];
+            if (!spectator(k)) continue;
+            v += v2_any(B, tb, p[0], k, h[0], k);
+            if (v3.kind)
+                for (int b = a + 1; b < A; b++) {
+                    const int l = occ[b];
+                    if (spectator(l)) v += v3_any(v3, p[0], k, l, h[0], k, l);
+                }
+        }
+        if (B.kinetic) v += kinetic_pair(B, p[0] < n ? p[0] : p[0] - n, h[0] < n ? h[0] : h[0] - n);
+    } else if (d == 2) {
+        v = v2_any(B, tb, p[0], p[1], h[0], h[1]);
+        if (v3.kind)
+            for (int a = 0; a < A; a++) {
+                const int k = occ[a];
+                if (spectator(k)) v += v3_any(v3, p[0], p[1], k, h[0], h[1], k);
+            }
+    } else if (v3.kind) {
+        v = v3_sorted(v3, p[0], p[1], p[2], h[0], h[1], h[2]);
+    }
+    return (e & 1) ? -v : v;
+}
+
+__device__ __forceinline__ int dist(const uint64_t* x, const uint64_t* y, int W)
+{
+    int c = 0;
+    for (int w = 0; w < W; w++) c += __popcll(x[w] ^ y[w]);
+    return c >> 1;
+}
+
+template <bool kFill>
+__global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, const float* __restrict__ tbme,
+                                                         V3Param v3, int64_t* __restrict__ row_ptr,
+                                                         int32_t* __restrict__ col, float* __restrict__ val)
+{
+    __shared__ int16_t occ_s[kH3Waves][kH3MaxA];
+    const BasisDev B = *Bp;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * kH3Waves + wave;
+    if (!kFill && i == 0 && lane == 0) row_ptr[B.row0] = 0;
+    if (i >= B.dim) return;
+    const SpeciesDev& SP = B.sp[0];
+    const SpeciesDev& SN = B.sp[1];
+    const int W = B.W;
+    // block of the row
+    int lo = 0, hi = B.nblk;  // blk_off[lo] <= i < blk_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (uni(B.blk_off)[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const int b = lo;
+    const BlockInfo bi = load_block(B.blk, b);
+    const int ip = (int)((i - bi.row0) / bi.nkn), in = (int)((i - bi.row0) % bi.nkn);
+    const int pg = uni(SP.key_off)[bi.kp] + ip, ng = uni(SN.key_off)[bi.kn] + in;
+    uint64_t xp[kMaxWords] = {0, 0, 0, 0}, xn[kMaxWords] = {0, 0, 0, 0};
+    for (int w = 0; w < W; w++) {
+        xp[w] = uni(SP.sd)[(int64_t)pg * W + w];
+        xn[w] = uni(SN.sd)[(int64_t)ng * W + w];
+    }
+    int16_t* occ = occ_s[wave];
+    if (kFill) {
+        if (lane == 0) {
+            int k = 0;
+            for (int s = 0; s < 2; s++)
+                for (int w = 0; w < W; w++) {
+                    uint64_t m = s ? xn[w] : xp[w];
+                    while (m) {
+                        occ[k++] = (int16_t)(s * B.nsps + w * 64 + __builtin_ctzll(m));
+                        m &= m - 1;
+                    }
+                }
+        }
+        wave_fence();
+    }
+    const float* tb = tbme ? tbme + B.tbme0 : nullptr;
+    const int64_t n1 = uni(SN.l1_ptr)[ng];
+    const int32_t* seg = SN.seg1 + (int64_t)ng * (SN.nk + 1);
+    int64_t out = kFill ? uni(row_ptr)[B.row0 + i] : 0;
+    for (int b2 = b; b2 < B.nblk; b2++) {
+        const BlockInfo bj = load_block(B.blk, b2);
+        const int kp0 = uni(SP.key_off)[bj.kp], nKp = uni(SP.key_off)[bj.kp + 1] - kp0;
+        const int kn0 = uni(SN.key_off)[bj.kn], nKn = bj.nkn;
+        const bool same_n = bj.kn == bi.kn;
+        const int s0 = uni(seg)[bj.kn], s1 = uni(seg)[bj.kn + 1];
+        for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
+            const int pl = c + lane;
+            uint64_t yp[kMaxWords] = {0, 0, 0, 0};
+            int dp = 4;
+            if (pl < nKp) {
+                for (int w = 0; w < W; w++) yp[w] = SP.sd[(int64_t)(kp0 + pl) * W + w];
+                dp = dist(xp, yp, W);
+            }
+            int cnt = dp == 3 ? (same_n ? 1 : 0) : dp == 2 ? s1 - s0 : 0;
+            uint64_t coop = __ballot(dp <= 1);
+            while (coop) {
+                const int L = __builtin_ctzll(coop);
+                coop &= coop - 1;
+                const int excl = read_lane(incl_scan64(cnt) - cnt, L);
+                const int dL = read_lane(dp, L), pL = c + L;
+                uint64_t ypL[kMaxWords] = {0, 0, 0, 0};
+                for (int w = 0; w < W; w++) ypL[w] = uni(SP.sd)[(int64_t)(kp0 + pL) * W + w];
+                int found = 0;
+                for (int nc = (b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
+                    const int nl = nc + lane;
+                    uint64_t yn[kMaxWords] = {0, 0, 0, 0};
+                    bool ok = false;
+                    if (nl < nKn) {
+                        for (int w = 0; w < W; w++) yn[w] = SN.sd[(int64_t)(kn0 + nl) * W + w];
+                        ok = dist(xn, yn, W) <= 3 - dL;
+                    }
+                    const uint64_t m = __ballot(ok);
+                    if (kFill && ok) {
+                        const int64_t pos = out + excl + found + __popcll(m & ((1ull << lane) - 1));
+                        col[pos] = bj.row0 + pL * nKn + nl;
+                        val[pos] = (float)entry_value(B, tb, v3, xp, xn, ypL, yn, occ);
+                    }
+                    found += __popcll(m);
+                }
+                if (lane == L) cnt = found;
+            }
+            const int incl = incl_scan64(cnt);
+            if (kFill && cnt > 0 && dp >= 2) {
+                int64_t pos = out + incl - cnt;
+                if (dp == 3) {
+                    col[pos] = bj.row0 + pl * nKn + in;
+                    val[pos] = (float)entry_value(B, tb, v3, xp, xn, yp, xn, occ);
+                } else {
+                    for (int r = s0; r < s1; r++, pos++) {
+                        const int nl = (int)(SN.l1[n1 + r] & kRecLocalMask);
+                        uint64_t yn[kMaxWords] = {0, 0, 0, 0};
+                        for (int w = 0; w < W; w++) yn[w] = SN.sd[(int64_t)(kn0 + nl) * W + w];
+                        col[pos] = bj.row0 + pl * nKn + nl;
+                        val[pos] = (float)entry_value(B, tb, v3, xp, xn, yp, yn, occ);
+                    }
+                }
+            }
+            out += read_lane(incl, 63);
+        }
+    }
+    if (!kFill && lane == 0) row_ptr[B.row0 + i + 1] = out;
+}
+
+}  // namespace
+
+// One launch per basis of the handle: count (row_ptr[R_b + 1 + i] = entries
+// of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]).
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, int nb, const float* tbme, int v3_kind,
+                          uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val, bool fill,
+                          hipStream_t s)
+{
+    const V3Param v3{v3_kind, v3_seed, v3_scale};
+    for (int p = 0; p < nb; p++) {
+        const int64_t D = dims[p];
+        const unsigned grid = (unsigned)((D + kH3Waves - 1) / kH3Waves);
+        if (grid == 0) {
+            if (!fill) {
+                // an empty basis still owns its first row_ptr slot
+                hipLaunchKernelGGL(h3_rows<false>, dim3(1), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr,
+                                   col, val);
+            }
+            continue;
+        }
+        if (fill)
+            hipLaunchKernelGGL(h3_rows<true>, dim3(grid), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr, col,
+                               val);
+        else
+            hipLaunchKernelGGL(h3_rows<false>, dim3(grid), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr,
+                               col, val);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ci

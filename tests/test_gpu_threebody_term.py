@@ -1,0 +1,155 @@
+"""Matrix with a three-body term on the GPU against the oracle, through the C ABI.
+
+Bar: structure (row_ptr, col) bit-exact; values within 1e-5 relative (max
+norm) of the FP64 oracle on the same FP32 two-body table and the same
+synthetic three-body interaction.  Small problems are compared row by row in
+full; the 6Li (W = 4 words) and 10B (W = 2) workloads on sampled rows, plus
+a property at full size: without the three-body term the matrix is the
+two-body matrix on its entries and zero on the rest.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-5
+SEED, SCALE = 0x5EED3, 2.0
+SMALL = [(2, 1, 2, 1, -1), (1, 2, 2, -1, -1), (3, 0, 2, 1, 1), (2, 2, 2, 0, 1), (3, 1, 2, 2, -1),
+         (3, 2, 2, 1, 1), (3, 3, 2, 0, 1), (2, 2, 4, 0, 1), (1, 1, 4, 2, 1), (2, 2, 0, 0, 1), (4, 4, 2, 0, 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ci():
+    import torch
+
+    import paper_1412_5989_amd as lib
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    lib.load_library()
+    return lib
+
+
+def gpu3(ci, p, kind, tbme_seed, kinetic=0):
+    import torch
+
+    b = ci.ci_basis_build([tuple(p) + ((ci.HW_MEV, 1) if kinetic else ())])
+    rp, nnz = ci.ci_hamiltonian3_count(b)
+    tb = torch.from_numpy(si.tbme_f32(tbme_seed, b.n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian3_fill(b, tb, (kind, SEED, SCALE), rp)
+    torch.cuda.synchronize()
+    return b, rp, col, val
+
+
+def oracle3(p, kind, tbme_seed, kinetic=0):
+    o = Oracle(Problem(*p, kinetic=kinetic))
+    o.set_tbme(si.tbme_f32(tbme_seed, o.n_tbme).astype(np.float64))
+    o.set_v3(kind, SEED, SCALE)
+    return o
+
+
+def rel(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300)) if ref.size else 0.0
+
+
+@pytest.mark.parametrize("kind", [1, 2, 0])
+@pytest.mark.parametrize("p", SMALL)
+def test_small_problems_every_row(ci, p, kind):
+    say("three-body term", p, "kind", kind)
+    b, rp, col, val = gpu3(ci, p, kind, 41)
+    o = oracle3(p, kind, 41)
+    counts, cols, vals = o.rows3(np.arange(o.dim))
+    assert b.nnz3[0] == int(counts.sum())
+    assert np.array_equal(np.diff(rp.cpu().numpy()), counts)
+    assert np.array_equal(col.cpu().numpy(), cols)
+    assert rel(val.cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1)])
+def test_with_kinetic_term(ci, p):
+    b, rp, col, val = gpu3(ci, p, 1, 42, kinetic=1)
+    o = oracle3(p, 1, 42, kinetic=1)
+    counts, cols, vals = o.rows3(np.arange(o.dim))
+    assert np.array_equal(col.cpu().numpy(), cols)
+    assert rel(val.cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+
+
+def test_batch_of_problems(ci):
+    # several bases in one handle: concatenated row_ptr segments, per-basis nnz
+    import torch
+
+    probs = [(2, 1, 2, 1, -1), (2, 2, 2, 0, 1), (3, 0, 2, 1, 1), (2, 2, 4, 0, 1)]
+    b = ci.ci_basis_build(probs)
+    rp, nnz = ci.ci_hamiltonian3_count(b)
+    tb = torch.from_numpy(si.tbme_f32(43, b.n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian3_fill(b, tb, (1, SEED, SCALE), rp)
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy().astype(np.float64)
+    tb = tb.cpu().numpy().astype(np.float64)
+    for k, p in enumerate(probs):
+        inf = b.info[k]
+        o = Oracle(Problem(*p))
+        o.set_tbme(tb[inf["tbme_offset"]:inf["tbme_offset"] + o.n_tbme])
+        o.set_v3(1, SEED, SCALE)
+        counts, cols, vals = o.rows3(np.arange(o.dim))
+        seg = rp[inf["row_ptr_offset"]:inf["row_ptr_offset"] + o.dim + 1]
+        assert nnz[k] == counts.sum() and np.array_equal(np.diff(seg), counts)
+        assert np.array_equal(col[seg[0]:seg[-1]], cols)
+        assert rel(val[seg[0]:seg[-1]], vals) <= VAL_TOL
+
+
+@pytest.mark.parametrize("name,nrows", [("li6_nmax6", 60), ("b10_nmax4", 24)])
+def test_workload_sampled_rows(ci, name, nrows):
+    import torch
+
+    w = si.WORKLOADS[name]
+    b, rp, col, val = gpu3(ci, w["problem"], 1, w["tbme_seed"])
+    D = b.info[0]["dim"]
+    say(name, "D", D, "nnz with the three-body term", b.nnz3[0])
+    o = oracle3(w["problem"], 1, w["tbme_seed"])
+    rows = si.sample_rows(D, nrows, seed=33)
+    counts, cols, vals = o.rows3(rows)
+    r = rp.cpu().numpy()
+    assert np.array_equal(r[rows + 1] - r[rows], counts)
+    pos = torch.from_numpy(np.concatenate([np.arange(r[i], r[i + 1]) for i in rows])).cuda()
+    assert np.array_equal(col[pos].cpu().numpy(), cols)
+    err = rel(val[pos].cpu().numpy().astype(np.float64), vals)
+    say(name, "sampled rows", nrows, "entries", len(cols), "max err / scale", err)
+    assert err <= VAL_TOL
+    del col, val
+    torch.cuda.empty_cache()
+
+
+def test_without_three_body_term_it_is_the_two_body_matrix(ci):
+    # full size (6Li): every entry of the two-body matrix appears with the same
+    # value, every other entry is exactly 0
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp3, col3, val3 = gpu3(ci, w["problem"], 0, w["tbme_seed"])
+    rp2, nnz2 = ci.ci_hamiltonian_count(b)
+    tb = torch.from_numpy(si.tbme_f32(w["tbme_seed"], b.n_tbme)).cuda()
+    col2, val2 = ci.ci_hamiltonian_fill(b, tb, rp2)
+    D = b.info[0]["dim"]
+    rows3 = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp3))
+    key3 = rows3 * D + col3.long()
+    del rows3
+    rows2 = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp2))
+    key2 = rows2 * D + col2.long()
+    del rows2
+    assert bool((key3[1:] > key3[:-1]).all())
+    at = torch.searchsorted(key3, key2)
+    assert bool((key3[at] == key2).all())
+    assert float(((val3[at] - val2).abs()).max()) <= 1e-6 * float(val2.abs().max())
+    mask = torch.ones_like(val3, dtype=torch.bool)
+    mask[at] = False
+    assert bool((val3[mask] == 0).all())
+    say("two-body entries", nnz2[0], "of", b.nnz3[0])

@@ -22,7 +22,7 @@ def declared_symbols():
     with open(os.path.join(ROOT, "include", "ci.h")) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ci_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ci_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_every_declared_symbol():
@@ -157,3 +157,12 @@ def test_threebody_decouple_argument_errors():
     assert L.ci_threebody_work_bytes(0) == 0
     for n in (1, 255, 256, 1000, 1 << 20):
         assert L.ci_threebody_work_bytes(n) >= 5 * n
+
+
+def test_three_body_term_argument_errors():
+    L = ci.load_library()
+    vp = ctypes.c_void_p
+    v3 = ci.ci_v3(ci.CI_V3_SYNTHETIC, 1, 1.0)
+    assert L.ci_hamiltonian3_count(None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian3_fill(None, None, ctypes.byref(v3), None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian3_fill(vp(1), None, None, vp(1), vp(1), vp(1), None) == ci.CI_EINVAL
