@@ -35,9 +35,9 @@ hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps,
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
-hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, int nb, const float* tbme, int v3_kind,
-                          uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val, bool fill,
-                          hipStream_t s);
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, int nb, const float* tbme,
+                          int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val,
+                          bool fill, hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
 }  // namespace ci
@@ -676,6 +676,13 @@ static std::vector<int64_t> h3_dims(const ci_basis* b)
     return d;
 }
 
+static std::vector<int> h3_words(const ci_basis* b)
+{
+    std::vector<int> w(b->host.size());
+    for (size_t p = 0; p < w.size(); p++) w[p] = b->host[p]->W;
+    return w;
+}
+
 int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
@@ -683,7 +690,9 @@ int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)b->info.size();
     const std::vector<int64_t> dims = h3_dims(b);
-    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), n, nullptr, 0, 0, 0.0, row_ptr, nullptr, nullptr, false, s);
+    const std::vector<int> words = h3_words(b);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), n, nullptr, 0, 0, 0.0, row_ptr, nullptr, nullptr,
+                                  false, s);
     if (e != hipSuccess) return hip_fail(e, "three-body count launch");
     e = launch_inclusive_scan(row_ptr, b->n_rowptr, b->d_scan_tmp, s);
     if (e != hipSuccess) return hip_fail(e, "scan launch");
@@ -703,8 +712,9 @@ int ci_hamiltonian3_fill(const ci_basis* b, const float* tbme, const ci_v3* v3, 
     if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
     if (int rc = h3_check(b)) return rc;
     const std::vector<int64_t> dims = h3_dims(b);
-    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), (int)dims.size(), tbme, v3->kind, v3->seed, v3->scale,
-                                  const_cast<int64_t*>(row_ptr), col, val, true, (hipStream_t)stream);
+    const std::vector<int> words = h3_words(b);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), (int)dims.size(), tbme, v3->kind, v3->seed,
+                                  v3->scale, const_cast<int64_t*>(row_ptr), col, val, true, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "three-body fill launch");
     return CI_OK;
 }

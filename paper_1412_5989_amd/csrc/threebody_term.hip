@@ -156,35 +156,46 @@ __device__ double kinetic_pair(const BasisDev& B, int p, int h)
 }
 
 // occupied orbits of the column state below combined orbit o
-__device__ __forceinline__ int below(const uint64_t* yp, const uint64_t* yn, int W, int n, int Z, int o)
+template <int W>
+__device__ __forceinline__ int below(const uint64_t* yp, const uint64_t* yn, int n, int Z, int o)
 {
-    const uint64_t* y = o < n ? yp : yn;
-    const int q = o < n ? o : o - n;
-    int c = o < n ? 0 : Z;
+    const bool prot = o < n;
+    const int q = prot ? o : o - n;
+    int c = prot ? 0 : Z;
+#pragma unroll
     for (int w = 0; w < W; w++) {
-        if (w < (q >> 6)) c += __popcll(y[w]);
-        else if (w == (q >> 6)) c += __popcll(y[w] & ((1ull << (q & 63)) - 1));
+        const uint64_t y = prot ? yp[w] : yn[w];
+        if (w < (q >> 6)) c += __popcll(y);
+        else if (w == (q >> 6)) c += __popcll(y & ((1ull << (q & 63)) - 1));
     }
     return c;
 }
 
+// the k-th of up to three orbits packed 10 bits each
+__device__ __forceinline__ int unpack3(int v, int k) { return (v >> (10 * k)) & 1023; }
+
 // <row|H|column> for states at most three nucleons apart: row words xp, xn,
 // column words yp, yn, the row's occupied orbits occ[A] (combined, ascending).
+template <int W>
 __device__ double entry_value(const BasisDev& B, const float* tb, const V3Param& v3, const uint64_t* xp,
                               const uint64_t* xn, const uint64_t* yp, const uint64_t* yn, const int16_t* occ)
 {
-    const int n = B.nsps, W = B.W, A = B.Z + B.NN;
-    int p[3] = {0, 0, 0}, h[3] = {0, 0, 0}, d = 0, dh = 0;
+    const int n = B.nsps, A = B.Z + B.NN;
+    // particles (row, not column) and holes (column, not row), ascending,
+    // packed 10 bits each
+    int P = 0, H = 0, d = 0, dh = 0;
+#pragma unroll
     for (int s = 0; s < 2; s++)
+#pragma unroll
         for (int w = 0; w < W; w++) {
             const uint64_t X = s ? xn[w] : xp[w], Y = s ? yn[w] : yp[w];
             uint64_t pm = X & ~Y, hm = Y & ~X;
-            while (pm && d < 3) {
-                p[d++] = s * n + w * 64 + __builtin_ctzll(pm);
+            while (pm) {
+                P |= (s * n + w * 64 + __builtin_ctzll(pm)) << (10 * d++);
                 pm &= pm - 1;
             }
-            while (hm && dh < 3) {
-                h[dh++] = s * n + w * 64 + __builtin_ctzll(hm);
+            while (hm) {
+                H |= (s * n + w * 64 + __builtin_ctzll(hm)) << (10 * dh++);
                 hm &= hm - 1;
             }
         }
@@ -201,50 +212,117 @@ __device__ double entry_value(const BasisDev& B, const float* tb, const V3Param&
         }
         return v;
     }
+    const int p0 = unpack3(P, 0), p1 = unpack3(P, 1), p2 = unpack3(P, 2);
+    const int h0 = unpack3(H, 0), h1 = unpack3(H, 1), h2 = unpack3(H, 2);
     int e = -d * (d - 1) / 2;
     for (int k = 0; k < d; k++) {
-        e += below(yp, yn, W, n, B.Z, h[k]) + below(yp, yn, W, n, B.Z, p[k]);
-        for (int m = 0; m < d; m++) e -= h[m] < p[k] ? 1 : 0;
+        const int pk = unpack3(P, k);
+        e += below<W>(yp, yn, n, B.Z, unpack3(H, k)) + below<W>(yp, yn, n, B.Z, pk);
+        e -= (h0 < pk) + (d > 1 && h1 < pk) + (d > 2 && h2 < pk);
     }
-    auto spectator = [&](int o) { return o != p[0] && (d < 2 || o != p[1]) && (d < 3 || o != p[2]); };
+    auto spectator = [&](int o) { return o != p0 && (d < 2 || o != p1) && (d < 3 || o != p2); };
     if (d == 1) {
         for (int a = 0; a < A; a++) {
             const int k = occ[a];
             if (!spectator(k)) continue;
-            v += v2_any(B, tb, p[0], k, h[0], k);
+            v += v2_any(B, tb, p0, k, h0, k);
             if (v3.kind)
                 for (int b = a + 1; b < A; b++) {
                     const int l = occ[b];
-                    if (spectator(l)) v += v3_any(v3, p[0], k, l, h[0], k, l);
+                    if (spectator(l)) v += v3_any(v3, p0, k, l, h0, k, l);
                 }
         }
-        if (B.kinetic) v += kinetic_pair(B, p[0] < n ? p[0] : p[0] - n, h[0] < n ? h[0] : h[0] - n);
+        if (B.kinetic) v += kinetic_pair(B, p0 < n ? p0 : p0 - n, h0 < n ? h0 : h0 - n);
     } else if (d == 2) {
-        v = v2_any(B, tb, p[0], p[1], h[0], h[1]);
+        v = v2_any(B, tb, p0, p1, h0, h1);
         if (v3.kind)
             for (int a = 0; a < A; a++) {
                 const int k = occ[a];
-                if (spectator(k)) v += v3_any(v3, p[0], p[1], k, h[0], h[1], k);
+                if (spectator(k)) v += v3_any(v3, p0, p1, k, h0, h1, k);
             }
     } else if (v3.kind) {
-        v = v3_sorted(v3, p[0], p[1], p[2], h[0], h[1], h[2]);
+        v = v3_sorted(v3, p0, p1, p2, h0, h1, h2);
     }
     return (e & 1) ? -v : v;
 }
 
-__device__ __forceinline__ int dist(const uint64_t* x, const uint64_t* y, int W)
+template <int W>
+__device__ __forceinline__ int dist(const uint64_t* x, const uint64_t* y)
 {
     int c = 0;
+#pragma unroll
     for (int w = 0; w < W; w++) c += __popcll(x[w] ^ y[w]);
     return c >> 1;
 }
 
-template <bool kFill>
+// The move of one species between row words x and column words y:
+// particles (in x, not y) and holes (in y, not x), ascending, as combined
+// indices (species-local + base) packed 10 bits each, and the species' part
+// of the phase, sum of below_y over holes and particles minus the
+// (hole < particle) pairs.  Every proton orbit precedes every neutron orbit,
+// so the phase of the whole move is e_p + e_n - dp*dn - d(d-1)/2 (mod 2).
+struct Move {
+    int P, H, e;
+};
+
+template <int W>
+__device__ __forceinline__ Move species_move(const uint64_t* x, const uint64_t* y, int base)
+{
+    Move m{0, 0, 0};
+    int np = 0, nh = 0, run = 0;  // run: column orbits of the words before w
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        uint64_t pm = x[w] & ~y[w], hm = y[w] & ~x[w];
+        while (pm) {
+            const int b = __builtin_ctzll(pm);
+            m.e += run + __popcll(y[w] & ((1ull << b) - 1));
+            m.P |= (base + w * 64 + b) << (10 * np++);
+            pm &= pm - 1;
+        }
+        while (hm) {
+            const int b = __builtin_ctzll(hm);
+            m.e += run + __popcll(y[w] & ((1ull << b) - 1));
+            m.H |= (base + w * 64 + b) << (10 * nh++);
+            hm &= hm - 1;
+        }
+        run += __popcll(y[w]);
+    }
+    // (hole < particle) pairs inside the species
+    for (int k = 0; k < np; k++)
+        for (int q = 0; q < nh; q++) m.e -= unpack3(m.H, q) < unpack3(m.P, k);
+    return m;
+}
+
+// Value of an entry three nucleons apart from the moves of both species
+// (dp + dn = 3): the phase times V_{particles, holes}.
+__device__ __forceinline__ double value3(const V3Param& v3, const Move& mp, int dp, const Move& mn)
+{
+    if (!v3.kind) return 0.0;
+    const int Pc = mp.P | (mn.P << (10 * dp)), Hc = mp.H | (mn.H << (10 * dp));
+    const double v = v3_sorted(v3, unpack3(Pc, 0), unpack3(Pc, 1), unpack3(Pc, 2), unpack3(Hc, 0), unpack3(Hc, 1),
+                               unpack3(Hc, 2));
+    const int e = mp.e + mn.e - dp * (3 - dp) - 3;
+    return (e & 1) ? -v : v;
+}
+
+// Entries at most two nucleons apart found by the wavefront's joint neutron
+// scans cost 4 to 30 three-body terms, the others (three apart) one; mixed in
+// one wavefront every lane would wait for the dearest.  The scan computes the
+// three-apart values at once and queues the others by class (two apart; one
+// or zero apart), 64 per batch, one entry per lane.
+struct H3Queue {
+    int32_t pos[64];  // offset from the row's first entry
+    int32_t pg[64];   // proton determinant (global index)
+    int32_t ng[64];   // neutron determinant (global index)
+};
+
+template <bool kFill, int W>
 __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, const float* __restrict__ tbme,
                                                          V3Param v3, int64_t* __restrict__ row_ptr,
                                                          int32_t* __restrict__ col, float* __restrict__ val)
 {
     __shared__ int16_t occ_s[kH3Waves][kH3MaxA];
+    __shared__ H3Queue queue_s[kH3Waves][2];
     const BasisDev B = *Bp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * kH3Waves + wave;
@@ -252,7 +330,6 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
     if (i >= B.dim) return;
     const SpeciesDev& SP = B.sp[0];
     const SpeciesDev& SN = B.sp[1];
-    const int W = B.W;
     // block of the row
     int lo = 0, hi = B.nblk;  // blk_off[lo] <= i < blk_off[hi]
     while (hi - lo > 1) {
@@ -264,7 +341,8 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
     const BlockInfo bi = load_block(B.blk, b);
     const int ip = (int)((i - bi.row0) / bi.nkn), in = (int)((i - bi.row0) % bi.nkn);
     const int pg = uni(SP.key_off)[bi.kp] + ip, ng = uni(SN.key_off)[bi.kn] + in;
-    uint64_t xp[kMaxWords] = {0, 0, 0, 0}, xn[kMaxWords] = {0, 0, 0, 0};
+    uint64_t xp[W], xn[W];
+#pragma unroll
     for (int w = 0; w < W; w++) {
         xp[w] = uni(SP.sd)[(int64_t)pg * W + w];
         xn[w] = uni(SN.sd)[(int64_t)ng * W + w];
@@ -273,7 +351,9 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
     if (kFill) {
         if (lane == 0) {
             int k = 0;
+#pragma unroll
             for (int s = 0; s < 2; s++)
+#pragma unroll
                 for (int w = 0; w < W; w++) {
                     uint64_t m = s ? xn[w] : xp[w];
                     while (m) {
@@ -288,6 +368,24 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
     const int64_t n1 = uni(SN.l1_ptr)[ng];
     const int32_t* seg = SN.seg1 + (int64_t)ng * (SN.nk + 1);
     int64_t out = kFill ? uni(row_ptr)[B.row0 + i] : 0;
+    const int64_t row_start = out;
+    H3Queue* Q = queue_s[wave];
+    int nq[2] = {0, 0};
+    auto flush = [&](int k) {
+        wave_fence();
+        if (lane < nq[k]) {
+            const int64_t gp = Q[k].pg[lane], gn = Q[k].ng[lane];
+            uint64_t yp2[W], yn2[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                yp2[w] = SP.sd[gp * W + w];
+                yn2[w] = SN.sd[gn * W + w];
+            }
+            val[row_start + Q[k].pos[lane]] = (float)entry_value<W>(B, tb, v3, xp, xn, yp2, yn2, occ);
+        }
+        wave_fence();
+        nq[k] = 0;
+    };
     for (int b2 = b; b2 < B.nblk; b2++) {
         const BlockInfo bj = load_block(B.blk, b2);
         const int kp0 = uni(SP.key_off)[bj.kp], nKp = uni(SP.key_off)[bj.kp + 1] - kp0;
@@ -296,35 +394,51 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         const int s0 = uni(seg)[bj.kn], s1 = uni(seg)[bj.kn + 1];
         for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
             const int pl = c + lane;
-            uint64_t yp[kMaxWords] = {0, 0, 0, 0};
+            uint64_t yp[W];
             int dp = 4;
-            if (pl < nKp) {
-                for (int w = 0; w < W; w++) yp[w] = SP.sd[(int64_t)(kp0 + pl) * W + w];
-                dp = dist(xp, yp, W);
-            }
+#pragma unroll
+            for (int w = 0; w < W; w++) yp[w] = pl < nKp ? SP.sd[(int64_t)(kp0 + pl) * W + w] : 0ull;
+            if (pl < nKp) dp = dist<W>(xp, yp);
             int cnt = dp == 3 ? (same_n ? 1 : 0) : dp == 2 ? s1 - s0 : 0;
+            // this lane's proton move (fill only)
+            Move mp{0, 0, 0};
+            if (kFill && dp <= 3) mp = species_move<W>(xp, yp, 0);
             uint64_t coop = __ballot(dp <= 1);
             while (coop) {
                 const int L = __builtin_ctzll(coop);
                 coop &= coop - 1;
                 const int excl = read_lane(incl_scan64(cnt) - cnt, L);
                 const int dL = read_lane(dp, L), pL = c + L;
-                uint64_t ypL[kMaxWords] = {0, 0, 0, 0};
+                const Move mpL{read_lane(mp.P, L), read_lane(mp.H, L), read_lane(mp.e, L)};
+                uint64_t ypL[W];
+#pragma unroll
                 for (int w = 0; w < W; w++) ypL[w] = uni(SP.sd)[(int64_t)(kp0 + pL) * W + w];
                 int found = 0;
                 for (int nc = (b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
                     const int nl = nc + lane;
-                    uint64_t yn[kMaxWords] = {0, 0, 0, 0};
-                    bool ok = false;
-                    if (nl < nKn) {
-                        for (int w = 0; w < W; w++) yn[w] = SN.sd[(int64_t)(kn0 + nl) * W + w];
-                        ok = dist(xn, yn, W) <= 3 - dL;
-                    }
+                    uint64_t yn[W];
+#pragma unroll
+                    for (int w = 0; w < W; w++) yn[w] = nl < nKn ? SN.sd[(int64_t)(kn0 + nl) * W + w] : 0ull;
+                    const int dn = dist<W>(xn, yn);
+                    const bool ok = nl < nKn && dn <= 3 - dL;
                     const uint64_t m = __ballot(ok);
-                    if (kFill && ok) {
-                        const int64_t pos = out + excl + found + __popcll(m & ((1ull << lane) - 1));
-                        col[pos] = bj.row0 + pL * nKn + nl;
-                        val[pos] = (float)entry_value(B, tb, v3, xp, xn, ypL, yn, occ);
+                    if (kFill) {
+                        const uint64_t below_lane = (1ull << lane) - 1;
+                        const int cls = !ok ? -1 : dL + dn == 3 ? 2 : dL + dn == 2 ? 0 : 1;
+                        const uint64_t mq[2] = {__ballot(cls == 0), __ballot(cls == 1)};
+                        for (int k = 0; k < 2; k++)
+                            if (nq[k] + __popcll(mq[k]) > 64) flush(k);
+                        const int64_t pos = out + excl + found + __popcll(m & below_lane);
+                        if (ok) col[pos] = bj.row0 + pL * nKn + nl;
+                        if (cls == 2) val[pos] = (float)value3(v3, mpL, dL, species_move<W>(xn, yn, B.nsps));
+                        if (cls == 0 || cls == 1) {
+                            const int k = nq[cls] + __popcll(mq[cls] & below_lane);
+                            Q[cls].pos[k] = (int32_t)(pos - row_start);
+                            Q[cls].pg[k] = kp0 + pL;
+                            Q[cls].ng[k] = kn0 + nl;
+                        }
+                        nq[0] += __popcll(mq[0]);
+                        nq[1] += __popcll(mq[1]);
                     }
                     found += __popcll(m);
                 }
@@ -335,49 +449,63 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
                 int64_t pos = out + incl - cnt;
                 if (dp == 3) {
                     col[pos] = bj.row0 + pl * nKn + in;
-                    val[pos] = (float)entry_value(B, tb, v3, xp, xn, yp, xn, occ);
+                    val[pos] = (float)value3(v3, mp, 3, Move{0, 0, 0});
                 } else {
                     for (int r = s0; r < s1; r++, pos++) {
-                        const int nl = (int)(SN.l1[n1 + r] & kRecLocalMask);
-                        uint64_t yn[kMaxWords] = {0, 0, 0, 0};
-                        for (int w = 0; w < W; w++) yn[w] = SN.sd[(int64_t)(kn0 + nl) * W + w];
+                        // the record is the same for every lane: one neutron move
+                        const int nl = (int)(uni(SN.l1)[n1 + r] & kRecLocalMask);
+                        uint64_t yn[W];
+#pragma unroll
+                        for (int w = 0; w < W; w++) yn[w] = uni(SN.sd)[(int64_t)(kn0 + nl) * W + w];
                         col[pos] = bj.row0 + pl * nKn + nl;
-                        val[pos] = (float)entry_value(B, tb, v3, xp, xn, yp, yn, occ);
+                        if (nl == in && same_n)
+                            val[pos] = (float)entry_value<W>(B, tb, v3, xp, xn, yp, yn, occ);
+                        else
+                            val[pos] = (float)value3(v3, mp, 2, species_move<W>(xn, yn, B.nsps));
                     }
                 }
             }
             out += read_lane(incl, 63);
         }
     }
+    if (kFill) {
+        flush(0);
+        flush(1);
+    }
     if (!kFill && lane == 0) row_ptr[B.row0 + i + 1] = out;
 }
 
 }  // namespace
 
+template <int W>
+static void launch_one(bool fill, unsigned grid, const BasisDev* B, const float* tbme, const V3Param& v3,
+                       int64_t* row_ptr, int32_t* col, float* val, hipStream_t s)
+{
+    if (fill)
+        hipLaunchKernelGGL((h3_rows<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, tbme, v3, row_ptr, col, val);
+    else
+        hipLaunchKernelGGL((h3_rows<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, tbme, v3, row_ptr, col, val);
+}
+
 // One launch per basis of the handle: count (row_ptr[R_b + 1 + i] = entries
 // of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]).
-hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, int nb, const float* tbme, int v3_kind,
-                          uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val, bool fill,
-                          hipStream_t s)
+// words[p]: 64-bit words per species bitstring of basis p (1..4).
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, int nb, const float* tbme,
+                          int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val,
+                          bool fill, hipStream_t s)
 {
     const V3Param v3{v3_kind, v3_seed, v3_scale};
     for (int p = 0; p < nb; p++) {
-        const int64_t D = dims[p];
-        const unsigned grid = (unsigned)((D + kH3Waves - 1) / kH3Waves);
-        if (grid == 0) {
-            if (!fill) {
-                // an empty basis still owns its first row_ptr slot
-                hipLaunchKernelGGL(h3_rows<false>, dim3(1), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr,
-                                   col, val);
-            }
-            continue;
+        // an empty basis still owns its first row_ptr slot (written by the count)
+        const unsigned grid = (unsigned)((dims[p] + kH3Waves - 1) / kH3Waves);
+        if (grid == 0 && fill) continue;
+        const unsigned g = grid > 0 ? grid : 1;
+        switch (words[p]) {
+        case 1: launch_one<1>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
+        case 2: launch_one<2>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
+        case 3: launch_one<3>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
+        default: launch_one<4>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
         }
-        if (fill)
-            hipLaunchKernelGGL(h3_rows<true>, dim3(grid), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr, col,
-                               val);
-        else
-            hipLaunchKernelGGL(h3_rows<false>, dim3(grid), dim3(64 * kH3Waves), 0, s, bases + p, tbme, v3, row_ptr,
-                               col, val);
     }
     return hipGetLastError();
 }
