@@ -242,6 +242,53 @@ def run_threebody(ci, torch, with_oracle, n1max=6, n3max=6):
     return res
 
 
+def run_three_body_term(ci, torch, prob, tbme_seed, with_oracle, reps=3):
+    """The matrix with a three-body term (states at most three nucleons
+    apart, synthetic interaction): count and fill timed with HIP events."""
+    import seeded_inputs as si
+
+    b = ci.ci_basis_build([prob])
+    stream = torch.cuda.current_stream()
+    ev_c, ev_f = EventTimer(torch, stream), EventTimer(torch, stream)
+    rp, nnz = ci.ci_hamiltonian3_count(b)
+    nnz = nnz[0]
+    D = b.info[0]["dim"]
+    tb = torch.from_numpy(si.tbme_f32(tbme_seed, b.n_tbme)).cuda()
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    v3 = (ci.CI_V3_SYNTHETIC, 0x5EED3, 1.0)
+    ci.ci_hamiltonian3_fill(b, tb, v3, rp, col, val)
+    for _ in range(reps):
+        with ev_c:
+            ci.ci_hamiltonian3_count(b)
+        with ev_f:
+            ci.ci_hamiltonian3_fill(b, tb, v3, rp, col, val)
+    torch.cuda.synchronize()
+    fill_ms = ev_f.mean_ms()
+    alg = 8 * nnz + 8 * (D + 1)  # col + val per entry, row_ptr per row
+    res = {"workload": "%s with a three-body term (d <= 3)" % "Z=%d N=%d Nmax=%d 2M=%d" % tuple(prob[:4]),
+           "nnz": nnz, "count_ms_incl_sync": ev_c.mean_ms(), "fill_ms": fill_ms,
+           "fill_nnz_per_s": nnz / (fill_ms * 1e-3), "fill_alg_GBps": alg / (fill_ms * 1e-3) / 1e9,
+           "fill_frac_of_hbm_peak": alg / (fill_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del col, val
+    b.free()
+    if with_oracle:
+        import oracle
+
+        o = oracle.Oracle(oracle.Problem(*prob))
+        o.set_tbme(si.tbme_f32(tbme_seed, o.n_tbme).astype(np.float64))
+        o.set_v3(o.V3_SYNTHETIC, 0x5EED3, 1.0)
+        rows = si.sample_rows(o.dim, 16, seed=7)
+        o.rows3(rows[:2])  # warm-up
+        t0 = time.perf_counter()
+        counts, _, _ = o.rows3(rows)
+        t = time.perf_counter() - t0
+        res.update({"cpu_oracle_nnz_per_s": float(counts.sum()) / t, "cpu_oracle_sample": "16 sampled rows",
+                    "cpu_oracle_cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))})
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_batched(ci, torch, steps, warmup):
     """64 bases in one handle; fill + vjp captured in one HIP graph."""
     import seeded_inputs as si
@@ -460,6 +507,8 @@ def main():
     res["lanczos"] = run_lanczos(ci, torch, prob, w["tbme_seed"])
     log("three-body")
     res["threebody"] = run_threebody(ci, torch, not args.no_cpu_baseline)
+    log("three-body term")
+    res["three_body_term"] = run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)
     if not args.no_batched:
         log("batched")
         res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)
