@@ -195,12 +195,17 @@ typedef struct {
 } ci_v3;
 
 /* Count pass of the d <= 3 structure: row_ptr (device int64, sum of (D_b + 1)),
- * nnz (host int64[n_probs]).  Synchronizes the stream. */
-int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
+ * nnz (host int64[n_probs]).  Synchronizes the stream.  The first three-body
+ * call on a handle also builds, and the handle keeps until ci_basis_free, an
+ * index of the neutron determinants within two nucleons of each other in
+ * every key (device memory; a few MB to tens of MB); calls on one handle
+ * must be ordered. */
+int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
 /* Fill pass: col (device int32), val (device FP32, FP64 sums) at row_ptr's
- * positions; tbme as for ci_hamiltonian_fill; v3 (host).  Asynchronous. */
-int ci_hamiltonian3_fill(const ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr,
-                         int32_t* col, float* val, ci_stream stream);
+ * positions; tbme as for ci_hamiltonian_fill; v3 (host).  Asynchronous once
+ * the handle holds its index (else it first builds it, synchronizing). */
+int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
+                         float* val, ci_stream stream);
 
 /* y = H x for problem `prob` of the handle, H in full CSR form (row_ptr, col,
  * val from ci_hamiltonian_count_full / _fill_full; the problem's own row

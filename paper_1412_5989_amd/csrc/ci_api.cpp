@@ -35,9 +35,11 @@ hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps,
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
-hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, int nb, const float* tbme,
-                          int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val,
-                          bool fill, hipStream_t s);
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
+                          int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
+                          int32_t* col, float* val, bool fill, hipStream_t s);
+hipError_t launch_h3_index(bool fill, const BasisDev* B, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
+                           uint32_t* rec, hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
 }  // namespace ci
@@ -80,10 +82,15 @@ struct ci_basis {
     std::vector<ci_problem> probs;          // key of the process-wide tuning cache
     int64_t n_rowptr = 0;
     int64_t n_tbme = 0;
+    // neutron partner index of the three-body walk (built on first use):
+    // per basis (seg, ptr, rec) device pointers, and the allocations
+    std::vector<const void*> h3_index;
+    std::vector<void*> h3_mem;
     ~ci_basis()
     {
         if (arena) hipFree(arena);
         if (lists) hipFree(lists);
+        for (void* m : h3_mem) hipFree(m);
     }
 };
 
@@ -669,6 +676,54 @@ static int h3_check(const ci_basis* b)
     return CI_OK;
 }
 
+// The neutron partner index of every basis (d <= 2 partners in every key):
+// count, scan, read back the length, fill.  Synchronizes the stream once per
+// basis, on the first three-body call of the handle.
+static int h3_build_index(ci_basis* b, hipStream_t s)
+{
+    if (!b->h3_index.empty()) return CI_OK;
+    const size_t n = b->host.size();
+    std::vector<const void*> idx(3 * n, nullptr);
+    std::vector<void*> mem;
+    auto cleanup = [&]() {
+        for (void* m : mem) hipFree(m);
+    };
+    for (size_t p = 0; p < n; p++) {
+        const HostBasis& hb = *b->host[p];
+        const HostSpecies& N = hb.sp[1];
+        const int64_t nsd = N.nsd();
+        const size_t seg_bytes = ((size_t)nsd * (N.nk() + 1) * 4 + 255) / 256 * 256;
+        const size_t ptr_bytes = ((size_t)(nsd + 1) * 8 + 255) / 256 * 256;
+        void* head = nullptr;
+        hipError_t e = hipMalloc(&head, seg_bytes + 2 * ptr_bytes);
+        if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index)");
+        mem.push_back(head);
+        int32_t* seg = (int32_t*)head;
+        int64_t* ptr = (int64_t*)((char*)head + seg_bytes);
+        int64_t* tmp = (int64_t*)((char*)head + seg_bytes + ptr_bytes);
+        int64_t total = 0;
+        if (nsd > 0) {  // (with no determinant the basis has no row to read the index)
+            e = launch_h3_index(false, b->d_bases + p, nsd, hb.W, seg, ptr, nullptr, s);
+            if (e == hipSuccess) e = launch_inclusive_scan(ptr, nsd + 1, tmp, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(&total, ptr + nsd, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index count");
+        void* rec = nullptr;
+        e = hipMalloc(&rec, (size_t)std::max<int64_t>(total, 1) * 4);
+        if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index records)");
+        mem.push_back(rec);
+        e = launch_h3_index(true, b->d_bases + p, nsd, hb.W, seg, ptr, (uint32_t*)rec, s);
+        if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index fill");
+        idx[3 * p] = seg;
+        idx[3 * p + 1] = ptr;
+        idx[3 * p + 2] = rec;
+    }
+    b->h3_index = idx;
+    b->h3_mem = mem;
+    return CI_OK;
+}
+
 static std::vector<int64_t> h3_dims(const ci_basis* b)
 {
     std::vector<int64_t> d(b->info.size());
@@ -683,16 +738,17 @@ static std::vector<int> h3_words(const ci_basis* b)
     return w;
 }
 
-int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
     if (int rc = h3_check(b)) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc = h3_build_index(b, s)) return rc;
     const int n = (int)b->info.size();
     const std::vector<int64_t> dims = h3_dims(b);
     const std::vector<int> words = h3_words(b);
-    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), n, nullptr, 0, 0, 0.0, row_ptr, nullptr, nullptr,
-                                  false, s);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), b->h3_index.data(), n, nullptr, 0, 0, 0.0,
+                                  row_ptr, nullptr, nullptr, false, s);
     if (e != hipSuccess) return hip_fail(e, "three-body count launch");
     e = launch_inclusive_scan(row_ptr, b->n_rowptr, b->d_scan_tmp, s);
     if (e != hipSuccess) return hip_fail(e, "scan launch");
@@ -705,16 +761,18 @@ int ci_hamiltonian3_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_
     return CI_OK;
 }
 
-int ci_hamiltonian3_fill(const ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr,
-                         int32_t* col, float* val, ci_stream stream)
+int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
+                         float* val, ci_stream stream)
 {
     if (!b || !v3 || !row_ptr || !col || !val || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
     if (int rc = h3_check(b)) return rc;
+    if (int rc = h3_build_index(b, (hipStream_t)stream)) return rc;
     const std::vector<int64_t> dims = h3_dims(b);
     const std::vector<int> words = h3_words(b);
-    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), (int)dims.size(), tbme, v3->kind, v3->seed,
-                                  v3->scale, const_cast<int64_t*>(row_ptr), col, val, true, (hipStream_t)stream);
+    hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), b->h3_index.data(), (int)dims.size(), tbme,
+                                  v3->kind, v3->seed, v3->scale, const_cast<int64_t*>(row_ptr), col, val, true,
+                                  (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "three-body fill launch");
     return CI_OK;
 }

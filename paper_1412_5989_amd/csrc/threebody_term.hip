@@ -305,6 +305,53 @@ __device__ __forceinline__ double value3(const V3Param& v3, const Move& mp, int 
     return (e & 1) ? -v : v;
 }
 
+// Neutron partner index of the three-body walk: for every neutron
+// determinant x and every neutron key, the determinants y of that key with
+// d(x, y) <= 2, ascending, as records local index | d << 24 (the two-body
+// path's lists hold d <= 1 in every key but d = 2 only in keys of x's own 2M
+// and parity; a proton one nucleon away moves the neutron key).
+struct H3Index {
+    const int32_t* seg;  // [nsd][nk + 1] first record of each key in x's list
+    const int64_t* ptr;  // [nsd + 1] start of x's list
+    const uint32_t* rec;
+};
+
+template <bool kFill, int W>
+__global__ void __launch_bounds__(64 * kH3Waves) h3_index(const BasisDev* __restrict__ Bp, int32_t* __restrict__ seg,
+                                                          int64_t* __restrict__ ptr, uint32_t* __restrict__ rec)
+{
+    const BasisDev B = *Bp;
+    const SpeciesDev& S = B.sp[1];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t x = (int64_t)blockIdx.x * kH3Waves + wave;
+    if (!kFill && x == 0 && lane == 0) ptr[0] = 0;
+    if (x >= S.nsd) return;
+    uint64_t xw[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) xw[w] = uni(S.sd)[x * W + w];
+    const int64_t base = kFill ? uni(ptr)[x] : 0;
+    int run = 0;
+    for (int k = 0; k < S.nk; k++) {
+        if (!kFill && lane == 0) seg[x * (S.nk + 1) + k] = run;
+        const int y0 = uni(S.key_off)[k], y1 = uni(S.key_off)[k + 1];
+        for (int c = y0; c < y1; c += 64) {
+            const int y = c + lane;
+            uint64_t yw[W];
+#pragma unroll
+            for (int w = 0; w < W; w++) yw[w] = y < y1 ? S.sd[(int64_t)y * W + w] : 0ull;
+            const int d = dist<W>(xw, yw);
+            const bool ok = y < y1 && d <= 2;
+            const uint64_t m = __ballot(ok);
+            if (kFill && ok) rec[base + run + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)(y - y0) | ((uint32_t)d << 24);
+            run += __popcll(m);
+        }
+    }
+    if (!kFill && lane == 0) {
+        seg[x * (S.nk + 1) + S.nk] = run;
+        ptr[x + 1] = run;
+    }
+}
+
 // Entries at most two nucleons apart found by the wavefront's joint neutron
 // scans cost 4 to 30 three-body terms, the others (three apart) one; mixed in
 // one wavefront every lane would wait for the dearest.  The scan computes the
@@ -317,12 +364,14 @@ struct H3Queue {
 };
 
 template <bool kFill, int W>
-__global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, const float* __restrict__ tbme,
-                                                         V3Param v3, int64_t* __restrict__ row_ptr,
-                                                         int32_t* __restrict__ col, float* __restrict__ val)
+__global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, H3Index X,
+                                                         const float* __restrict__ tbme, V3Param v3,
+                                                         int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                         float* __restrict__ val)
 {
     __shared__ int16_t occ_s[kH3Waves][kH3MaxA];
     __shared__ H3Queue queue_s[kH3Waves][2];
+    __shared__ uint8_t lanes_s[kH3Waves][64];
     const BasisDev B = *Bp;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * kH3Waves + wave;
@@ -365,8 +414,10 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         wave_fence();
     }
     const float* tb = tbme ? tbme + B.tbme0 : nullptr;
-    const int64_t n1 = uni(SN.l1_ptr)[ng];
     const int32_t* seg = SN.seg1 + (int64_t)ng * (SN.nk + 1);
+    const uint64_t* rec1 = SN.l1 + uni(SN.l1_ptr)[ng];
+    const int32_t* seg2 = X.seg + (int64_t)ng * (SN.nk + 1);
+    const uint32_t* rec2 = X.rec + uni(X.ptr)[ng];
     int64_t out = kFill ? uni(row_ptr)[B.row0 + i] : 0;
     const int64_t row_start = out;
     H3Queue* Q = queue_s[wave];
@@ -391,7 +442,8 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         const int kp0 = uni(SP.key_off)[bj.kp], nKp = uni(SP.key_off)[bj.kp + 1] - kp0;
         const int kn0 = uni(SN.key_off)[bj.kn], nKn = bj.nkn;
         const bool same_n = bj.kn == bi.kn;
-        const int s0 = uni(seg)[bj.kn], s1 = uni(seg)[bj.kn + 1];
+        const int s0 = uni(seg)[bj.kn], n_le1 = uni(seg)[bj.kn + 1] - s0;  // neutrons of the key at most one away
+        const int r0 = uni(seg2)[bj.kn], r1 = uni(seg2)[bj.kn + 1];  // ... at most two away
         for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
             const int pl = c + lane;
             uint64_t yp[W];
@@ -399,20 +451,17 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
 #pragma unroll
             for (int w = 0; w < W; w++) yp[w] = pl < nKp ? SP.sd[(int64_t)(kp0 + pl) * W + w] : 0ull;
             if (pl < nKp) dp = dist<W>(xp, yp);
-            int cnt = dp == 3 ? (same_n ? 1 : 0) : dp == 2 ? s1 - s0 : 0;
+            int cnt = dp == 3 ? (same_n ? 1 : 0) : dp == 2 ? n_le1 : dp == 1 ? r1 - r0 : 0;
             // this lane's proton move (fill only)
             Move mp{0, 0, 0};
             if (kFill && dp <= 3) mp = species_move<W>(xp, yp, 0);
-            uint64_t coop = __ballot(dp <= 1);
+            // the row's own proton determinant (zero away): the wavefront scans the neutron key
+            uint64_t coop = __ballot(dp == 0);
             while (coop) {
                 const int L = __builtin_ctzll(coop);
                 coop &= coop - 1;
                 const int excl = read_lane(incl_scan64(cnt) - cnt, L);
-                const int dL = read_lane(dp, L), pL = c + L;
-                const Move mpL{read_lane(mp.P, L), read_lane(mp.H, L), read_lane(mp.e, L)};
-                uint64_t ypL[W];
-#pragma unroll
-                for (int w = 0; w < W; w++) ypL[w] = uni(SP.sd)[(int64_t)(kp0 + pL) * W + w];
+                const int pL = c + L;
                 int found = 0;
                 for (int nc = (b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
                     const int nl = nc + lane;
@@ -420,17 +469,17 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
 #pragma unroll
                     for (int w = 0; w < W; w++) yn[w] = nl < nKn ? SN.sd[(int64_t)(kn0 + nl) * W + w] : 0ull;
                     const int dn = dist<W>(xn, yn);
-                    const bool ok = nl < nKn && dn <= 3 - dL;
+                    const bool ok = nl < nKn && dn <= 3;
                     const uint64_t m = __ballot(ok);
                     if (kFill) {
                         const uint64_t below_lane = (1ull << lane) - 1;
-                        const int cls = !ok ? -1 : dL + dn == 3 ? 2 : dL + dn == 2 ? 0 : 1;
+                        const int cls = !ok ? -1 : dn == 3 ? 2 : dn == 2 ? 0 : 1;
                         const uint64_t mq[2] = {__ballot(cls == 0), __ballot(cls == 1)};
                         for (int k = 0; k < 2; k++)
                             if (nq[k] + __popcll(mq[k]) > 64) flush(k);
                         const int64_t pos = out + excl + found + __popcll(m & below_lane);
                         if (ok) col[pos] = bj.row0 + pL * nKn + nl;
-                        if (cls == 2) val[pos] = (float)value3(v3, mpL, dL, species_move<W>(xn, yn, B.nsps));
+                        if (cls == 2) val[pos] = (float)value3(v3, Move{0, 0, 0}, 0, species_move<W>(xn, yn, B.nsps));
                         if (cls == 0 || cls == 1) {
                             const int k = nq[cls] + __popcll(mq[cls] & below_lane);
                             Q[cls].pos[k] = (int32_t)(pos - row_start);
@@ -444,25 +493,66 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
                 }
                 if (lane == L) cnt = found;
             }
-            const int incl = incl_scan64(cnt);
-            if (kFill && cnt > 0 && dp >= 2) {
-                int64_t pos = out + incl - cnt;
-                if (dp == 3) {
-                    col[pos] = bj.row0 + pl * nKn + in;
-                    val[pos] = (float)value3(v3, mp, 3, Move{0, 0, 0});
-                } else {
-                    for (int r = s0; r < s1; r++, pos++) {
-                        // the record is the same for every lane: one neutron move
-                        const int nl = (int)(uni(SN.l1)[n1 + r] & kRecLocalMask);
+            const int incl = incl_scan64(cnt), excl = incl - cnt;
+            if (kFill) {
+                if (cnt > 0 && dp == 3) {
+                    col[out + excl] = bj.row0 + pl * nKn + in;
+                    val[out + excl] = (float)value3(v3, mp, 3, Move{0, 0, 0});
+                }
+                // (proton, neutron record) pairs, 64 per step: one proton away
+                // with the neutrons at most two away, two away with those at
+                // most one away (the two-body path's list)
+                uint8_t* lanes = lanes_s[wave];
+                const uint64_t below_lane = (1ull << lane) - 1;
+                for (int cp = 1; cp <= 2; cp++) {
+                    const uint64_t mk = __ballot(dp == cp);
+                    const int nr = cp == 1 ? r1 - r0 : n_le1;
+                    const int total = __popcll(mk) * nr;
+                    if (total == 0) continue;
+                    if (dp == cp) lanes[__popcll(mk & below_lane)] = (uint8_t)lane;
+                    wave_fence();
+                    for (int t0 = 0; t0 < total; t0 += 64) {
+                        const int t = t0 + lane;
+                        const bool act = t < total;
+                        const int j = act ? t / nr : 0, r = act ? t - j * nr : 0;
+                        const int L = lanes[j];
+                        const int plL = __builtin_amdgcn_ds_bpermute(L << 2, pl);
+                        const int exL = __builtin_amdgcn_ds_bpermute(L << 2, excl);
+                        const Move mpL{__builtin_amdgcn_ds_bpermute(L << 2, mp.P),
+                                       __builtin_amdgcn_ds_bpermute(L << 2, mp.H),
+                                       __builtin_amdgcn_ds_bpermute(L << 2, mp.e)};
+                        int nl = 0, dn = 3;
+                        if (act) {
+                            if (cp == 1) {
+                                const uint32_t rc = rec2[r0 + r];
+                                nl = (int)(rc & 0xffffff);
+                                dn = (int)(rc >> 24);
+                            } else {
+                                const uint64_t rc = rec1[s0 + r];
+                                nl = (int)(rc & kRecLocalMask);
+                                dn = (int)((rc >> 57) & 3);
+                            }
+                        }
                         uint64_t yn[W];
 #pragma unroll
-                        for (int w = 0; w < W; w++) yn[w] = uni(SN.sd)[(int64_t)(kn0 + nl) * W + w];
-                        col[pos] = bj.row0 + pl * nKn + nl;
-                        if (nl == in && same_n)
-                            val[pos] = (float)entry_value<W>(B, tb, v3, xp, xn, yp, yn, occ);
-                        else
-                            val[pos] = (float)value3(v3, mp, 2, species_move<W>(xn, yn, B.nsps));
+                        for (int w = 0; w < W; w++) yn[w] = act ? SN.sd[(int64_t)(kn0 + nl) * W + w] : 0ull;
+                        const int cls = !act ? -1 : cp + dn == 3 ? 2 : cp + dn == 2 ? 0 : 1;
+                        const uint64_t mq[2] = {__ballot(cls == 0), __ballot(cls == 1)};
+                        for (int k = 0; k < 2; k++)
+                            if (nq[k] + __popcll(mq[k]) > 64) flush(k);
+                        const int64_t pos = out + exL + r;
+                        if (act) col[pos] = bj.row0 + plL * nKn + nl;
+                        if (cls == 2) val[pos] = (float)value3(v3, mpL, cp, species_move<W>(xn, yn, B.nsps));
+                        if (cls == 0 || cls == 1) {
+                            const int k = nq[cls] + __popcll(mq[cls] & below_lane);
+                            Q[cls].pos[k] = (int32_t)(pos - row_start);
+                            Q[cls].pg[k] = kp0 + plL;
+                            Q[cls].ng[k] = kn0 + nl;
+                        }
+                        nq[0] += __popcll(mq[0]);
+                        nq[1] += __popcll(mq[1]);
                     }
+                    wave_fence();
                 }
             }
             out += read_lane(incl, 63);
@@ -478,21 +568,51 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
 }  // namespace
 
 template <int W>
-static void launch_one(bool fill, unsigned grid, const BasisDev* B, const float* tbme, const V3Param& v3,
-                       int64_t* row_ptr, int32_t* col, float* val, hipStream_t s)
+static void launch_one(bool fill, unsigned grid, const BasisDev* B, const H3Index& X, const float* tbme,
+                       const V3Param& v3, int64_t* row_ptr, int32_t* col, float* val, hipStream_t s)
 {
     if (fill)
-        hipLaunchKernelGGL((h3_rows<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, tbme, v3, row_ptr, col, val);
+        hipLaunchKernelGGL((h3_rows<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, X, tbme, v3, row_ptr, col,
+                           val);
     else
-        hipLaunchKernelGGL((h3_rows<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, tbme, v3, row_ptr, col, val);
+        hipLaunchKernelGGL((h3_rows<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, X, tbme, v3, row_ptr, col,
+                           val);
+}
+
+template <int W>
+static void launch_index(bool fill, unsigned grid, const BasisDev* B, int32_t* seg, int64_t* ptr, uint32_t* rec,
+                         hipStream_t s)
+{
+    if (fill)
+        hipLaunchKernelGGL((h3_index<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, seg, ptr, rec);
+    else
+        hipLaunchKernelGGL((h3_index<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, seg, ptr, rec);
+}
+
+// Neutron partner index of one basis (nsd neutron determinants, nk keys, W
+// words): pass 1 writes seg and the list lengths into ptr[1..nsd] (ptr[0] = 0;
+// the caller scans ptr), pass 2 the records.
+hipError_t launch_h3_index(bool fill, const BasisDev* B, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
+                           uint32_t* rec, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((nsd + kH3Waves - 1) / kH3Waves);
+    if (grid == 0) return hipSuccess;
+    switch (W) {
+    case 1: launch_index<1>(fill, grid, B, seg, ptr, rec, s); break;
+    case 2: launch_index<2>(fill, grid, B, seg, ptr, rec, s); break;
+    case 3: launch_index<3>(fill, grid, B, seg, ptr, rec, s); break;
+    default: launch_index<4>(fill, grid, B, seg, ptr, rec, s); break;
+    }
+    return hipGetLastError();
 }
 
 // One launch per basis of the handle: count (row_ptr[R_b + 1 + i] = entries
 // of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]).
-// words[p]: 64-bit words per species bitstring of basis p (1..4).
-hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, int nb, const float* tbme,
-                          int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr, int32_t* col, float* val,
-                          bool fill, hipStream_t s)
+// words[p]: 64-bit words per species bitstring of basis p (1..4); index[p]:
+// its neutron partner index (seg, ptr, rec).
+hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
+                          int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
+                          int32_t* col, float* val, bool fill, hipStream_t s)
 {
     const V3Param v3{v3_kind, v3_seed, v3_scale};
     for (int p = 0; p < nb; p++) {
@@ -500,11 +620,12 @@ hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int*
         const unsigned grid = (unsigned)((dims[p] + kH3Waves - 1) / kH3Waves);
         if (grid == 0 && fill) continue;
         const unsigned g = grid > 0 ? grid : 1;
+        const H3Index X{(const int32_t*)index[3 * p], (const int64_t*)index[3 * p + 1], (const uint32_t*)index[3 * p + 2]};
         switch (words[p]) {
-        case 1: launch_one<1>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
-        case 2: launch_one<2>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
-        case 3: launch_one<3>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
-        default: launch_one<4>(fill, g, bases + p, tbme, v3, row_ptr, col, val, s); break;
+        case 1: launch_one<1>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
+        case 2: launch_one<2>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
+        case 3: launch_one<3>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
+        default: launch_one<4>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
         }
     }
     return hipGetLastError();
