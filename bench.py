@@ -356,6 +356,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-threebody", action="store_true",
                     help="run only the three-body decoupling section (for counter and trace runs of its kernels)")
+    ap.add_argument("--only-three-body-term", action="store_true",
+                    help="run only the section of the matrix with a three-body term (counter and trace runs)")
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed construction steps (no ceiling probes, Lanczos, three-body or "
                          "batched sections): for counter and trace runs of the step's kernels")
@@ -384,6 +386,11 @@ def main():
     w = si.WORKLOADS[args.workload]
     prob = w["problem"]
     stream = torch.cuda.current_stream()
+    if args.only_three_body_term:
+        res = {"three_body_term": run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)}
+        copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(res), flush=True)
+        return
 
     # inputs resident in HBM before the timed region: the two-body table and
     # the upstream gradient (which needs the structure, so one setup pass)
