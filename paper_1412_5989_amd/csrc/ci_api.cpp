@@ -764,7 +764,7 @@ int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream
 int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
                          float* val, ci_stream stream)
 {
-    if (!b || !v3 || !row_ptr || !col || !val || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !v3 || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
     if (int rc = h3_check(b)) return rc;
     if (int rc = h3_build_index(b, (hipStream_t)stream)) return rc;

@@ -166,3 +166,4 @@ def test_three_body_term_argument_errors():
     assert L.ci_hamiltonian3_count(None, None, None, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian3_fill(None, None, ctypes.byref(v3), None, None, None, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian3_fill(vp(1), None, None, vp(1), vp(1), vp(1), None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian3_fill(vp(1), None, ctypes.byref(v3), None, vp(1), vp(1), None) == ci.CI_EINVAL
