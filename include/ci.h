@@ -197,7 +197,7 @@ typedef struct {
 /* Count pass of the d <= 3 structure: row_ptr (device int64, sum of (D_b + 1)),
  * nnz (host int64[n_probs]).  Synchronizes the stream.  The first three-body
  * call on a handle also builds, and the handle keeps until ci_basis_free, an
- * index of the neutron determinants within two nucleons of each other in
+ * index per species of the determinants within two nucleons of each other in
  * every key (device memory; a few MB to tens of MB); calls on one handle
  * must be ordered. */
 int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);

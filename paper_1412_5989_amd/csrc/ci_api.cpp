@@ -38,8 +38,8 @@ size_t lanczos_work_bytes(int64_t dim, int max_iter);
 hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
                           int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
                           int32_t* col, float* val, bool fill, hipStream_t s);
-hipError_t launch_h3_index(bool fill, const BasisDev* B, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
-                           uint32_t* rec, hipStream_t s);
+hipError_t launch_h3_index(bool fill, const BasisDev* B, int species, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
+                           uint64_t* rec, hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
                        int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
 }  // namespace ci
@@ -676,48 +676,52 @@ static int h3_check(const ci_basis* b)
     return CI_OK;
 }
 
-// The neutron partner index of every basis (d <= 2 partners in every key):
+// The partner indexes of every basis, neutrons and protons (d <= 2 partners
+// in every key):
 // count, scan, read back the length, fill.  Synchronizes the stream once per
 // basis, on the first three-body call of the handle.
 static int h3_build_index(ci_basis* b, hipStream_t s)
 {
     if (!b->h3_index.empty()) return CI_OK;
     const size_t n = b->host.size();
-    std::vector<const void*> idx(3 * n, nullptr);
+    std::vector<const void*> idx(6 * n, nullptr);
     std::vector<void*> mem;
     auto cleanup = [&]() {
         for (void* m : mem) hipFree(m);
     };
     for (size_t p = 0; p < n; p++) {
         const HostBasis& hb = *b->host[p];
-        const HostSpecies& N = hb.sp[1];
-        const int64_t nsd = N.nsd();
-        const size_t seg_bytes = ((size_t)nsd * (N.nk() + 1) * 4 + 255) / 256 * 256;
-        const size_t ptr_bytes = ((size_t)(nsd + 1) * 8 + 255) / 256 * 256;
-        void* head = nullptr;
-        hipError_t e = hipMalloc(&head, seg_bytes + 2 * ptr_bytes);
-        if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index)");
-        mem.push_back(head);
-        int32_t* seg = (int32_t*)head;
-        int64_t* ptr = (int64_t*)((char*)head + seg_bytes);
-        int64_t* tmp = (int64_t*)((char*)head + seg_bytes + ptr_bytes);
-        int64_t total = 0;
-        if (nsd > 0) {  // (with no determinant the basis has no row to read the index)
-            e = launch_h3_index(false, b->d_bases + p, nsd, hb.W, seg, ptr, nullptr, s);
-            if (e == hipSuccess) e = launch_inclusive_scan(ptr, nsd + 1, tmp, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(&total, ptr + nsd, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (int k = 0; k < 2; k++) {
+            const int species = k == 0 ? 1 : 0;  // neutrons first, then protons
+            const HostSpecies& S = hb.sp[species];
+            const int64_t nsd = S.nsd();
+            const size_t seg_bytes = ((size_t)nsd * (S.nk() + 1) * 4 + 255) / 256 * 256;
+            const size_t ptr_bytes = ((size_t)(nsd + 1) * 8 + 255) / 256 * 256;
+            void* head = nullptr;
+            hipError_t e = hipMalloc(&head, seg_bytes + 2 * ptr_bytes);
+            if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index)");
+            mem.push_back(head);
+            int32_t* seg = (int32_t*)head;
+            int64_t* ptr = (int64_t*)((char*)head + seg_bytes);
+            int64_t* tmp = (int64_t*)((char*)head + seg_bytes + ptr_bytes);
+            int64_t total = 0;
+            if (nsd > 0) {  // (with no determinant the basis has no row to read the index)
+                e = launch_h3_index(false, b->d_bases + p, species, nsd, hb.W, seg, ptr, nullptr, s);
+                if (e == hipSuccess) e = launch_inclusive_scan(ptr, nsd + 1, tmp, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(&total, ptr + nsd, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+            }
+            if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index count");
+            void* rec = nullptr;
+            e = hipMalloc(&rec, (size_t)std::max<int64_t>(total, 1) * 8);
+            if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index records)");
+            mem.push_back(rec);
+            if (nsd > 0) e = launch_h3_index(true, b->d_bases + p, species, nsd, hb.W, seg, ptr, (uint64_t*)rec, s);
+            if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index fill");
+            idx[6 * p + 3 * k] = seg;
+            idx[6 * p + 3 * k + 1] = ptr;
+            idx[6 * p + 3 * k + 2] = rec;
         }
-        if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index count");
-        void* rec = nullptr;
-        e = hipMalloc(&rec, (size_t)std::max<int64_t>(total, 1) * 4);
-        if (e != hipSuccess) return cleanup(), hip_fail(e, "hipMalloc(three-body index records)");
-        mem.push_back(rec);
-        e = launch_h3_index(true, b->d_bases + p, nsd, hb.W, seg, ptr, (uint32_t*)rec, s);
-        if (e != hipSuccess) return cleanup(), hip_fail(e, "three-body index fill");
-        idx[3 * p] = seg;
-        idx[3 * p + 1] = ptr;
-        idx[3 * p + 2] = rec;
     }
     b->h3_index = idx;
     b->h3_mem = mem;

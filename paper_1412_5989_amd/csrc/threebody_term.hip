@@ -305,23 +305,30 @@ __device__ __forceinline__ double value3(const V3Param& v3, const Move& mp, int 
     return (e & 1) ? -v : v;
 }
 
-// Neutron partner index of the three-body walk: for every neutron
-// determinant x and every neutron key, the determinants y of that key with
-// d(x, y) <= 2, ascending, as records local index | d << 24 (the two-body
-// path's lists hold d <= 1 in every key but d = 2 only in keys of x's own 2M
-// and parity; a proton one nucleon away moves the neutron key).
+// Partner index of the three-body walk, per species: for every determinant x
+// and every key, the determinants y of that key with d(x, y) <= 2, ascending
+// (the two-body path's lists hold d <= 1 in every key but d = 2 only in keys
+// of x's own 2M and parity; a proton one nucleon away moves the neutron key).  Records use the two-body partner layout (local
+// index, h1, p1, h2, p2, d); the sign bit holds the parity of the move's
+// species phase part (sum of below_y over holes and particles minus the
+// hole < particle pairs), which for d <= 1 is the two-body record's sign.
 struct H3Index {
     const int32_t* seg;  // [nsd][nk + 1] first record of each key in x's list
     const int64_t* ptr;  // [nsd + 1] start of x's list
-    const uint32_t* rec;
+    const uint64_t* rec;
+};
+
+struct H3Indexes {
+    H3Index n, p;  // neutrons, protons
 };
 
 template <bool kFill, int W>
-__global__ void __launch_bounds__(64 * kH3Waves) h3_index(const BasisDev* __restrict__ Bp, int32_t* __restrict__ seg,
-                                                          int64_t* __restrict__ ptr, uint32_t* __restrict__ rec)
+__global__ void __launch_bounds__(64 * kH3Waves) h3_index(const BasisDev* __restrict__ Bp, int species,
+                                                          int32_t* __restrict__ seg, int64_t* __restrict__ ptr,
+                                                          uint64_t* __restrict__ rec)
 {
     const BasisDev B = *Bp;
-    const SpeciesDev& S = B.sp[1];
+    const SpeciesDev& S = B.sp[species];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t x = (int64_t)blockIdx.x * kH3Waves + wave;
     if (!kFill && x == 0 && lane == 0) ptr[0] = 0;
@@ -342,7 +349,13 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_index(const BasisDev* __rest
             const int d = dist<W>(xw, yw);
             const bool ok = y < y1 && d <= 2;
             const uint64_t m = __ballot(ok);
-            if (kFill && ok) rec[base + run + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)(y - y0) | ((uint32_t)d << 24);
+            if (kFill && ok) {
+                const Move mv = species_move<W>(xw, yw, 0);
+                const int p1 = unpack3(mv.P, 0), p2 = unpack3(mv.P, 1), h1 = unpack3(mv.H, 0), h2 = unpack3(mv.H, 1);
+                rec[base + run + __popcll(m & ((1ull << lane) - 1))] =
+                    make_rec((uint32_t)(y - y0), d, d >= 1 ? h1 : 0, d >= 1 ? p1 : 0, d == 2 ? h2 : 0,
+                             d == 2 ? p2 : 0, (mv.e & 1) != 0);
+            }
             run += __popcll(m);
         }
     }
@@ -350,6 +363,23 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_index(const BasisDev* __rest
         seg[x * (S.nk + 1) + S.nk] = run;
         ptr[x + 1] = run;
     }
+}
+
+// The neutron move of a partner record (orbits species-local + base): the
+// particles p1 (< p2), holes h1 (< h2), and the phase part from the sign bit.
+__device__ __forceinline__ Move rec_move(uint64_t rc, int base)
+{
+    const int d = (int)((rc >> 57) & 3);
+    Move m{0, 0, (int)((rc >> 56) & 1)};
+    if (d >= 1) {
+        m.P = base + (int)((rc >> 32) & 255);
+        m.H = base + (int)((rc >> 24) & 255);
+    }
+    if (d == 2) {
+        m.P |= (base + (int)((rc >> 48) & 255)) << 10;
+        m.H |= (base + (int)((rc >> 40) & 255)) << 10;
+    }
+    return m;
 }
 
 // Entries at most two nucleons apart found by the wavefront's joint neutron
@@ -364,7 +394,7 @@ struct H3Queue {
 };
 
 template <bool kFill, int W>
-__global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, H3Index X,
+__global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, H3Indexes X,
                                                          const float* __restrict__ tbme, V3Param v3,
                                                          int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                          float* __restrict__ val)
@@ -416,8 +446,10 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
     const float* tb = tbme ? tbme + B.tbme0 : nullptr;
     const int32_t* seg = SN.seg1 + (int64_t)ng * (SN.nk + 1);
     const uint64_t* rec1 = SN.l1 + uni(SN.l1_ptr)[ng];
-    const int32_t* seg2 = X.seg + (int64_t)ng * (SN.nk + 1);
-    const uint32_t* rec2 = X.rec + uni(X.ptr)[ng];
+    const int32_t* seg2 = X.n.seg + (int64_t)ng * (SN.nk + 1);
+    const uint64_t* rec2 = X.n.rec + uni(X.n.ptr)[ng];
+    const int32_t* segP = X.p.seg + (int64_t)pg * (SP.nk + 1);
+    const uint64_t* recP = X.p.rec + uni(X.p.ptr)[pg];
     int64_t out = kFill ? uni(row_ptr)[B.row0 + i] : 0;
     const int64_t row_start = out;
     H3Queue* Q = queue_s[wave];
@@ -444,24 +476,17 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         const bool same_n = bj.kn == bi.kn;
         const int s0 = uni(seg)[bj.kn], n_le1 = uni(seg)[bj.kn + 1] - s0;  // neutrons of the key at most one away
         const int r0 = uni(seg2)[bj.kn], r1 = uni(seg2)[bj.kn + 1];  // ... at most two away
-        for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
-            const int pl = c + lane;
-            uint64_t yp[W];
-            int dp = 4;
-#pragma unroll
-            for (int w = 0; w < W; w++) yp[w] = pl < nKp ? SP.sd[(int64_t)(kp0 + pl) * W + w] : 0ull;
-            if (pl < nKp) dp = dist<W>(xp, yp);
+        // one step: 64 proton determinants of the block's proton key (pl their
+        // local index, dp their distance, mp their move when filling)
+        auto step = [&](int pl, int dp, const Move& mp) {
             int cnt = dp == 3 ? (same_n ? 1 : 0) : dp == 2 ? n_le1 : dp == 1 ? r1 - r0 : 0;
-            // this lane's proton move (fill only)
-            Move mp{0, 0, 0};
-            if (kFill && dp <= 3) mp = species_move<W>(xp, yp, 0);
             // the row's own proton determinant (zero away): the wavefront scans the neutron key
             uint64_t coop = __ballot(dp == 0);
             while (coop) {
                 const int L = __builtin_ctzll(coop);
                 coop &= coop - 1;
                 const int excl = read_lane(incl_scan64(cnt) - cnt, L);
-                const int pL = c + L;
+                const int pL = read_lane(pl, L);
                 int found = 0;
                 for (int nc = (b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
                     const int nl = nc + lane;
@@ -521,28 +546,16 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
                         const Move mpL{__builtin_amdgcn_ds_bpermute(L << 2, mp.P),
                                        __builtin_amdgcn_ds_bpermute(L << 2, mp.H),
                                        __builtin_amdgcn_ds_bpermute(L << 2, mp.e)};
-                        int nl = 0, dn = 3;
-                        if (act) {
-                            if (cp == 1) {
-                                const uint32_t rc = rec2[r0 + r];
-                                nl = (int)(rc & 0xffffff);
-                                dn = (int)(rc >> 24);
-                            } else {
-                                const uint64_t rc = rec1[s0 + r];
-                                nl = (int)(rc & kRecLocalMask);
-                                dn = (int)((rc >> 57) & 3);
-                            }
-                        }
-                        uint64_t yn[W];
-#pragma unroll
-                        for (int w = 0; w < W; w++) yn[w] = act ? SN.sd[(int64_t)(kn0 + nl) * W + w] : 0ull;
+                        // the neutron record carries its move: no determinant words needed
+                        const uint64_t rc = !act ? 0ull : cp == 1 ? rec2[r0 + r] : rec1[s0 + r];
+                        const int nl = (int)(rc & kRecLocalMask), dn = (int)((rc >> 57) & 3);
                         const int cls = !act ? -1 : cp + dn == 3 ? 2 : cp + dn == 2 ? 0 : 1;
                         const uint64_t mq[2] = {__ballot(cls == 0), __ballot(cls == 1)};
                         for (int k = 0; k < 2; k++)
                             if (nq[k] + __popcll(mq[k]) > 64) flush(k);
                         const int64_t pos = out + exL + r;
                         if (act) col[pos] = bj.row0 + plL * nKn + nl;
-                        if (cls == 2) val[pos] = (float)value3(v3, mpL, cp, species_move<W>(xn, yn, B.nsps));
+                        if (cls == 2) val[pos] = (float)value3(v3, mpL, cp, rec_move(rc, B.nsps));
                         if (cls == 0 || cls == 1) {
                             const int k = nq[cls] + __popcll(mq[cls] & below_lane);
                             Q[cls].pos[k] = (int32_t)(pos - row_start);
@@ -556,6 +569,30 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
                 }
             }
             out += read_lane(incl, 63);
+        };
+        if (same_n) {
+            // the block holds the row's neutron key: every proton determinant
+            // up to three away contributes; scan the proton key
+            for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
+                const int pl = c + lane;
+                uint64_t yp[W];
+                int dp = 4;
+#pragma unroll
+                for (int w = 0; w < W; w++) yp[w] = pl < nKp ? SP.sd[(int64_t)(kp0 + pl) * W + w] : 0ull;
+                if (pl < nKp) dp = dist<W>(xp, yp);
+                Move mp{0, 0, 0};
+                if (kFill && dp <= 3) mp = species_move<W>(xp, yp, 0);
+                step(pl, dp, mp);
+            }
+        } else {
+            // only proton determinants at most two away contribute: walk the
+            // row's proton partner index in this key (moves in the records)
+            const int q0 = uni(segP)[bj.kp], q1 = uni(segP)[bj.kp + 1];
+            for (int c = q0; c < q1; c += 64) {
+                const int r = c + lane;
+                const uint64_t rc = r < q1 ? recP[r] : 0ull;
+                step((int)(rc & kRecLocalMask), r < q1 ? (int)((rc >> 57) & 3) : 4, rec_move(rc, 0));
+            }
         }
     }
     if (kFill) {
@@ -568,7 +605,7 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
 }  // namespace
 
 template <int W>
-static void launch_one(bool fill, unsigned grid, const BasisDev* B, const H3Index& X, const float* tbme,
+static void launch_one(bool fill, unsigned grid, const BasisDev* B, const H3Indexes& X, const float* tbme,
                        const V3Param& v3, int64_t* row_ptr, int32_t* col, float* val, hipStream_t s)
 {
     if (fill)
@@ -580,36 +617,36 @@ static void launch_one(bool fill, unsigned grid, const BasisDev* B, const H3Inde
 }
 
 template <int W>
-static void launch_index(bool fill, unsigned grid, const BasisDev* B, int32_t* seg, int64_t* ptr, uint32_t* rec,
-                         hipStream_t s)
+static void launch_index(bool fill, unsigned grid, const BasisDev* B, int species, int32_t* seg, int64_t* ptr,
+                         uint64_t* rec, hipStream_t s)
 {
     if (fill)
-        hipLaunchKernelGGL((h3_index<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, seg, ptr, rec);
+        hipLaunchKernelGGL((h3_index<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, species, seg, ptr, rec);
     else
-        hipLaunchKernelGGL((h3_index<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, seg, ptr, rec);
+        hipLaunchKernelGGL((h3_index<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, species, seg, ptr, rec);
 }
 
-// Neutron partner index of one basis (nsd neutron determinants, nk keys, W
-// words): pass 1 writes seg and the list lengths into ptr[1..nsd] (ptr[0] = 0;
-// the caller scans ptr), pass 2 the records.
-hipError_t launch_h3_index(bool fill, const BasisDev* B, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
-                           uint32_t* rec, hipStream_t s)
+// Partner index of one species of one basis (nsd determinants, W words):
+// pass 1 writes seg and the list lengths into ptr[1..nsd] (ptr[0] = 0; the
+// caller scans ptr), pass 2 the records.
+hipError_t launch_h3_index(bool fill, const BasisDev* B, int species, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
+                           uint64_t* rec, hipStream_t s)
 {
     const unsigned grid = (unsigned)((nsd + kH3Waves - 1) / kH3Waves);
     if (grid == 0) return hipSuccess;
     switch (W) {
-    case 1: launch_index<1>(fill, grid, B, seg, ptr, rec, s); break;
-    case 2: launch_index<2>(fill, grid, B, seg, ptr, rec, s); break;
-    case 3: launch_index<3>(fill, grid, B, seg, ptr, rec, s); break;
-    default: launch_index<4>(fill, grid, B, seg, ptr, rec, s); break;
+    case 1: launch_index<1>(fill, grid, B, species, seg, ptr, rec, s); break;
+    case 2: launch_index<2>(fill, grid, B, species, seg, ptr, rec, s); break;
+    case 3: launch_index<3>(fill, grid, B, species, seg, ptr, rec, s); break;
+    default: launch_index<4>(fill, grid, B, species, seg, ptr, rec, s); break;
     }
     return hipGetLastError();
 }
 
 // One launch per basis of the handle: count (row_ptr[R_b + 1 + i] = entries
 // of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]).
-// words[p]: 64-bit words per species bitstring of basis p (1..4); index[p]:
-// its neutron partner index (seg, ptr, rec).
+// words[p]: 64-bit words per species bitstring of basis p (1..4); index[6p..]:
+// its neutron, then proton, partner index (seg, ptr, rec).
 hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
                           int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
                           int32_t* col, float* val, bool fill, hipStream_t s)
@@ -620,7 +657,9 @@ hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int*
         const unsigned grid = (unsigned)((dims[p] + kH3Waves - 1) / kH3Waves);
         if (grid == 0 && fill) continue;
         const unsigned g = grid > 0 ? grid : 1;
-        const H3Index X{(const int32_t*)index[3 * p], (const int64_t*)index[3 * p + 1], (const uint32_t*)index[3 * p + 2]};
+        const H3Indexes X{{(const int32_t*)index[6 * p], (const int64_t*)index[6 * p + 1], (const uint64_t*)index[6 * p + 2]},
+                          {(const int32_t*)index[6 * p + 3], (const int64_t*)index[6 * p + 4],
+                           (const uint64_t*)index[6 * p + 5]}};
         switch (words[p]) {
         case 1: launch_one<1>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
         case 2: launch_one<2>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
