@@ -140,7 +140,11 @@ int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap);
 int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info,
                    ci_basis** out, ci_stream stream);
 
-/* Frees the handle and its device tables (NULL is allowed). */
+/* Frees the handle (NULL is allowed).  Its two device blocks (index tables,
+ * partner lists) go to a cache of the library after the device is
+ * synchronized, and later builds of similar size on that device take them
+ * instead of allocating; the cache keeps at most 8 blocks per device and
+ * 4 GiB in all and frees the oldest beyond that. */
 void ci_basis_free(ci_basis* b);
 
 /* Count pass (Sec. 4.1): row_ptr (device, int64, sum_b (D_b + 1)) receives

@@ -59,6 +59,112 @@ static int hip_fail(hipError_t e, const char* where)
     return fail(CI_EHIP, std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
 }
 
+// ---------------------------------------------------------------------------
+// Device block cache of the handles' index memory.  A build takes two blocks
+// (index tables, partner lists); returning them with hipFree would synchronize
+// the device and cost tens of microseconds each, so a freed handle parks them
+// here and the next build of a similar problem takes them back.  A block enters
+// the cache only after its device has been synchronized (no kernel that reads
+// it can still be running); the cache holds at most kCacheBlocks blocks per
+// device and kCacheBytes in total, and frees the oldest beyond that.  A block
+// is reused for requests of between half its size and its size.
+namespace {
+constexpr int kCacheBlocks = 8;
+constexpr size_t kCacheBytes = size_t(4) << 30;
+struct CachedBlock {
+    int device;
+    void* p;
+    size_t bytes;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;  // oldest first
+size_t g_cache_total = 0;
+}  // namespace
+
+static hipError_t dev_alloc(int device, size_t bytes, void** p, size_t* got)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); i++) {
+            const CachedBlock& c = g_cache[i];
+            if (c.device == device && c.bytes >= bytes && c.bytes / 2 <= bytes &&
+                (best < 0 || c.bytes < g_cache[best].bytes))
+                best = i;
+        }
+        if (best >= 0) {
+            *p = g_cache[best].p;
+            *got = g_cache[best].bytes;
+            g_cache_total -= *got;
+            g_cache.erase(g_cache.begin() + best);
+            return hipSuccess;
+        }
+    }
+    *got = bytes;
+    return hipMalloc(p, bytes);
+}
+
+static void dev_release(int device, void* p, size_t bytes)
+{
+    if (!p) return;
+    int cur = -1;
+    bool ok = bytes <= kCacheBytes && hipGetDevice(&cur) == hipSuccess;
+    if (ok && cur != device) ok = hipSetDevice(device) == hipSuccess;
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (cur >= 0 && cur != device) hipSetDevice(cur);
+    if (!ok) {
+        hipFree(p);
+        return;
+    }
+    std::vector<void*> evict;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto count_dev = [&]() {
+            int n = 0;
+            for (const CachedBlock& c : g_cache) n += c.device == device;
+            return n;
+        };
+        while (!g_cache.empty() && (count_dev() >= kCacheBlocks || g_cache_total + bytes > kCacheBytes)) {
+            // the oldest block of this device, else the oldest of any
+            int v = 0;
+            for (int i = 0; i < (int)g_cache.size(); i++)
+                if (g_cache[i].device == device) {
+                    v = i;
+                    break;
+                }
+            evict.push_back(g_cache[v].p);
+            g_cache_total -= g_cache[v].bytes;
+            g_cache.erase(g_cache.begin() + v);
+        }
+        g_cache.push_back({device, p, bytes});
+        g_cache_total += bytes;
+    }
+    for (void* q : evict) hipFree(q);
+}
+
+// Per-thread pinned staging buffer of the host-written tables and the list
+// lengths read back (grown as needed and kept): copies out of pinned memory
+// are asynchronous, so the host goes on while they run.  Each build
+// synchronizes its stream before returning, so the next build on the thread
+// finds the buffer free.
+static char* pinned_staging(size_t bytes)
+{
+    struct Buf {
+        char* p = nullptr;
+        size_t n = 0;
+    };
+    static thread_local Buf b;
+    if (b.n < bytes) {
+        if (b.p) hipHostFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        const size_t cap = std::max(bytes, (size_t)1 << 20);
+        if (hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        b.n = cap;
+    }
+    return b.p;
+}
+
 struct ci_basis {
     int device = 0;
     std::vector<ci_basis_info> info;
@@ -88,8 +194,8 @@ struct ci_basis {
     std::vector<void*> h3_mem;
     ~ci_basis()
     {
-        if (arena) hipFree(arena);
-        if (lists) hipFree(lists);
+        dev_release(device, arena, arena_bytes);
+        dev_release(device, lists, list_bytes);
         for (void* m : h3_mem) hipFree(m);
     }
 };
@@ -364,18 +470,15 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
 
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    e = hipMalloc(&h->arena, bytes);
+    e = dev_alloc(h->device, bytes, &h->arena, &h->arena_bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(index tables)");
-    h->arena_bytes = bytes;
     char* dev = (char*)h->arena;
     auto D = [&](size_t off) { return (void*)(dev + off); };
 
-    // host mirror of the host-written tables (a per-thread buffer kept between
-    // builds; the stream is synchronized before this call returns, so the
-    // copy out of it is finished when the next build on the thread reuses it)
-    static thread_local std::vector<char> mirror_buf;
-    if (mirror_buf.size() < host_bytes) mirror_buf.resize(host_bytes);
-    char* mirror = mirror_buf.data();
+    // host mirror of the host-written tables, then the list lengths (pinned)
+    const size_t tot_off = (host_bytes + 255) / 256 * 256;
+    char* mirror = pinned_staging(tot_off + 4 * ub.size() * sizeof(int64_t));
+    if (!mirror) return fail(CI_EHIP, "hipHostMalloc(staging buffer)");
     auto put = [&](size_t off, const void* src, size_t n) {
         if (n) std::memcpy(mirror + off, src, n);
     };
@@ -490,13 +593,14 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     }
     e = hipMemcpyAsync(dev + pair_start, mirror + pair_start, host_bytes - pair_start, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pair index)");
-    std::vector<int64_t> totals(4 * ub.size());
+    int64_t* tot_pinned = (int64_t*)(mirror + tot_off);
     for (size_t u = 0; u < ub.size(); u++) {
-        e = hipMemcpyAsync(&totals[4 * u], D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(tot_pinned + 4 * u, D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(list lengths)");
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(partner count)");
+    std::vector<int64_t> totals(tot_pinned, tot_pinned + 4 * ub.size());
     for (int i = 0; i < nsp; i++) {
         const int c = canon[i];
         totals[2 * i] = totals[2 * c];
@@ -515,9 +619,8 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         lo1[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i], 1));
         lo12[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i + 1], 1));
     }
-    e = hipMalloc(&h->lists, LL.bytes());
+    e = dev_alloc(h->device, LL.bytes(), &h->lists, &h->list_bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(partner lists)");
-    h->list_bytes = LL.bytes();
     char* ldev = (char*)h->lists;
     for (size_t u = 0; u < ub.size(); u++)
         for (int sidx = 0; sidx < 2; sidx++) {
