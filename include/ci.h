@@ -134,9 +134,13 @@ int ci_basis_plan(const ci_problem* probs, int32_t n_probs, ci_basis_info* info)
 int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap);
 
 /* Builds the basis indexing (Sec. 2) of n_probs problems: enumerates the
- * determinants, blocks, one- and two-nucleon partner lists and the two-body
- * pair index on the host, then makes ONE device allocation and ONE copy
- * (Sec. 5.2).  info[n_probs] is filled; *out receives the handle. */
+ * determinants, blocks and the two-body pair index on the host and moves the
+ * host-built tables with one device allocation (Sec. 5.2); the one- and
+ * two-nucleon partner lists are built on the device (one more allocation,
+ * sized after a count pass that the build waits for).  info[n_probs] is
+ * filled; *out receives the handle.  Returns while the partner lists are
+ * still being filled on `stream`: later calls on the same stream are ordered
+ * after them; work on another stream must first synchronize with it. */
 int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info,
                    ci_basis** out, ci_stream stream);
 

@@ -142,11 +142,41 @@ static void dev_release(int device, void* p, size_t bytes)
     for (void* q : evict) hipFree(q);
 }
 
-// Per-thread pinned staging buffer of the host-written tables and the list
-// lengths read back (grown as needed and kept): copies out of pinned memory
-// are asynchronous, so the host goes on while they run.  Each build
-// synchronizes its stream before returning, so the next build on the thread
-// finds the buffer free.
+// Per-thread pinned staging buffer of the host-written tables, the list
+// lengths read back and the descriptors (grown as needed and kept): copies out
+// of pinned memory are asynchronous, so the host goes on while they run.  A
+// build returns before its last copy out of the buffer has run; an event
+// recorded after that copy is waited on before the next build on the thread
+// writes the buffer again.
+struct StagingFence {
+    hipEvent_t ev = nullptr;
+    int device = -1;
+    bool pending = false;
+};
+static thread_local StagingFence t_fence;
+
+static hipError_t staging_wait()
+{
+    if (!t_fence.pending) return hipSuccess;
+    t_fence.pending = false;
+    return hipEventSynchronize(t_fence.ev);
+}
+
+static hipError_t staging_fence(hipStream_t s, int device)
+{
+    if (!t_fence.ev || t_fence.device != device) {
+        if (t_fence.ev) hipEventDestroy(t_fence.ev);
+        t_fence.ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&t_fence.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        t_fence.device = device;
+    }
+    hipError_t e = hipEventRecord(t_fence.ev, s);
+    if (e != hipSuccess) return e;
+    t_fence.pending = true;
+    return hipSuccess;
+}
+
 static char* pinned_staging(size_t bytes)
 {
     struct Buf {
@@ -154,12 +184,33 @@ static char* pinned_staging(size_t bytes)
         size_t n = 0;
     };
     static thread_local Buf b;
+    if (staging_wait() != hipSuccess) return nullptr;
     if (b.n < bytes) {
         if (b.p) hipHostFree(b.p);
         b.p = nullptr;
         b.n = 0;
         const size_t cap = std::max(bytes, (size_t)1 << 20);
         if (hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        b.n = cap;
+    }
+    return b.p;
+}
+
+// Per-thread pinned buffer for the nnz counts the count passes read back
+// (they synchronize before returning, so the buffer is free again).
+static int64_t* pinned_counts(size_t n)
+{
+    struct Buf {
+        int64_t* p = nullptr;
+        size_t n = 0;
+    };
+    static thread_local Buf b;
+    if (b.n < n) {
+        if (b.p) hipHostFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        const size_t cap = std::max<size_t>(n, 4096);
+        if (hipHostMalloc((void**)&b.p, cap * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) return nullptr;
         b.n = cap;
     }
     return b.p;
@@ -475,9 +526,11 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     char* dev = (char*)h->arena;
     auto D = [&](size_t off) { return (void*)(dev + off); };
 
-    // host mirror of the host-written tables, then the list lengths (pinned)
+    // host mirror of the host-written tables, then the list lengths, then the
+    // descriptors (pinned)
     const size_t tot_off = (host_bytes + 255) / 256 * 256;
-    char* mirror = pinned_staging(tot_off + 4 * ub.size() * sizeof(int64_t));
+    const size_t bd_off = (tot_off + 4 * ub.size() * sizeof(int64_t) + 255) / 256 * 256;
+    char* mirror = pinned_staging(bd_off + n_probs * sizeof(BasisDev));
     if (!mirror) return fail(CI_EHIP, "hipHostMalloc(staging buffer)");
     auto put = [&](size_t off, const void* src, size_t n) {
         if (n) std::memcpy(mirror + off, src, n);
@@ -687,8 +740,11 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         R += hb.dim + 1;
         T += hb.n_tbme;
     }
-    e = hipMemcpyAsync(D(o_bases), bd.data(), bd.size() * sizeof(BasisDev), hipMemcpyHostToDevice, s);
+    std::memcpy(mirror + bd_off, bd.data(), bd.size() * sizeof(BasisDev));
+    e = hipMemcpyAsync(D(o_bases), mirror + bd_off, bd.size() * sizeof(BasisDev), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
+    e = staging_fence(s, h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
     h->d_bases = (BasisDev*)D(o_bases);
     h->d_basis_row0 = (int64_t*)D(o_row0);
     h->d_seg_first = (int64_t*)D(o_first);
@@ -705,9 +761,8 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     h->nrows = row0[n_probs];
     h->n_rowptr = R;
     h->n_tbme = T;
-    // the host buffers of the copies go out of scope at return
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(basis build)");
+    // the partner lists are still being filled on the stream: later work on
+    // it is ordered after them
     *out = h.release();
     return CI_OK;
 }
@@ -733,10 +788,13 @@ static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int ful
     if (e != hipSuccess) return hip_fail(e, "count launch");
     e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
     if (e != hipSuccess) return hip_fail(e, "nnz launch");
-    e = hipMemcpyAsync(nnz, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    int64_t* pin = pinned_counts(n);
+    if (!pin) return fail(CI_EHIP, "hipHostMalloc(counts)");
+    e = hipMemcpyAsync(pin, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(nnz)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(count)");
+    std::memcpy(nnz, pin, n * sizeof(int64_t));
     return CI_OK;
 }
 
@@ -861,10 +919,13 @@ int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream
     if (e != hipSuccess) return hip_fail(e, "scan launch");
     e = launch_nnz(row_ptr, b->d_seg_first, b->d_seg_last, b->d_nnz, n, s);
     if (e != hipSuccess) return hip_fail(e, "nnz launch");
-    e = hipMemcpyAsync(nnz, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    int64_t* pin = pinned_counts(n);
+    if (!pin) return fail(CI_EHIP, "hipHostMalloc(counts)");
+    e = hipMemcpyAsync(pin, b->d_nnz, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(nnz)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(three-body count)");
+    std::memcpy(nnz, pin, n * sizeof(int64_t));
     return CI_OK;
 }
 
