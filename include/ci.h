@@ -306,6 +306,12 @@ int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, in
  * buffer must be ordered.  CI_EINVAL for null pointers or n < 0, with work
  * for n > 2^31 - 1; CI_ESPACE for a short work buffer. */
 size_t ci_threebody_work_bytes(int64_t n);
+/* Host only: the Clebsch-Gordan coefficient <j1 m1 j2 m2 | J M> (all
+ * arguments doubled, Condon-Shortley phases) by Racah's formula in long
+ * double, the routine the decoupling's coefficient tables are built with; 0
+ * outside the selection rules.  CI_EINVAL for a null out or a j outside
+ * [0, 120]. */
+int ci_clebsch_gordan(int32_t j1, int32_t m1, int32_t j2, int32_t m2, int32_t J, int32_t M, double* out);
 int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,
                           float* out, void* work, size_t work_bytes, ci_stream stream);
 

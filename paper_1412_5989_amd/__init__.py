@@ -78,7 +78,7 @@ EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "
            "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
-           "ci_threebody_orbitals", "ci_threebody_decouple", "ci_threebody_work_bytes",
+           "ci_threebody_orbitals", "ci_threebody_decouple", "ci_threebody_work_bytes", "ci_clebsch_gordan",
            "ci_basis_count", "ci_basis_get_info", "ci_basis_states"]
 
 _lib = None
@@ -124,6 +124,7 @@ def load_library():
     L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
     L.ci_hamiltonian3_count.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian3_fill.argtypes = [vp, vp, P(ci_v3), vp, vp, vp, vp]
+    L.ci_clebsch_gordan.argtypes = [i32, i32, i32, i32, i32, i32, P(ctypes.c_double)]
     L.ci_threebody_work_bytes.argtypes = [i64]
     L.ci_threebody_work_bytes.restype = sz
     L.ci_vjp_work_bytes.argtypes = [vp]
@@ -439,6 +440,13 @@ def ci_probe_ceilings(mib: int = 1024, stream=None) -> dict:
     _check(load_library().ci_probe_ceilings(_ptr(buf), buf.numel(), ctypes.byref(gbs), ctypes.byref(steps),
                                             _stream_ptr(stream)))
     return {"store_GBps": gbs.value, "xor_popcount_steps_per_s": steps.value, "store_bytes": int(mib) << 20}
+
+
+def ci_clebsch_gordan(j1: int, m1: int, j2: int, m2: int, J: int, M: int) -> float:
+    """<j1 m1 j2 m2 | J M>, doubled arguments (host; the decoupling's table routine)."""
+    out = ctypes.c_double()
+    _check(load_library().ci_clebsch_gordan(j1, m1, j2, m2, J, M, ctypes.byref(out)))
+    return out.value
 
 
 def ci_threebody_plan(n1max: int, n3max: int) -> dict:

@@ -1195,6 +1195,15 @@ int ci_threebody_orbitals(const ci_threebody* t, int32_t* nlj, int32_t* morb, in
     return CI_OK;
 }
 
+int ci_clebsch_gordan(int32_t j1, int32_t m1, int32_t j2, int32_t m2, int32_t J, int32_t M, double* out)
+{
+    if (!out) return fail(CI_EINVAL, "null pointer");
+    if (j1 < 0 || j2 < 0 || J < 0 || j1 > 120 || j2 > 120 || J > 120)
+        return fail(CI_EINVAL, "angular momenta (doubled) must lie in [0, 120]");
+    *out = clebsch_gordan2(j1, m1, j2, m2, J, M);
+    return CI_OK;
+}
+
 size_t ci_threebody_work_bytes(int64_t n) { return decouple_work_bytes(n); }
 
 int ci_threebody_decouple(const ci_threebody* t, const float* coupled, const int32_t* requests, int64_t n,

@@ -43,6 +43,9 @@ struct ThreeBodyHost {
 };
 
 int threebody_plan(int n1max, int n3max, ThreeBodyHost& h, std::string& err);
+// <j1 m1 j2 m2 | J M> (doubled arguments) by Racah's formula in long double:
+// the routine the coefficient tables are built with.
+double clebsch_gordan2(int j1, int m1, int j2, int m2, int J, int M);
 // Keys of the coupled elements in storage order: (t, t', 2J, 2T, 2J_ab,
 // 2T_ab, 2J_de, 2T_de) per element.
 void threebody_keys(const ThreeBodyHost& h, int32_t* keys);

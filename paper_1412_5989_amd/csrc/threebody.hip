@@ -63,11 +63,11 @@ double racah_cg(int j1, int m1, int j2, int m2, int J, int M)
 {
     if (m1 + m2 != M || iabs(m1) > j1 || iabs(m2) > j2 || iabs(M) > J) return 0.0;
     if (((j1 + m1) & 1) || ((j2 + m2) & 1) || ((J + M) & 1) || !triangle2(j1, j2, J)) return 0.0;
-    static std::vector<long double> f;
-    if (f.empty()) {
-        f.assign(200, 1.0L);
-        for (int k = 1; k < 200; k++) f[k] = f[k - 1] * k;
-    }
+    static const std::vector<long double> f = [] {
+        std::vector<long double> t(200, 1.0L);
+        for (int k = 1; k < 200; k++) t[k] = t[k - 1] * k;
+        return t;
+    }();
     const int a = (j1 + j2 - J) / 2, b = (j1 - j2 + J) / 2, c = (-j1 + j2 + J) / 2, d = (j1 + j2 + J) / 2 + 1;
     const long double pre = sqrtl((long double)(J + 1) * f[a] * f[b] * f[c] / f[d] * f[(J + M) / 2] *
                                   f[(J - M) / 2] * f[(j1 - m1) / 2] * f[(j1 + m1) / 2] * f[(j2 - m2) / 2] *
@@ -419,6 +419,8 @@ __global__ void __launch_bounds__(kOrderThreads) order_scatter(const uint8_t* __
 }
 
 }  // namespace
+
+double clebsch_gordan2(int j1, int m1, int j2, int m2, int J, int M) { return racah_cg(j1, m1, j2, m2, J, M); }
 
 // ------------------------------------------------------------------ host layout
 

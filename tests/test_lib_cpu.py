@@ -167,3 +167,31 @@ def test_three_body_term_argument_errors():
     assert L.ci_hamiltonian3_fill(None, None, ctypes.byref(v3), None, None, None, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian3_fill(vp(1), None, None, vp(1), vp(1), vp(1), None) == ci.CI_EINVAL
     assert L.ci_hamiltonian3_fill(vp(1), None, ctypes.byref(v3), None, vp(1), vp(1), None) == ci.CI_EINVAL
+
+
+def test_coefficient_routine_of_the_decoupling_tables_is_exact_enough():
+    # the routine the decoupling's coefficient tables are built with (Racah's
+    # formula in long double) against exact rationals, up to the largest
+    # arguments of the largest supported space (n1max = 12: j <= 25/2, J_ab <= 25,
+    # J <= 75/2): first coupling (odd j1, j2 <= 25) and second (even J12 <= 50, odd j3 <= 25)
+    import random
+
+    from oracle.threebody import cg
+
+    rng = random.Random(12)
+    worst, n = 0.0, 0
+    for j1, j2 in [(a, b) for a in range(1, 26, 2) for b in range(1, 26, 2)] + \
+                  [(a, b) for a in range(0, 51, 2) for b in range(1, 26, 2)]:
+        for J in range(abs(j1 - j2), j1 + j2 + 1, 2):
+            m1 = rng.randrange(-j1, j1 + 1, 2) if j1 else 0
+            m2 = rng.randrange(-j2, j2 + 1, 2)
+            M = m1 + m2
+            v = ci.ci_clebsch_gordan(j1, m1, j2, m2, J, M)
+            ref = cg(j1, m1, j2, m2, J, M) if abs(M) <= J else 0.0
+            worst = max(worst, abs(v - ref))
+            n += 1
+    assert n > 5000 and worst <= 1e-14
+    assert ci.ci_clebsch_gordan(3, 1, 3, 1, 0, 2) == 0.0  # |M| > J
+    assert ci.ci_clebsch_gordan(1, 1, 1, 1, 4, 2) == 0.0  # outside the triangle
+    with pytest.raises(ci.CIError):
+        ci.ci_clebsch_gordan(121, 1, 1, 1, 120, 2)
