@@ -110,7 +110,13 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
     n, t, nr = run(256, 3)
     nrows = int(min(o.dim, max(256, nr * budget_s / max(t, 1e-3))))
     n, t, nr = run(nrows, 2)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
+    # the same on one thread, on a smaller sample (~3 s)
+    oracle.set_threads(1)
+    try:
+        n1, t1, nr1 = run(max(32, int(nr * 3.0 / max(t * threads, 1e-3))), 4)
+    finally:
+        oracle.set_threads(threads)
     return {
         "value": n / t,
         "unit": "nonzeros/s",
@@ -118,6 +124,8 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
         "kind": "oracle",
         "sample": "%d sampled rows of the same workload (%d stored entries), row scan + values on %d "
                   "OpenMP threads, gradient of those rows on 1 thread, %.1f s" % (nr, n, threads, t),
+        "value_1_thread": n1 / t1,
+        "sample_1_thread": "%d sampled rows (%d stored entries), %.1f s" % (nr1, n1, t1),
     }
 
 

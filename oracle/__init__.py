@@ -69,6 +69,8 @@ def _load():
     L.orc_element.argtypes = [vp, i64, i64]
     L.orc_grad_rows.argtypes = [vp, vp, i64, vp, vp]
     L.orc_set_v3.argtypes = [vp, i32, ctypes.c_uint64, dbl]
+    L.orc_set_threads.argtypes = [i32]
+    L.orc_max_threads.restype = i32
     L.orc_v3.restype = dbl
     L.orc_v3.argtypes = [vp, i32, i32, i32, i32, i32, i32]
     L.orc_row_counts3.argtypes = [vp, vp, i64, vp]
@@ -77,6 +79,15 @@ def _load():
     L.orc_element3.argtypes = [vp, i64, i64]
     _lib = L
     return L
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the row-parallel oracle functions."""
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -25,6 +25,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_MAXW 8 /* 64-bit words per species bitstring (n_sps <= 512) */
 
@@ -895,3 +896,8 @@ void orc_rows3(void* h, const int64_t* rows, int64_t nrows, const int64_t* offs,
 
 /* <Phi_i|H|Phi_j> with the three-body term for any i, j (both triangles) */
 double orc_element3(void* h, int64_t i, int64_t j) { return element3((orc_ctx*)h, i, j); }
+
+/* OpenMP threads of the row-parallel functions (the CPU-baseline timing runs
+ * the oracle at all host threads and at one). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
