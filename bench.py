@@ -279,6 +279,27 @@ def run_three_body_term(ci, torch, prob, tbme_seed, with_oracle, reps=3):
            "fill_nnz_per_s": nnz / (fill_ms * 1e-3), "fill_alg_GBps": alg / (fill_ms * 1e-3) / 1e9,
            "fill_frac_of_hbm_peak": alg / (fill_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del col, val
+    torch.cuda.empty_cache()
+    # the full symmetric matrix with the term, and its lowest eigenpair (Lanczos)
+    rpf, nnzf = ci.ci_hamiltonian3_count_full(b)
+    colf = torch.empty(nnzf[0], dtype=torch.int32, device="cuda")
+    valf = torch.empty(nnzf[0], dtype=torch.float32, device="cuda")
+    ci.ci_hamiltonian3_fill_full(b, tb, v3, rpf, colf, valf)
+    ev_ff, ev_sp = EventTimer(torch, stream), EventTimer(torch, stream)
+    with ev_ff:
+        ci.ci_hamiltonian3_fill_full(b, tb, v3, rpf, colf, valf)
+    x = torch.ones(D, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        with ev_sp:
+            y = ci.ci_hamiltonian_spmv(b, 0, rpf, colf, valf, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, _, it = ci.ci_lanczos(b, 0, rpf, colf, valf, max_iter=300, tol=1e-12)
+    t_l = time.perf_counter() - t0
+    res.update({"nnz_full": nnzf[0], "fill_full_ms": ev_ff.mean_ms(),
+                "spmv_ms": ev_sp.mean_ms(), "spmv_GBps": (8 * nnzf[0] + 24 * D) / (ev_sp.mean_ms() * 1e-3) / 1e9,
+                "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E})
+    del colf, valf, y, x
     b.free()
     if with_oracle:
         import oracle

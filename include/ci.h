@@ -214,6 +214,12 @@ int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream
  * the handle holds its index (else it first builds it, synchronizing). */
 int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
                          float* val, ci_stream stream);
+/* The same two passes for the FULL symmetric matrix with the three-body term
+ * (both triangles, every (i, j) with d(i, j) <= 3, columns ascending), as
+ * ci_lanczos takes it; every element is computed directly. */
+int ci_hamiltonian3_count_full(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream);
+int ci_hamiltonian3_fill_full(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr,
+                              int32_t* col, float* val, ci_stream stream);
 
 /* y = H x for problem `prob` of the handle, H in full CSR form (row_ptr, col,
  * val from ci_hamiltonian_count_full / _fill_full; the problem's own row

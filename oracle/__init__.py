@@ -77,6 +77,8 @@ def _load():
     L.orc_rows3.argtypes = [vp, vp, i64, vp, vp, vp]
     L.orc_element3.restype = dbl
     L.orc_element3.argtypes = [vp, i64, i64]
+    L.orc_row_counts3_full.argtypes = [vp, vp, i64, vp]
+    L.orc_rows3_full.argtypes = [vp, vp, i64, vp, vp, vp]
     _lib = L
     return L
 
@@ -253,6 +255,29 @@ class Oracle:
             _load().orc_rows3(self._h, _ptr(rows), len(rows), _ptr(offs), _ptr(cols),
                               _ptr(vals) if values else None)
         return counts, cols[:tot], (vals[:tot] if values else None)
+
+    def rows3_full(self, rows, values: bool = True):
+        """Like rows3(), for the full symmetric matrix (every column of the row)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        counts = np.zeros(len(rows), np.int64)
+        if len(rows):
+            _load().orc_row_counts3_full(self._h, _ptr(rows), len(rows), _ptr(counts))
+        offs = np.zeros(len(rows), np.int64)
+        if len(rows):
+            offs[1:] = np.cumsum(counts)[:-1]
+        tot = int(counts.sum())
+        cols = np.zeros(max(tot, 1), np.int32)
+        vals = np.zeros(max(tot, 1), np.float64) if values else None
+        if len(rows):
+            _load().orc_rows3_full(self._h, _ptr(rows), len(rows), _ptr(offs), _ptr(cols),
+                                   _ptr(vals) if values else None)
+        return counts, cols[:tot], (vals[:tot] if values else None)
+
+    def lowest_eigenpair3(self):
+        """Lowest eigenvalue and eigenvector of the matrix with the three-body
+        term (numpy's dense symmetric eigensolver)."""
+        w, v = np.linalg.eigh(self.dense3())
+        return float(w[0]), v[:, 0]
 
     def element3(self, i: int, j: int) -> float:
         return _load().orc_element3(self._h, int(i), int(j))

@@ -901,3 +901,32 @@ double orc_element3(void* h, int64_t i, int64_t j) { return element3((orc_ctx*)h
  * the oracle at all host threads and at one). */
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* The same for the full symmetric matrix with the three-body term: every
+ * column j (both triangles) with at most three nucleons different. */
+void orc_row_counts3_full(void* h, const int64_t* rows, int64_t nrows, int64_t* counts)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t n = 0;
+        for (int64_t j = 0; j < c->D; j++)
+            if (ndiff(c, rows[r], j) <= 3) n++;
+        counts[r] = n;
+    }
+}
+
+void orc_rows3_full(void* h, const int64_t* rows, int64_t nrows, const int64_t* offs, int32_t* cols, double* vals)
+{
+    orc_ctx* c = (orc_ctx*)h;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t i = rows[r], o = offs[r];
+        for (int64_t j = 0; j < c->D; j++) {
+            if (ndiff(c, i, j) > 3) continue;
+            cols[o] = (int32_t)j;
+            if (vals) vals[o] = element3(c, i, j);
+            o++;
+        }
+    }
+}

@@ -74,7 +74,8 @@ class ci_tuning(ctypes.Structure):
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
-           "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill", "ci_hamiltonian_spmv", "ci_lanczos",
+           "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill",
+           "ci_hamiltonian3_count_full", "ci_hamiltonian3_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
            "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
@@ -124,6 +125,8 @@ def load_library():
     L.ci_threebody_decouple.argtypes = [vp, vp, vp, i64, vp, vp, sz, vp]
     L.ci_hamiltonian3_count.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian3_fill.argtypes = [vp, vp, P(ci_v3), vp, vp, vp, vp]
+    L.ci_hamiltonian3_count_full.argtypes = [vp, vp, vp, vp]
+    L.ci_hamiltonian3_fill_full.argtypes = [vp, vp, P(ci_v3), vp, vp, vp, vp]
     L.ci_clebsch_gordan.argtypes = [i32, i32, i32, i32, i32, i32, P(ctypes.c_double)]
     L.ci_threebody_work_bytes.argtypes = [i64]
     L.ci_threebody_work_bytes.restype = sz
@@ -302,23 +305,23 @@ def ci_hamiltonian_fill_full(basis: Basis, tbme, row_ptr, col=None, val=None, st
     return col, val
 
 
-def ci_hamiltonian3_count(basis: Basis, stream=None):
-    """Count pass of the matrix with a three-body term (states at most three
-    nucleons apart, upper triangle): (row_ptr, nnz list per basis)."""
+def _h3_count(basis: Basis, full: bool, stream=None):
     torch = _torch()
     row_ptr = torch.empty(basis.n_rowptr, dtype=torch.int64, device=basis.device)
     nnz = np.zeros(basis.n_probs, np.int64)
-    _check(load_library().ci_hamiltonian3_count(basis.handle, _ptr(row_ptr), nnz.ctypes.data_as(ctypes.c_void_p),
-                                                _stream_ptr(stream)))
-    basis.nnz3 = [int(x) for x in nnz]
-    return row_ptr, basis.nnz3
+    fn = load_library().ci_hamiltonian3_count_full if full else load_library().ci_hamiltonian3_count
+    _check(fn(basis.handle, _ptr(row_ptr), nnz.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+    counts = [int(x) for x in nnz]
+    if full:
+        basis.nnz3_full = counts
+    else:
+        basis.nnz3 = counts
+    return row_ptr, counts
 
 
-def ci_hamiltonian3_fill(basis: Basis, tbme, v3, row_ptr, col=None, val=None, stream=None):
-    """Fill pass with the three-body term: (col int32, val float32).
-    v3 = (kind, seed, scale) with kind CI_V3_NONE / CI_V3_SYNTHETIC / CI_V3_IDENTITY."""
+def _h3_fill(basis: Basis, tbme, v3, row_ptr, col, val, full: bool, stream=None):
     torch = _torch()
-    tot = sum(basis.nnz3)
+    tot = sum(basis.nnz3_full if full else basis.nnz3)
     _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
     _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
     if col is None:
@@ -329,9 +332,31 @@ def ci_hamiltonian3_fill(basis: Basis, tbme, v3, row_ptr, col=None, val=None, st
     _check_tensor(val, torch.float32, tot, "val")
     kind, seed, scale = v3
     p = ci_v3(int(kind), int(seed) & ((1 << 64) - 1), float(scale))
-    _check(load_library().ci_hamiltonian3_fill(basis.handle, _ptr(tbme), ctypes.byref(p), _ptr(row_ptr), _ptr(col),
-                                               _ptr(val), _stream_ptr(stream)))
+    fn = load_library().ci_hamiltonian3_fill_full if full else load_library().ci_hamiltonian3_fill
+    _check(fn(basis.handle, _ptr(tbme), ctypes.byref(p), _ptr(row_ptr), _ptr(col), _ptr(val), _stream_ptr(stream)))
     return col, val
+
+
+def ci_hamiltonian3_count(basis: Basis, stream=None):
+    """Count pass of the matrix with a three-body term (states at most three
+    nucleons apart, upper triangle): (row_ptr, nnz list per basis)."""
+    return _h3_count(basis, False, stream)
+
+
+def ci_hamiltonian3_fill(basis: Basis, tbme, v3, row_ptr, col=None, val=None, stream=None):
+    """Fill pass with the three-body term: (col int32, val float32).
+    v3 = (kind, seed, scale) with kind CI_V3_NONE / CI_V3_SYNTHETIC / CI_V3_IDENTITY."""
+    return _h3_fill(basis, tbme, v3, row_ptr, col, val, False, stream)
+
+
+def ci_hamiltonian3_count_full(basis: Basis, stream=None):
+    """Count pass of the FULL symmetric matrix with the three-body term."""
+    return _h3_count(basis, True, stream)
+
+
+def ci_hamiltonian3_fill_full(basis: Basis, tbme, v3, row_ptr, col=None, val=None, stream=None):
+    """Fill pass of the FULL symmetric matrix with the three-body term (for ci_lanczos)."""
+    return _h3_fill(basis, tbme, v3, row_ptr, col, val, True, stream)
 
 
 def ci_hamiltonian_spmv(basis: Basis, prob: int, row_ptr, col, val, x, y=None, stream=None):

@@ -37,7 +37,7 @@ hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* 
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
 hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
                           int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
-                          int32_t* col, float* val, bool fill, hipStream_t s);
+                          int32_t* col, float* val, bool fill, int full, hipStream_t s);
 hipError_t launch_h3_index(bool fill, const BasisDev* B, int species, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
                            uint64_t* rec, hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
@@ -903,7 +903,7 @@ static std::vector<int> h3_words(const ci_basis* b)
     return w;
 }
 
-int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+static int h3_count_impl(ci_basis* b, int64_t* row_ptr, int64_t* nnz, int full, ci_stream stream)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
     if (int rc = h3_check(b)) return rc;
@@ -913,7 +913,7 @@ int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream
     const std::vector<int64_t> dims = h3_dims(b);
     const std::vector<int> words = h3_words(b);
     hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), b->h3_index.data(), n, nullptr, 0, 0, 0.0,
-                                  row_ptr, nullptr, nullptr, false, s);
+                                  row_ptr, nullptr, nullptr, false, full, s);
     if (e != hipSuccess) return hip_fail(e, "three-body count launch");
     e = launch_inclusive_scan(row_ptr, b->n_rowptr, b->d_scan_tmp, s);
     if (e != hipSuccess) return hip_fail(e, "scan launch");
@@ -929,8 +929,8 @@ int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream
     return CI_OK;
 }
 
-int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
-                         float* val, ci_stream stream)
+static int h3_fill_impl(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
+                        float* val, int full, ci_stream stream)
 {
     if (!b || !v3 || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
@@ -939,10 +939,32 @@ int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const 
     const std::vector<int64_t> dims = h3_dims(b);
     const std::vector<int> words = h3_words(b);
     hipError_t e = launch_h3_rows(b->d_bases, dims.data(), words.data(), b->h3_index.data(), (int)dims.size(), tbme,
-                                  v3->kind, v3->seed, v3->scale, const_cast<int64_t*>(row_ptr), col, val, true,
+                                  v3->kind, v3->seed, v3->scale, const_cast<int64_t*>(row_ptr), col, val, true, full,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "three-body fill launch");
     return CI_OK;
+}
+
+int ci_hamiltonian3_count(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    return h3_count_impl(b, row_ptr, nnz, 0, stream);
+}
+
+int ci_hamiltonian3_fill(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
+                         float* val, ci_stream stream)
+{
+    return h3_fill_impl(b, tbme, v3, row_ptr, col, val, 0, stream);
+}
+
+int ci_hamiltonian3_count_full(ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
+{
+    return h3_count_impl(b, row_ptr, nnz, 1, stream);
+}
+
+int ci_hamiltonian3_fill_full(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
+                              float* val, ci_stream stream)
+{
+    return h3_fill_impl(b, tbme, v3, row_ptr, col, val, 1, stream);
 }
 
 // Number of adjoint tiles of the handle for shape t (the device computes the

@@ -397,7 +397,7 @@ template <bool kFill, int W>
 __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restrict__ Bp, H3Indexes X,
                                                          const float* __restrict__ tbme, V3Param v3,
                                                          int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
-                                                         float* __restrict__ val)
+                                                         float* __restrict__ val, int full)
 {
     __shared__ int16_t occ_s[kH3Waves][kH3MaxA];
     __shared__ H3Queue queue_s[kH3Waves][2];
@@ -469,7 +469,8 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         wave_fence();
         nq[k] = 0;
     };
-    for (int b2 = b; b2 < B.nblk; b2++) {
+    // full: every column of the row (both triangles); else j >= i
+    for (int b2 = full ? 0 : b; b2 < B.nblk; b2++) {
         const BlockInfo bj = load_block(B.blk, b2);
         const int kp0 = uni(SP.key_off)[bj.kp], nKp = uni(SP.key_off)[bj.kp + 1] - kp0;
         const int kn0 = uni(SN.key_off)[bj.kn], nKn = bj.nkn;
@@ -488,7 +489,7 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
                 const int excl = read_lane(incl_scan64(cnt) - cnt, L);
                 const int pL = read_lane(pl, L);
                 int found = 0;
-                for (int nc = (b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
+                for (int nc = (!full && b2 == b && pL == ip ? in : 0); nc < nKn; nc += 64) {
                     const int nl = nc + lane;
                     uint64_t yn[W];
 #pragma unroll
@@ -573,7 +574,7 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
         if (same_n) {
             // the block holds the row's neutron key: every proton determinant
             // up to three away contributes; scan the proton key
-            for (int c = (b2 == b ? ip : 0); c < nKp; c += 64) {
+            for (int c = (!full && b2 == b ? ip : 0); c < nKp; c += 64) {
                 const int pl = c + lane;
                 uint64_t yp[W];
                 int dp = 4;
@@ -606,14 +607,14 @@ __global__ void __launch_bounds__(64 * kH3Waves) h3_rows(const BasisDev* __restr
 
 template <int W>
 static void launch_one(bool fill, unsigned grid, const BasisDev* B, const H3Indexes& X, const float* tbme,
-                       const V3Param& v3, int64_t* row_ptr, int32_t* col, float* val, hipStream_t s)
+                       const V3Param& v3, int64_t* row_ptr, int32_t* col, float* val, int full, hipStream_t s)
 {
     if (fill)
         hipLaunchKernelGGL((h3_rows<true, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, X, tbme, v3, row_ptr, col,
-                           val);
+                           val, full);
     else
         hipLaunchKernelGGL((h3_rows<false, W>), dim3(grid), dim3(64 * kH3Waves), 0, s, B, X, tbme, v3, row_ptr, col,
-                           val);
+                           val, full);
 }
 
 template <int W>
@@ -644,12 +645,13 @@ hipError_t launch_h3_index(bool fill, const BasisDev* B, int species, int64_t ns
 }
 
 // One launch per basis of the handle: count (row_ptr[R_b + 1 + i] = entries
-// of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]).
+// of row i, row_ptr[R_b] = 0) or fill (entries at row_ptr[R_b + i]); full:
+// every column of a row, else the upper triangle.
 // words[p]: 64-bit words per species bitstring of basis p (1..4); index[6p..]:
 // its neutron, then proton, partner index (seg, ptr, rec).
 hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
                           int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
-                          int32_t* col, float* val, bool fill, hipStream_t s)
+                          int32_t* col, float* val, bool fill, int full, hipStream_t s)
 {
     const V3Param v3{v3_kind, v3_seed, v3_scale};
     for (int p = 0; p < nb; p++) {
@@ -661,10 +663,10 @@ hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int*
                           {(const int32_t*)index[6 * p + 3], (const int64_t*)index[6 * p + 4],
                            (const uint64_t*)index[6 * p + 5]}};
         switch (words[p]) {
-        case 1: launch_one<1>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
-        case 2: launch_one<2>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
-        case 3: launch_one<3>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
-        default: launch_one<4>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, s); break;
+        case 1: launch_one<1>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, full, s); break;
+        case 2: launch_one<2>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, full, s); break;
+        case 3: launch_one<3>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, full, s); break;
+        default: launch_one<4>(fill, g, bases + p, X, tbme, v3, row_ptr, col, val, full, s); break;
         }
     }
     return hipGetLastError();

@@ -153,3 +153,62 @@ def test_without_three_body_term_it_is_the_two_body_matrix(ci):
     mask[at] = False
     assert bool((val3[mask] == 0).all())
     say("two-body entries", nnz2[0], "of", b.nnz3[0])
+
+
+def gpu3_full(ci, p, kind, tbme_seed):
+    import torch
+
+    b = ci.ci_basis_build([p])
+    rp, nnz = ci.ci_hamiltonian3_count_full(b)
+    tb = torch.from_numpy(si.tbme_f32(tbme_seed, b.n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian3_fill_full(b, tb, (kind, SEED, SCALE), rp)
+    torch.cuda.synchronize()
+    return b, rp, col, val
+
+
+@pytest.mark.parametrize("p", [(2, 1, 2, 1, -1), (2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1), (3, 3, 2, 0, 1)])
+def test_full_matrix_every_row(ci, p):
+    b, rp, col, val = gpu3_full(ci, p, 1, 44)
+    o = oracle3(p, 1, 44)
+    counts, cols, vals = o.rows3_full(np.arange(o.dim))
+    assert np.array_equal(np.diff(rp.cpu().numpy()), counts)
+    assert np.array_equal(col.cpu().numpy(), cols)
+    assert rel(val.cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1), (3, 3, 2, 0, 1)])
+def test_lanczos_with_three_body_term(ci, p):
+    # the lowest eigenpair of H with the three-body term: Lanczos on the GPU's
+    # full matrix against the oracle's dense eigensolver
+    b, rp, col, val = gpu3_full(ci, p, 1, 45)
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    o = oracle3(p, 1, 45)
+    E_ref, v_ref = o.lowest_eigenpair3()
+    say("lanczos with three-body term", p, "D", o.dim, "iters", it, "E", E, "ref", E_ref)
+    assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
+    assert abs(float(v.cpu().numpy() @ v_ref)) >= 1.0 - 1e-6
+
+
+def test_full_matrix_li6_sampled_and_lanczos(ci):
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp, col, val = gpu3_full(ci, w["problem"], 1, w["tbme_seed"])
+    D = b.info[0]["dim"]
+    rp_u, nnz_u = ci.ci_hamiltonian3_count(b)
+    assert b.nnz3_full[0] == 2 * nnz_u[0] - D
+    o = oracle3(w["problem"], 1, w["tbme_seed"])
+    rows = si.sample_rows(D, 30, seed=34)
+    counts, cols, vals = o.rows3_full(rows)
+    r = rp.cpu().numpy()
+    assert np.array_equal(r[rows + 1] - r[rows], counts)
+    pos = torch.from_numpy(np.concatenate([np.arange(r[i], r[i + 1]) for i in rows])).cuda()
+    assert np.array_equal(col[pos].cpu().numpy(), cols)
+    assert rel(val[pos].cpu().numpy().astype(np.float64), vals) <= VAL_TOL
+    E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-12)
+    Hv = ci.ci_hamiltonian_spmv(b, 0, rp, col, val, v)
+    res = float(torch.linalg.norm(Hv - E * v))
+    say("li6 with three-body term: nnz full", b.nnz3_full[0], "lanczos iters", it, "E", E, "residual", res)
+    assert res <= 1e-5 * abs(E)
+    del col, val
+    torch.cuda.empty_cache()

@@ -130,3 +130,20 @@ def test_symmetric(p):
     for _ in range(300):
         i, j = rng.integers(0, o.dim, 2)
         assert o.element3(i, j) == pytest.approx(o.element3(j, i), abs=1e-12)
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 1, 2, 1, 1)])
+def test_full_rows_are_upper_rows_and_their_transpose(p):
+    # every element below the diagonal is computed directly; it must equal
+    # the stored upper element (the matrix is symmetric)
+    o = oracle3(p)
+    D = o.dim
+    counts, cols, vals = o.rows3(np.arange(D))
+    U = np.zeros((D, D))
+    U[np.repeat(np.arange(D), counts), cols] = vals
+    H = U + np.triu(U, 1).T
+    fc, fcols, fvals = o.rows3_full(np.arange(D))
+    F = np.zeros((D, D))
+    F[np.repeat(np.arange(D), fc), fcols] = fvals
+    assert fc.sum() == 2 * counts.sum() - D
+    np.testing.assert_allclose(F, H, rtol=0, atol=1e-11)
