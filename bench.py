@@ -114,7 +114,8 @@ def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
     # the same on one thread, on a smaller sample (~3 s)
     oracle.set_threads(1)
     try:
-        n1, t1, nr1 = run(max(32, int(nr * 3.0 / max(t * threads, 1e-3))), 4)
+        _, tp, np_ = run(64, 5)  # probe, then ~3 s
+        n1, t1, nr1 = run(int(min(o.dim, max(64, np_ * 3.0 / max(tp, 1e-3)))), 4)
     finally:
         oracle.set_threads(threads)
     return {
