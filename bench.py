@@ -5,8 +5,11 @@ One step is the whole construction path for one problem, starting from the
 problem description and the two-body table resident in HBM:
     ci_basis_build  (basis indexing, one upload)
     ci_hamiltonian_count (count + scan; one sync to read nnz)
-    ci_hamiltonian_fill  (col/val of every stored entry)
-    ci_hamiltonian_vjp   (adjoint onto the table, upstream G_e = psi_i psi_j)
+    ci_hamiltonian_fill_keys  (col/val of every stored entry, plus one
+                               structure word per entry for the adjoint)
+    ci_hamiltonian_vjp_keys   (adjoint onto the table, upstream G_e = psi_i psi_j)
+(--adjoint walk: ci_hamiltonian_fill + ci_hamiltonian_vjp, which walks the
+partner lists again instead of reading stored words.)
 value = nnz / (seconds per step).  The default workload is 6Li, Nmax = 6,
 2M = 2, positive parity (D = 186,894, 55.5 M stored entries).
 
@@ -319,7 +322,7 @@ def run_three_body_term(ci, torch, prob, tbme_seed, with_oracle, reps=3):
     return res
 
 
-def run_batched(ci, torch, steps, warmup):
+def run_batched(ci, torch, steps, warmup, stored):
     """64 bases in one handle; fill + vjp captured in one HIP graph."""
     import seeded_inputs as si
 
@@ -347,18 +350,26 @@ def run_batched(ci, torch, steps, warmup):
     t0 = time.perf_counter()
     tuning = ci.ci_hamiltonian_tune(b, tb, rp, col, val, G, gt, work, reps=2)
     t_tune = time.perf_counter() - t0
+    keys = torch.empty(tot if stored else 0, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
+
+    def one():
+        if stored:
+            ci.ci_hamiltonian_fill_keys(b, tb, rp, col, val, keys)
+            ci.ci_hamiltonian_vjp_keys(b, rp, keys, G, gt, work)
+        else:
+            ci.ci_hamiltonian_fill(b, tb, rp, col, val)
+            ci.ci_hamiltonian_vjp(b, rp, G, gt, work)
+
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         for _ in range(2):
-            ci.ci_hamiltonian_fill(b, tb, rp, col, val)
-            ci.ci_hamiltonian_vjp(b, rp, G, gt, work)
+            one()
     torch.cuda.current_stream().wait_stream(s)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        ci.ci_hamiltonian_fill(b, tb, rp, col, val)
-        ci.ci_hamiltonian_vjp(b, rp, G, gt, work)
+        one()
     for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
@@ -371,7 +382,8 @@ def run_batched(ci, torch, steps, warmup):
     ms = a.elapsed_time(e) / steps
     out = {"bases": len(probs), "dim_total": int(sum(i["dim"] for i in b.info)), "nnz_total": tot,
            "ms_per_replay": ms, "nnz_per_s": tot / (ms * 1e-3), "setup_s": t_setup,
-           "graph": "fill + vjp of all bases, one capture", "tuning": dict(tuning, tune_s=t_tune)}
+           "graph": "fill + vjp of all bases, one capture", "adjoint": "stored" if stored else "walk",
+           "tuning": dict(tuning, tune_s=t_tune)}
     b.free()
     return out
 
@@ -392,8 +404,12 @@ def main():
                     help="run only the timed construction steps (no ceiling probes, Lanczos, three-body or "
                          "batched sections): for counter and trace runs of the step's kernels")
     ap.add_argument("--tuning", default=None, metavar="W,G,R,N,P",
-                    help="fixed launch shapes row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent instead "
+                    help="fixed launch shapes row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent"
+                         "[,adjk_rows,adjk_tile_n] instead "
                          "of the autotuner (for profiling runs)")
+    ap.add_argument("--adjoint", choices=("stored", "walk"), default="stored",
+                    help="stored: the fill stores one structure word per entry and the adjoint reads them; "
+                         "walk: the adjoint walks the partner lists again")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device to device three times (a plain "
                          "copy of known size, to scale hardware byte counters under rocprofv3)")
@@ -443,7 +459,8 @@ def main():
     fixed = None
     t0 = time.perf_counter()
     if args.tuning:
-        fixed = dict(zip(("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent"),
+        fixed = dict(zip(("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows",
+                          "adjk_tile_n"),
                          (int(x) for x in args.tuning.split(","))))
         b.tuning = fixed
         tuning = b.tuning
@@ -454,7 +471,21 @@ def main():
     b.free()
     col = torch.empty(nnz, dtype=torch.int32, device="cuda")
     val = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    stored = args.adjoint == "stored"
+    keys = torch.empty(nnz if stored else 0, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
+
+    def fill(h, r):
+        if stored:
+            ci.ci_hamiltonian_fill_keys(h, tbme, r, col, val, keys)
+        else:
+            ci.ci_hamiltonian_fill(h, tbme, r, col, val)
+
+    def vjp(h, r):
+        if stored:
+            ci.ci_hamiltonian_vjp_keys(h, r, keys, G, gt, work)
+        else:
+            ci.ci_hamiltonian_vjp(h, r, G, gt, work)
 
     t_basis, t_count = [], []
     ev_fill, ev_vjp = EventTimer(torch, stream), EventTimer(torch, stream)
@@ -471,12 +502,12 @@ def main():
             t_basis.append(t1 - t0)
             t_count.append(t2 - t1)
             with ev_fill:
-                ci.ci_hamiltonian_fill(h, tbme, r, col, val)
+                fill(h, r)
             with ev_vjp:
-                ci.ci_hamiltonian_vjp(h, r, G, gt, work)
+                vjp(h, r)
         else:
-            ci.ci_hamiltonian_fill(h, tbme, r, col, val)
-            ci.ci_hamiltonian_vjp(h, r, G, gt, work)
+            fill(h, r)
+            vjp(h, r)
         torch.cuda.synchronize()
         h.free()
 
@@ -494,14 +525,16 @@ def main():
     fill_ms = ev_fill.mean_ms()
     vjp_ms = ev_vjp.mean_ms()
     # dominant kernel: the fill writes 8 B per stored entry (int32 col + FP32
-    # val) and reads 8 B per row of row_ptr; that is its algorithmic traffic
+    # val; 12 B with the stored word) and reads 8 B per row of row_ptr; that
+    # is its algorithmic traffic
     dom, dom_ms = ("fill", fill_ms) if fill_ms >= vjp_ms else ("vjp", vjp_ms)
     if dom == "fill":
-        alg_bytes = 8 * nnz + 8 * (D + 1)
+        alg_bytes = (12 if stored else 8) * nnz + 8 * (D + 1)
         traffic = measured_traffic("row_kernel_fill_%s.md" % args.workload)
-    else:  # reads 4 B of upstream gradient per entry + row_ptr, writes the table
-        alg_bytes = 4 * nnz + 8 * (D + 1) + 4 * n_tbme
-        traffic = measured_traffic("adjoint_kernel_%s.md" % args.workload)
+    else:  # reads 4 B of upstream gradient (and 4 B of stored word) per entry + row_ptr, writes the table
+        alg_bytes = (8 if stored else 4) * nnz + 8 * (D + 1) + 4 * n_tbme
+        traffic = measured_traffic(("adjoint_stored_kernel_%s.md" if stored else "adjoint_kernel_%s.md")
+                                   % args.workload)
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     res = {
         "metric": "Hamiltonian nonzeros/sec (fwd, adjoint, batched) + roofline fraction, 1 MI355X",
@@ -518,7 +551,8 @@ def main():
         "data": "synthetic: seeded N(0,1) MeV two-body table, seeded psi for the upstream gradient",
         "config": {"workload": args.workload, "Z": prob[0], "N": prob[1], "nmax": prob[2],
                    "two_m": prob[3], "parity": prob[4], "dim": D, "nnz": nnz, "n_tbme": n_tbme,
-                   "step": "basis build + count/scan + fill + vjp"},
+                   "step": "basis build + count/scan + fill + vjp",
+                   "adjoint": "stored structure words" if stored else "partner-list walk"},
         "stages_ms": {"basis_build": 1e3 * float(np.mean(t_basis)), "count_scan_sync": 1e3 * float(np.mean(t_count)),
                       "fill": fill_ms, "vjp": vjp_ms},
         "tuning": dict(tuning, tune_s=t_tune, source="fixed" if fixed else "autotuner"),
@@ -548,7 +582,7 @@ def main():
     res["three_body_term"] = run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)
     if not args.no_batched:
         log("batched")
-        res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1)
+        res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1, stored)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(prob, w["tbme_seed"], si.PSI_SEED.get(args.workload, 0))

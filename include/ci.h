@@ -113,13 +113,17 @@ typedef struct ci_basis ci_basis; /* opaque */
  * workgroup a tile of rows of one block -- tn = min(adj_tile_n, |Kn|) neutron
  * determinants times tp = max(1, adj_rows / tn) proton determinants -- whose
  * contributions are summed in one shared-memory table before they reach the
- * FP64 accumulators. */
+ * FP64 accumulators; the adjoint from stored words (ci_hamiltonian_vjp_keys)
+ * has its own tile fields, adjk_rows and adjk_tile_n (default 64 and 8),
+ * which ci_hamiltonian_tune leaves as they are. */
 typedef struct {
     int32_t row_waves;      /* wavefronts per workgroup of count and fill: 4 or 8 */
     int32_t row_grab;       /* 0: one grid over all rows; 1..4096: persistent, rows per grab */
     int32_t adj_rows;       /* adjoint: target rows per tile, 1..4096 */
     int32_t adj_tile_n;     /* adjoint: neutron determinants per tile, 1..4096 */
     int32_t adj_persistent; /* adjoint: 0 one workgroup per tile, 1 persistent workgroups */
+    int32_t adjk_rows;      /* adjoint from stored words: target rows per tile, 1..4096 */
+    int32_t adjk_tile_n;    /* adjoint from stored words: neutron determinants per tile, 1..4096 */
 } ci_tuning;
 
 /* Thread-local text of the last error. */
@@ -168,6 +172,24 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
  * of at least ci_vjp_work_bytes(b) bytes (FP64 accumulators).  Asynchronous. */
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val,
                        float* grad_tbme, void* work, size_t work_bytes, ci_stream stream);
+
+/* The fill and its adjoint with the structure stored instead of recomputed:
+ * ci_hamiltonian_fill_keys writes what ci_hamiltonian_fill writes (the same
+ * col and val bits) and also keys (device uint32, one word per stored entry,
+ * same positions): for an entry that is one two-body term, its position in
+ * the basis' table (low 30 bits; all ones when no table element exists) and
+ * its sign (bit 30); for the diagonal and one-nucleon differences (several
+ * terms, Sec. 2), bit 31 and a record of the moved nucleon.  The words are
+ * opaque to the caller and valid for this handle and row_ptr only.
+ * ci_hamiltonian_vjp_keys computes what ci_hamiltonian_vjp computes from
+ * those words (row_ptr, grad_val, grad_tbme, work as there) without walking
+ * the partner lists again.  CI_EINVAL for null pointers, CI_EUNSUPPORTED when
+ * a basis' table has 2^30 - 1 or more elements.  Asynchronous. */
+int ci_hamiltonian_fill_keys(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                             float* val, uint32_t* keys, ci_stream stream);
+int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uint32_t* keys,
+                            const float* grad_val, float* grad_tbme, void* work, size_t work_bytes,
+                            ci_stream stream);
 
 /* The same two passes for the FULL symmetric matrix (both triangles, every
  * (i, j) with d(i, j) <= 2, columns ascending in a row), as the eigensolver

@@ -12,6 +12,7 @@ Entry points (same names as the C ABI):
   ci_hamiltonian_count(basis) -> (row_ptr, nnz)            count pass (Sec. 4.1)
   ci_hamiltonian_fill(basis, tbme, row_ptr) -> (col, val)  fill pass (Sec. 2, 4.1)
   ci_hamiltonian_vjp(basis, row_ptr, grad_val) -> grad_tbme  adjoint
+  ci_hamiltonian_fill_keys / ci_hamiltonian_vjp_keys       the same with the structure stored per entry
   CIHamiltonian.apply(tbme, basis, row_ptr, col) -> val      autograd wrapper
 """
 from __future__ import annotations
@@ -65,7 +66,8 @@ CI_V3_NONE, CI_V3_SYNTHETIC, CI_V3_IDENTITY = 0, 1, 2
 
 class ci_tuning(ctypes.Structure):
     _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
-                ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32)]
+                ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32), ("adjk_rows", ctypes.c_int32),
+                ("adjk_tile_n", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -74,6 +76,7 @@ class ci_tuning(ctypes.Structure):
 # every symbol include/ci.h declares
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
+           "ci_hamiltonian_fill_keys", "ci_hamiltonian_vjp_keys",
            "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill",
            "ci_hamiltonian3_count_full", "ci_hamiltonian3_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
            "ci_lanczos_work_bytes",
@@ -104,6 +107,8 @@ def load_library():
     L.ci_hamiltonian_count.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.ci_hamiltonian_fill_keys.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.ci_hamiltonian_vjp_keys.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.ci_hamiltonian_count_full.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill_full.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_spmv.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
@@ -433,6 +438,47 @@ def ci_hamiltonian_vjp(basis: Basis, row_ptr, grad_val, grad_tbme=None, work=Non
     return grad_tbme
 
 
+def ci_hamiltonian_fill_keys(basis: Basis, tbme, row_ptr, col=None, val=None, keys=None, stream=None):
+    """Fill pass that also stores one structure word per entry (int32 device
+    tensor; opaque) for ci_hamiltonian_vjp_keys: (col, val, keys)."""
+    torch = _torch()
+    if basis.nnz is None:
+        raise RuntimeError("call ci_hamiltonian_count first")
+    tot = sum(basis.nnz)
+    _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    if col is None:
+        col = torch.empty(tot, dtype=torch.int32, device=basis.device)
+    if val is None:
+        val = torch.empty(tot, dtype=torch.float32, device=basis.device)
+    if keys is None:
+        keys = torch.empty(tot, dtype=torch.int32, device=basis.device)
+    _check_tensor(col, torch.int32, tot, "col")
+    _check_tensor(val, torch.float32, tot, "val")
+    _check_tensor(keys, torch.int32, tot, "keys")
+    _check(load_library().ci_hamiltonian_fill_keys(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                                   _ptr(keys), _stream_ptr(stream)))
+    return col, val, keys
+
+
+def ci_hamiltonian_vjp_keys(basis: Basis, row_ptr, keys, grad_val, grad_tbme=None, work=None, stream=None):
+    """Adjoint from the words of ci_hamiltonian_fill_keys: grad_tbme as ci_hamiltonian_vjp."""
+    torch = _torch()
+    tot = sum(basis.nnz)
+    _check_tensor(row_ptr, torch.int64, basis.n_rowptr, "row_ptr")
+    _check_tensor(keys, torch.int32, tot, "keys")
+    _check_tensor(grad_val, torch.float32, tot, "grad_val")
+    if grad_tbme is None:
+        grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
+    nwork = basis.vjp_work_bytes()
+    if work is None:
+        work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
+    _check(load_library().ci_hamiltonian_vjp_keys(basis.handle, _ptr(row_ptr), _ptr(keys), _ptr(grad_val),
+                                                  _ptr(grad_tbme), _ptr(work), work.numel() * work.element_size(),
+                                                  _stream_ptr(stream)))
+    return grad_tbme
+
+
 def ci_hamiltonian_tune(basis: Basis, tbme, row_ptr, col, val, grad_val, grad_tbme=None, work=None,
                         reps: int = 3, stream=None) -> dict:
     """Autotuner: times the launch shapes of fill and adjoint on these buffers,
@@ -556,20 +602,32 @@ def _make_autograd():
     import torch
 
     class CIHamiltonian(torch.autograd.Function):
-        """val = H(tbme) on a fixed structure; backward runs the adjoint kernel."""
+        """val = H(tbme) on a fixed structure; backward runs the adjoint kernel.
+
+        store_keys: the forward also stores one structure word per entry (4
+        bytes each, kept until backward) and the backward reads them instead
+        of walking the partner lists again."""
 
         @staticmethod
-        def forward(ctx, tbme, basis, row_ptr, col=None):
-            _, val = ci_hamiltonian_fill(basis, tbme.detach().contiguous(), row_ptr, col=col)
+        def forward(ctx, tbme, basis, row_ptr, col=None, store_keys=True):
             ctx.basis = basis
-            ctx.save_for_backward(row_ptr)
+            if store_keys:
+                _, val, keys = ci_hamiltonian_fill_keys(basis, tbme.detach().contiguous(), row_ptr, col=col)
+                ctx.save_for_backward(row_ptr, keys)
+            else:
+                _, val = ci_hamiltonian_fill(basis, tbme.detach().contiguous(), row_ptr, col=col)
+                ctx.save_for_backward(row_ptr)
             return val
 
         @staticmethod
         def backward(ctx, gval):
-            (row_ptr,) = ctx.saved_tensors
-            g = ci_hamiltonian_vjp(ctx.basis, row_ptr, gval.contiguous().to(torch.float32))
-            return g, None, None, None
+            saved = ctx.saved_tensors
+            gval = gval.contiguous().to(torch.float32)
+            if len(saved) == 2:
+                g = ci_hamiltonian_vjp_keys(ctx.basis, saved[0], saved[1], gval)
+            else:
+                g = ci_hamiltonian_vjp(ctx.basis, saved[0], gval)
+            return g, None, None, None, None
 
     return CIHamiltonian
 

@@ -22,11 +22,11 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
                       int n, hipStream_t s);
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
+                       uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
 hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
                       int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
-                      const float* gval, float* gtbme, double* gacc, int64_t ntbme, const ci_tuning& t,
-                      unsigned long long* queue, hipStream_t s);
+                      const float* gval, const uint32_t* keys, float* gtbme, double* gacc, int64_t ntbme,
+                      const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
@@ -345,7 +345,7 @@ std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 64, 8}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
@@ -799,11 +799,11 @@ static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int ful
 }
 
 static int fill_impl(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
-                     int full, hipStream_t s)
+                     uint32_t* keys, int full, hipStream_t s)
 {
     if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
     hipError_t e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr,
-                               b->n_rowptr, col, val, b->tune, b->d_queue, full, s);
+                               b->n_rowptr, col, val, keys, b->tune, b->d_queue, full, s);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
     return CI_OK;
 }
@@ -816,7 +816,24 @@ int ci_hamiltonian_count(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_s
 int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
                         float* val, ci_stream stream)
 {
-    return fill_impl(b, tbme, row_ptr, col, val, 0, (hipStream_t)stream);
+    return fill_impl(b, tbme, row_ptr, col, val, nullptr, 0, (hipStream_t)stream);
+}
+
+// The stored words hold a table position of the entry's basis in 30 bits.
+static bool keys_fit(const ci_basis* b)
+{
+    for (const auto& i : b->info)
+        if (i.n_tbme >= (int64_t)0x3fffffff) return false;
+    return true;
+}
+
+int ci_hamiltonian_fill_keys(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
+                             float* val, uint32_t* keys, ci_stream stream)
+{
+    if (!b) return fail(CI_EINVAL, "null pointer");
+    if (!keys && b->nrows > 0) return fail(CI_EINVAL, "null pointer");
+    if (!keys_fit(b)) return fail(CI_EUNSUPPORTED, "two-body table too large for the stored words");
+    return fill_impl(b, tbme, row_ptr, col, val, keys, 0, (hipStream_t)stream);
 }
 
 int ci_hamiltonian_count_full(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, ci_stream stream)
@@ -827,7 +844,7 @@ int ci_hamiltonian_count_full(const ci_basis* b, int64_t* row_ptr, int64_t* nnz,
 int ci_hamiltonian_fill_full(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
                              float* val, ci_stream stream)
 {
-    return fill_impl(b, tbme, row_ptr, col, val, 1, (hipStream_t)stream);
+    return fill_impl(b, tbme, row_ptr, col, val, nullptr, 1, (hipStream_t)stream);
 }
 
 static int h3_check(const ci_basis* b)
@@ -969,8 +986,9 @@ int ci_hamiltonian3_fill_full(ci_basis* b, const float* tbme, const ci_v3* v3, c
 
 // Number of adjoint tiles of the handle for shape t (the device computes the
 // same counts in tile_offsets).
-static int64_t count_tiles(const ci_basis* b, const ci_tuning& t)
+static int64_t count_tiles(const ci_basis* b, const ci_tuning& t, bool stored)
 {
+    const int64_t rows = stored ? t.adjk_rows : t.adj_rows, tile_n = stored ? t.adjk_tile_n : t.adj_tile_n;
     int64_t n = 0;
     for (size_t p = 0; p < b->host.size(); p++) {
         const HostBasis& hb = *b->host[p];
@@ -978,8 +996,8 @@ static int64_t count_tiles(const ci_basis* b, const ci_tuning& t)
             const HostSpecies &P = hb.sp[0], &N = hb.sp[1];
             const int64_t nKp = P.key_off[hb.blk_kp[bi] + 1] - P.key_off[hb.blk_kp[bi]];
             const int64_t nKn = N.key_off[hb.blk_kn[bi] + 1] - N.key_off[hb.blk_kn[bi]];
-            const int64_t tn = std::min<int64_t>(t.adj_tile_n, nKn);
-            const int64_t tp = std::max<int64_t>(1, t.adj_rows / tn);
+            const int64_t tn = std::min<int64_t>(tile_n, nKn);
+            const int64_t tp = std::max<int64_t>(1, rows / tn);
             n += ((nKp + tp - 1) / tp) * ((nKn + tn - 1) / tn);
         }
     }
@@ -987,11 +1005,12 @@ static int64_t count_tiles(const ci_basis* b, const ci_tuning& t)
 }
 
 static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
-                             void* work, const ci_tuning& t, hipStream_t s)
+                             void* work, const ci_tuning& t, hipStream_t s, const uint32_t* keys = nullptr)
 {
-    return launch_vjp(b->d_bases, b->d_blk_basis, b->d_blk_local, b->nblocks, count_tiles(b, t), b->d_tile_off,
-                      b->nrows, row_ptr, b->n_rowptr, grad_val, grad_tbme, (double*)work, b->n_tbme, t, b->d_queue,
-                      s);
+    return launch_vjp(b->d_bases, b->d_blk_basis, b->d_blk_local, b->nblocks, count_tiles(b, t, keys != nullptr),
+                      b->d_tile_off,
+                      b->nrows, row_ptr, b->n_rowptr, grad_val, keys, grad_tbme, (double*)work, b->n_tbme, t,
+                      b->d_queue, s);
 }
 
 size_t ci_vjp_work_bytes(const ci_basis* b) { return b ? (size_t)b->n_tbme * sizeof(double) : 0; }
@@ -999,7 +1018,8 @@ size_t ci_vjp_work_bytes(const ci_basis* b) { return b ? (size_t)b->n_tbme * siz
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
                        void* work, size_t work_bytes, ci_stream stream)
 {
-    if (!b || !row_ptr || !grad_val) return fail(CI_EINVAL, "null pointer");
+    // every row stores its diagonal, so grad_val may be null only without rows
+    if (!b || !row_ptr || (!grad_val && b->nrows > 0)) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
@@ -1008,11 +1028,25 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
     return CI_OK;
 }
 
+int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uint32_t* keys, const float* grad_val,
+                            float* grad_tbme, void* work, size_t work_bytes, ci_stream stream)
+{
+    if (!b || !row_ptr || ((!grad_val || !keys) && b->nrows > 0)) return fail(CI_EINVAL, "null pointer");
+    if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
+    if (!keys_fit(b)) return fail(CI_EUNSUPPORTED, "two-body table too large for the stored words");
+    if (work_bytes < ci_vjp_work_bytes(b))
+        return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
+    hipError_t e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, (hipStream_t)stream, keys);
+    if (e != hipSuccess) return hip_fail(e, "vjp launch");
+    return CI_OK;
+}
+
 static bool tuning_ok(const ci_tuning& t)
 {
     return (t.row_waves == 4 || t.row_waves == 8) && t.row_grab >= 0 && t.row_grab <= 4096 && t.adj_rows >= 1 &&
            t.adj_rows <= 4096 && t.adj_tile_n >= 1 && t.adj_tile_n <= 4096 &&
-           (t.adj_persistent == 0 || t.adj_persistent == 1);
+           (t.adj_persistent == 0 || t.adj_persistent == 1) && t.adjk_rows >= 1 && t.adjk_rows <= 4096 &&
+           t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096;
 }
 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
@@ -1063,7 +1097,8 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
             b->tune.row_grab = grab;
             float ms = 0.0f;
             rc = time_ms([&] { return launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme,
-                                                  row_ptr, b->n_rowptr, col, val, b->tune, b->d_queue, 0, s); },
+                                                  row_ptr, b->n_rowptr, col, val, nullptr, b->tune, b->d_queue, 0,
+                                                  s); },
                          reps, s, e0, e1, &ms);
             if (rc == CI_OK && (!have || ms < best_ms)) {
                 best_ms = ms;
@@ -1103,7 +1138,7 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     remember_tuning(b->probs, best);
     // leave col / val / grad_tbme as the chosen shapes compute them
     e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
-                    val, b->tune, b->d_queue, 0, s);
+                    val, nullptr, b->tune, b->d_queue, 0, s);
     if (e == hipSuccess) e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "autotune final run");

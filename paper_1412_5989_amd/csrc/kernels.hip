@@ -95,9 +95,15 @@ __device__ __forceinline__ cptr<T> cst(const T* p)
 // proton determinant, and overlapping neutron moves), so the number of
 // device-scope atomics drops by that reuse factor.  A key that finds no slot
 // within kAdjProbes probes goes to the accumulator directly.
+// Two workgroup shapes: the adjoint that walks the partner lists has work to
+// overlap with its device-scope atomics and runs best at 8 wavefronts and a
+// 4096-slot table (three workgroups per CU); the adjoint that reads stored
+// words has little, and runs best with fewer atomics: 16 wavefronts sharing a
+// 16384-slot table (128 KiB of the CU's 160 KiB, one workgroup per CU).
 constexpr int kAdjWaves = 8;
 constexpr int kAdjSlotBits = 12;
-constexpr int kAdjSlots = 1 << kAdjSlotBits;
+constexpr int kAdjKeysWaves = 16;
+constexpr int kAdjKeysSlotBits = 14;
 constexpr int kAdjProbes = 8;
 constexpr uint32_t kAdjEmpty = 0xffffffffu;
 
@@ -217,6 +223,15 @@ __device__ __forceinline__ int lane_search64(int start, int x)
     return lo;
 }
 
+// Word stored per entry for the adjoint: a single two-body term holds its
+// table position in the low 30 bits (kKeyNone: no table element, the entry is
+// 0) and its sign in bit 30; a multi-term entry (diagonal, one nucleon moved)
+// sets bit 31 and holds its queue record in the low 25 bits.
+constexpr uint32_t kKeySpecial = 0x80000000u;
+constexpr uint32_t kKeyNeg = 0x40000000u;
+constexpr uint32_t kKeyPos = 0x3fffffffu;
+constexpr uint32_t kKeyNone = 0x3fffffffu;
+
 struct RowView {
     const BasisDev* B;
     const float* tbme;  // this basis' table (fill)
@@ -227,9 +242,11 @@ struct RowView {
     lptr<uint32_t> hkey;
     lptr<float> hval;
     bool use_table;
+    int hbits;  // the table has 1 << hbits slots
     const float* gval;  // upstream values (adjoint)
     int32_t* col;
     float* val;
+    uint32_t* keys;  // one word per stored entry (written by the fill, read by the adjoint), or null
     int64_t pos0;  // first entry of the row
     int64_t cap;   // end of all entries (no access at or beyond)
     int Z, NN;     // particles
@@ -242,7 +259,7 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
 {
     if (R.use_table) {
         const uint32_t gk = (uint32_t)(R.tbme0 + k);
-        uint32_t s = (gk * 2654435761u) >> (32 - kAdjSlotBits);
+        uint32_t s = (gk * 2654435761u) >> (32 - R.hbits);
         for (int t = 0; t < kAdjProbes; t++) {
             // claim an empty slot, or learn which key holds it (one LDS round trip)
             uint32_t cur = kAdjEmpty;
@@ -252,7 +269,7 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
                 __hip_atomic_fetch_add(R.hval + s, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return;
             }
-            s = (s + 1) & (kAdjSlots - 1);
+            s = (s + 1) & ((1u << R.hbits) - 1);
         }
     }
     atomic_add_f64(glbw(R.gacc) + k, (double)g);
@@ -420,6 +437,33 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
     wave_sync();
 }
 
+// Occupied orbits of row (gP, gN) into L.occ, for the multi-term entries:
+// lane j < 2W holds determinant word j (protons, then neutrons), a wave scan
+// gives each word's first slot in occ, and the shells of the occupied orbits
+// give the single-particle sum.
+__device__ void row_occ(const BasisDev& B, WaveLds& L, RowView& R, int gP, int gN)
+{
+    const int lane = threadIdx.x & 63;
+    const SpeciesDev& SP = B.sp[0];
+    const SpeciesDev& SN = B.sp[1];
+    const int W = B.W;
+    uint64_t word = 0;
+    if (lane < 2 * W)
+        word = lane < W ? glb(SP.sd)[(int64_t)gP * W + lane] : glb(SN.sd)[(int64_t)gN * W + (lane - W)];
+    const int cnt = __popcll(word);
+    int t = wave_incl_scan(cnt) - cnt;
+    const int obase = (lane < W ? lane : lane - W) * 64;
+    for (uint64_t x = word; x; x &= x - 1) L.occ[t++] = (uint8_t)(obase + __ffsll((long long)x) - 1);
+    wave_sync();
+    const int A = R.Z + R.NN;
+    int shells = 0;
+    for (int j0 = 0; j0 < A; j0 += 64) {
+        const int j = j0 + lane;
+        shells += lane63(wave_incl_scan(j < A ? glb(B.orb_n)[L.occ[j]] : 0));
+    }
+    R.spe_sum = ((double)shells + 1.5 * A) * B.hw;
+}
+
 // One row: count (returns the number of entries), fill or adjoint.
 template <int MODE>
 __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView& R)
@@ -444,28 +488,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     const gptr<int32_t> sN12 = glb(SN.seg12 + (int64_t)gN * (nkn + 1));
     const int self12 = uniform(cst(SN.self12)[gN]);
 
-    if (MODE != kCount) {
-        // occupied orbits of the row (for the multi-term entries): lane j < 2W
-        // holds determinant word j (protons, then neutrons), a wave scan gives
-        // each word's first slot in occ, and the shells of the occupied orbits
-        // give the single-particle sum
-        const int W = B.W;
-        uint64_t word = 0;
-        if (lane < 2 * W)
-            word = lane < W ? glb(SP.sd)[(int64_t)gP * W + lane] : glb(SN.sd)[(int64_t)gN * W + (lane - W)];
-        const int cnt = __popcll(word);
-        int t = wave_incl_scan(cnt) - cnt;
-        const int obase = (lane < W ? lane : lane - W) * 64;
-        for (uint64_t x = word; x; x &= x - 1) L.occ[t++] = (uint8_t)(obase + __ffsll((long long)x) - 1);
-        wave_sync();
-        const int A = R.Z + R.NN;
-        int shells = 0;
-        for (int j0 = 0; j0 < A; j0 += 64) {
-            const int j = j0 + lane;
-            shells += lane63(wave_incl_scan(j < A ? glb(B.orb_n)[L.occ[j]] : 0));
-        }
-        R.spe_sum = ((double)shells + 1.5 * A) * B.hw;
-    }
+    if (MODE != kCount) row_occ(B, L, R, gP, gN);
 
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
@@ -594,6 +617,9 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                         qr = kind | ((uint32_t)rec_h1(mr) << 8) | ((uint32_t)rec_p1(mr) << 16) |
                              ((uint32_t)rec_neg(mr) << 24);
                     }
+                    if (MODE == kFill && R.keys && p < R.cap)
+                        glbw(R.keys)[p] = special ? (kKeySpecial | qr)
+                                                  : (key >= 0 ? ((uint32_t)key | (neg ? kKeyNeg : 0u)) : kKeyNone);
                 }
                 const uint64_t m = __ballot(special);
                 if (m) {
@@ -618,12 +644,54 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     return pos;
 }
 
+// Adjoint of one row from the words the fill stored (R.keys): the row's
+// entries [R.pos0, end) are read in order, single terms go straight to the
+// accumulators and multi-term entries through the queue; the partner lists
+// are not walked.
+__device__ void do_row_keys(const BasisDev& B, WaveLds& L, int bi, int r, RowView& R, int64_t end)
+{
+    const int lane = threadIdx.x & 63;
+    const int kp = uniform(cst(B.blk_kp)[bi]), kn = uniform(cst(B.blk_kn)[bi]);
+    const cptr<int32_t> pkoff = cst(B.sp[0].key_off), nkoff = cst(B.sp[1].key_off);
+    const int nKn = nkoff[kn + 1] - nkoff[kn];
+    const int ip = uniform(r / nKn), in = uniform(r - ip * nKn);
+    row_occ(B, L, R, uniform(pkoff[kp] + ip), uniform(nkoff[kn] + in));
+    const int64_t n = (end < R.cap ? end : R.cap) - R.pos0;
+    int qn = 0;
+    for (int64_t e0 = 0; e0 < n; e0 += 64) {
+        const int64_t e = e0 + lane;
+        uint32_t k = 0;
+        float g = 0.0f;
+        if (e < n) {
+            k = glb(R.keys)[R.pos0 + e];
+            g = glb(R.gval)[R.pos0 + e];
+        }
+        const bool special = e < n && (k & kKeySpecial);
+        if (e < n && !special && (k & kKeyPos) != kKeyNone) adj_add(R, (int)(k & kKeyPos), (k & kKeyNeg) ? -g : g);
+        const uint64_t m = __ballot(special);
+        if (m) {
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            if (special) {
+                L.qpos[qn + rank] = (int32_t)e;
+                L.qrec[qn + rank] = k & ~kKeySpecial;
+            }
+            qn += __popcll(m);
+            wave_sync();
+            if (qn > kQueue - 64) {  // room for one more round
+                flush_queue<kAdjoint>(R, L, qn);
+                qn = 0;
+            }
+        }
+    }
+    flush_queue<kAdjoint>(R, L, qn);
+}
+
 template <int MODE>
 __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int r, const float* __restrict__ tbme,
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
                                            double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, bool full, WaveLds& L);
+                                           bool use_table, int hbits, bool full, uint32_t* keys, WaveLds& L);
 
 // Row grow of the batch (rows of all bases are numbered consecutively) on the
 // calling wavefront.
@@ -634,7 +702,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
                                         int64_t nrp, int32_t* __restrict__ col, float* __restrict__ val,
                                         const float* __restrict__ gval, double* __restrict__ gacc,
                                         lptr<uint32_t> hkey, lptr<float> hval, bool use_table, bool full,
-                                        WaveLds& L)
+                                        uint32_t* keys, WaveLds& L)
 {
     // basis of the row (few bases: linear search)
     int b = 0;
@@ -652,7 +720,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
     }
     const int bi = uniform(lo);
     run_row_at<MODE>(B, bi, i, i - (int)blk_off[bi], tbme, row_ptr, nrp, col, val, gval, gacc, hkey, hval, use_table,
-                     full, L);
+                     0, full, keys, L);
 }
 
 // Row i of basis B, row r of its block bi.
@@ -661,7 +729,7 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
                                            double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, bool full, WaveLds& L)
+                                           bool use_table, int hbits, bool full, uint32_t* keys, WaveLds& L)
 {
     RowView R;
     R.B = &B;
@@ -671,9 +739,11 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
     R.hkey = hkey;
     R.hval = hval;
     R.use_table = use_table;
+    R.hbits = hbits;
     R.gval = gval;
     R.col = col;
     R.val = val;
+    R.keys = keys;
     R.Z = B.Z;
     R.NN = B.NN;
     R.spe_sum = 0.0;
@@ -686,7 +756,10 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
     } else {
         R.pos0 = uniform64(cst(row_ptr)[B.row0 + i]);
         R.cap = uniform64(cst(row_ptr)[nrp - 1]);  // the entries of all bases end here
-        do_row<MODE>(B, L, bi, r, R);
+        if (MODE == kAdjoint && keys)
+            do_row_keys(B, L, bi, r, R, uniform64(cst(row_ptr)[B.row0 + i + 1]));
+        else
+            do_row<MODE>(B, L, bi, r, R);
     }
 }
 
@@ -697,8 +770,8 @@ template <int MODE, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
     row_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
                int64_t nrows, const float* __restrict__ tbme, int64_t* __restrict__ row_ptr, int64_t nrp,
-               int32_t* __restrict__ col, float* __restrict__ val, int grab, unsigned long long* __restrict__ queue,
-               int full)
+               int32_t* __restrict__ col, float* __restrict__ val, uint32_t* __restrict__ keys, int grab,
+               unsigned long long* __restrict__ queue, int full)
 {
     __shared__ WaveLds lds[WAVES];
     const int wid = uniform(threadIdx.x >> 6);
@@ -706,7 +779,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t grow = (int64_t)blockIdx.x * WAVES + wid;
         if (grow < nrows)
             run_row<MODE>(bases, nb, basis_row0, grow, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, false, full != 0, lds[wid]);
+                          nullptr, false, full != 0, keys, lds[wid]);
         return;
     }
     for (;;) {
@@ -719,7 +792,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const int64_t g1 = g0 + grab < nrows ? g0 + grab : nrows;
         for (int64_t g = g0; g < g1; g++)
             run_row<MODE>(bases, nb, basis_row0, g, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
-                          nullptr, false, full != 0, lds[wid]);
+                          nullptr, false, full != 0, keys, lds[wid]);
     }
 }
 
@@ -782,19 +855,21 @@ __global__ void __launch_bounds__(256) tile_offsets(const BasisDev* __restrict__
 // index; persistent == 1: a persistent grid takes tiles from the work counter
 // *queue (zero at launch).  use_table == 0 (global table positions do not fit
 // 32 bits): every contribution goes to the accumulator.
-__global__ void __launch_bounds__(64 * kAdjWaves)
+template <int WAVES, int SLOT_BITS>
+__global__ void __launch_bounds__(64 * WAVES)
     adjoint_kernel(const BasisDev* __restrict__ bases, const int32_t* __restrict__ blk_basis,
                    const int32_t* __restrict__ blk_local, int nblocks, const int64_t* __restrict__ tile_off,
                    int rows, int tile_n, const int64_t* __restrict__ row_ptr, int64_t nrp,
-                   const float* __restrict__ gval, double* __restrict__ gacc, int use_table, int persistent,
-                   unsigned long long* __restrict__ queue)
+                   const float* __restrict__ gval, const uint32_t* __restrict__ keys, double* __restrict__ gacc,
+                   int use_table, int persistent, unsigned long long* __restrict__ queue)
 {
-    __shared__ WaveLds lds[kAdjWaves];
-    __shared__ uint32_t hkey[kAdjSlots];
-    __shared__ float hval[kAdjSlots];
+    constexpr int kSlots = 1 << SLOT_BITS;
+    __shared__ WaveLds lds[WAVES];
+    __shared__ uint32_t hkey[kSlots];
+    __shared__ float hval[kSlots];
     __shared__ int next_row;
     __shared__ int t_gb, t_ip0, t_in0, t_tp, t_tn, t_nKn, t_valid;
-    for (int s = threadIdx.x; s < kAdjSlots; s += 64 * kAdjWaves) {
+    for (int s = threadIdx.x; s < kSlots; s += 64 * WAVES) {
         hkey[s] = kAdjEmpty;
         hval[s] = 0.0f;
     }
@@ -848,11 +923,11 @@ __global__ void __launch_bounds__(64 * kAdjWaves)
             const int r = (ip0 + u) * nKn + in0 + v;
             run_row_at<kAdjoint>(B, bi, uniform((int)cst(B.blk_off)[bi] + r), r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
                                  nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval,
-                                 use_table != 0, false, lds[wid]);
+                                 use_table != 0, SLOT_BITS, false, const_cast<uint32_t*>(keys), lds[wid]);
         }
         __syncthreads();
         if (use_table) {
-            for (int s = threadIdx.x; s < kAdjSlots; s += 64 * kAdjWaves) {
+            for (int s = threadIdx.x; s < kSlots; s += 64 * WAVES) {
                 const uint32_t k = hkey[s];
                 if (k != kAdjEmpty) {
                     atomic_add_f64(glbw(gacc) + k, (double)hval[s]);
@@ -1013,8 +1088,8 @@ static unsigned resident_blocks(const void* kernel, int threads, int kind)
 
 template <int MODE, int WAVES>
 static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
-                          const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, int grab,
-                          unsigned long long* queue, int full, hipStream_t s)
+                          const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, uint32_t* keys,
+                          int grab, unsigned long long* queue, int full, hipStream_t s)
 {
     unsigned grid = grid_for(nrows, WAVES);
     if (grab > 0) {
@@ -1025,21 +1100,21 @@ static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_ro
         grid = res < need ? res : need;
     }
     hipLaunchKernelGGL((row_kernel<MODE, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, bases, nb, basis_row0,
-                       nrows, tbme, row_ptr, nrp, col, val, grab, queue, full);
+                       nrows, tbme, row_ptr, nrp, col, val, keys, grab, queue, full);
 }
 
 template <int MODE>
 static hipError_t launch_rows(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                               const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                              const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
+                              uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
     if (t.row_waves == 8)
-        launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, full,
-                               s);
+        launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, keys, t.row_grab, queue,
+                               full, s);
     else
-        launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, t.row_grab, queue, full,
-                               s);
+        launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, keys, t.row_grab, queue,
+                               full, s);
     return hipGetLastError();
 }
 
@@ -1047,8 +1122,8 @@ hipError_t launch_count(const BasisDev* bases, int nb, const int64_t* basis_row0
                         int64_t* row_ptr, int64_t nrp, const int64_t* seg_first, int64_t* scan_tmp,
                         const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
-    hipError_t e = launch_rows<kCount>(bases, nb, basis_row0, nrows, nullptr, row_ptr, nrp, nullptr, nullptr, t,
-                                       queue, full, s);
+    hipError_t e = launch_rows<kCount>(bases, nb, basis_row0, nrows, nullptr, row_ptr, nrp, nullptr, nullptr,
+                                       nullptr, t, queue, full, s);
     if (e != hipSuccess) return e;
     // the first slot of each basis' segment holds 0 before the scan, so the
     // inclusive scan leaves there the number of entries of the bases before it
@@ -1065,32 +1140,41 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
 
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
-                       const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
+                       uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s)
 {
-    return launch_rows<kFill>(bases, nb, basis_row0, nrows, tbme, const_cast<int64_t*>(row_ptr), nrp, col, val, t,
-                              queue, full, s);
+    return launch_rows<kFill>(bases, nb, basis_row0, nrows, tbme, const_cast<int64_t*>(row_ptr), nrp, col, val, keys,
+                              t, queue, full, s);
 }
 
 hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
                       int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
-                      const float* gval, float* gtbme, double* gacc, int64_t ntbme, const ci_tuning& t,
-                      unsigned long long* queue, hipStream_t s)
+                      const float* gval, const uint32_t* keys, float* gtbme, double* gacc, int64_t ntbme,
+                      const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
     if (nrows > 0 && ntiles > 0) {
         const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
-        hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, t.adj_rows,
-                           t.adj_tile_n, tile_off);
+        const int rows = keys ? t.adjk_rows : t.adj_rows, tile_n = keys ? t.adjk_tile_n : t.adj_tile_n;
+        hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, rows, tile_n,
+                           tile_off);
+        const void* kern = keys ? (const void*)adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>
+                                : (const void*)adjoint_kernel<kAdjWaves, kAdjSlotBits>;
+        const int threads = 64 * (keys ? kAdjKeysWaves : kAdjWaves);
         unsigned grid = (unsigned)ntiles;
         if (t.adj_persistent) {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
-            const unsigned res = resident_blocks((const void*)adjoint_kernel, 64 * kAdjWaves, 6);
+            const unsigned res = resident_blocks(kern, threads, keys ? 7 : 6);
             grid = res < grid ? res : grid;
         }
-        hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(64 * kAdjWaves), 0, s, bases, blk_basis, blk_local,
-                           nblocks, tile_off, t.adj_rows, t.adj_tile_n, row_ptr, nrp, gval, gacc, use_table,
-                           t.adj_persistent ? 1 : 0, queue);
+        if (keys)
+            hipLaunchKernelGGL((adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>), dim3(grid), dim3(threads), 0, s,
+                               bases, blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys,
+                               gacc, use_table, t.adj_persistent ? 1 : 0, queue);
+        else
+            hipLaunchKernelGGL((adjoint_kernel<kAdjWaves, kAdjSlotBits>), dim3(grid), dim3(threads), 0, s, bases,
+                               blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys, gacc,
+                               use_table, t.adj_persistent ? 1 : 0, queue);
     }
     if (ntbme > 0) hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
     return hipGetLastError();

@@ -347,7 +347,8 @@ def test_tuning_validation_and_tuner(ci):
     probs = SMALL[:6]
     seeds = [300 + k for k in range(len(probs))]
     b, rp, col, val, tb = run_forward(ci, probs, seeds)
-    for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_tile_n=0), dict(adj_persistent=2)):
+    for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_tile_n=0), dict(adj_persistent=2),
+                dict(adjk_rows=0), dict(adjk_tile_n=4097)):
         with pytest.raises(ci.CIError):
             b.tuning = bad
     rp_t = torch.from_numpy(rp).cuda()
@@ -372,9 +373,11 @@ def test_tuning_validation_and_tuner(ci):
     assert float((g - g_ref).abs().max()) <= GRAD_TOL * float(g_ref.abs().max())
 
 
-def test_batched_64_bases_sampled_rows(ci):
+@pytest.mark.parametrize("stored", [False, True])
+def test_batched_64_bases_sampled_rows(ci, stored):
     # The 64-basis batch at full size, tuned and run as one captured graph of
-    # fill + adjoint (as timed by the benchmark).  Values: sampled rows of every
+    # fill + adjoint (stored: the fill stores the structure words and the
+    # adjoint reads them, as timed by the benchmark).  Values: sampled rows of every
     # basis against the oracle.  Adjoint: the upstream gradient is psi_i psi_j
     # on the sampled rows' entries and zero elsewhere, so the oracle's gradient
     # of those rows is the exact FP64 reference for every basis' table.
@@ -414,20 +417,29 @@ def test_batched_64_bases_sampled_rows(ci):
     col.fill_(-1)
     val.fill_(float("nan"))
     gt.fill_(float("nan"))
+    keys = torch.empty(tot, dtype=torch.int32, device="cuda")
+
+    def step():
+        if stored:
+            ci.ci_hamiltonian_fill_keys(b, tbme, rp_t, col, val, keys)
+            ci.ci_hamiltonian_vjp_keys(b, rp_t, keys, G, gt, work)
+        else:
+            ci.ci_hamiltonian_fill(b, tbme, rp_t, col, val)
+            ci.ci_hamiltonian_vjp(b, rp_t, G, gt, work)
+
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        ci.ci_hamiltonian_fill(b, tbme, rp_t, col, val)
-        ci.ci_hamiltonian_vjp(b, rp_t, G, gt, work)
+        step()
     torch.cuda.current_stream().wait_stream(s)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        ci.ci_hamiltonian_fill(b, tbme, rp_t, col, val)
-        ci.ci_hamiltonian_vjp(b, rp_t, G, gt, work)
+        step()
     for rep in range(2):
         col.fill_(-1)
+        keys.fill_(-1)
         gt.fill_(float("nan"))
-        say("batch graph replay", rep)
+        say("batch graph replay", rep, "stored", stored)
         graph.replay()
         torch.cuda.synchronize()
         g = gt.cpu().numpy().astype(np.float64)

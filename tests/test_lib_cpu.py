@@ -102,6 +102,8 @@ def test_argument_errors_before_any_device_call():
     assert L.ci_hamiltonian_fill(None, None, None, None, None, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_vjp(None, None, None, None, None, 0, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_count(None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_fill_keys(None, None, None, None, None, None, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_vjp_keys(None, None, None, None, None, None, 0, None) == ci.CI_EINVAL
     assert L.ci_vjp_work_bytes(None) == 0 and L.ci_basis_count(None) == 0
 
 
