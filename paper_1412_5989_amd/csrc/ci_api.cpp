@@ -111,9 +111,9 @@ static void dev_release(int device, void* p, size_t bytes)
     bool ok = bytes <= kCacheBytes && hipGetDevice(&cur) == hipSuccess;
     if (ok && cur != device) ok = hipSetDevice(device) == hipSuccess;
     if (ok) ok = hipDeviceSynchronize() == hipSuccess;
-    if (cur >= 0 && cur != device) hipSetDevice(cur);
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
     if (!ok) {
-        hipFree(p);
+        (void)hipFree(p);
         return;
     }
     std::vector<void*> evict;
@@ -139,7 +139,7 @@ static void dev_release(int device, void* p, size_t bytes)
         g_cache.push_back({device, p, bytes});
         g_cache_total += bytes;
     }
-    for (void* q : evict) hipFree(q);
+    for (void* q : evict) (void)hipFree(q);
 }
 
 // Per-thread pinned staging buffer of the host-written tables, the list
@@ -165,7 +165,7 @@ static hipError_t staging_wait()
 static hipError_t staging_fence(hipStream_t s, int device)
 {
     if (!t_fence.ev || t_fence.device != device) {
-        if (t_fence.ev) hipEventDestroy(t_fence.ev);
+        if (t_fence.ev) (void)hipEventDestroy(t_fence.ev);
         t_fence.ev = nullptr;
         hipError_t e = hipEventCreateWithFlags(&t_fence.ev, hipEventDisableTiming);
         if (e != hipSuccess) return e;
@@ -186,7 +186,7 @@ static char* pinned_staging(size_t bytes)
     static thread_local Buf b;
     if (staging_wait() != hipSuccess) return nullptr;
     if (b.n < bytes) {
-        if (b.p) hipHostFree(b.p);
+        if (b.p) (void)hipHostFree(b.p);
         b.p = nullptr;
         b.n = 0;
         const size_t cap = std::max(bytes, (size_t)1 << 20);
@@ -206,7 +206,7 @@ static int64_t* pinned_counts(size_t n)
     };
     static thread_local Buf b;
     if (b.n < n) {
-        if (b.p) hipHostFree(b.p);
+        if (b.p) (void)hipHostFree(b.p);
         b.p = nullptr;
         b.n = 0;
         const size_t cap = std::max<size_t>(n, 4096);
@@ -247,7 +247,7 @@ struct ci_basis {
     {
         dev_release(device, arena, arena_bytes);
         dev_release(device, lists, list_bytes);
-        for (void* m : h3_mem) hipFree(m);
+        for (void* m : h3_mem) (void)hipFree(m);
     }
 };
 
@@ -331,8 +331,6 @@ int time_ms(F f, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* m
 
 }  // namespace
 
-extern "C" {
-
 // Process-wide cache of tuned launch shapes, keyed by the problem list.
 namespace {
 std::mutex g_tune_mu;
@@ -360,6 +358,8 @@ void remember_tuning(const std::vector<ci_problem>& p, const ci_tuning& t)
     g_tune[tune_key(p)] = t;
 }
 }  // namespace
+
+extern "C" {
 
 const char* ci_last_error(void) { return g_err.c_str(); }
 
@@ -639,7 +639,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     for (size_t u = 0; u < ub.size(); u++) {
         const int rc = plan_tbme_index(*ub[u], err);
         if (rc != CI_OK) {
-            hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(s);
             return fail(rc, "problem " + std::to_string(u) + ": " + err);
         }
         write_pair64(*ub[u], (uint64_t*)(mirror + uo[u].pair));
@@ -865,7 +865,7 @@ static int h3_build_index(ci_basis* b, hipStream_t s)
     std::vector<const void*> idx(6 * n, nullptr);
     std::vector<void*> mem;
     auto cleanup = [&]() {
-        for (void* m : mem) hipFree(m);
+        for (void* m : mem) (void)hipFree(m);
     };
     for (size_t p = 0; p < n; p++) {
         const HostBasis& hb = *b->host[p];
@@ -1080,7 +1080,7 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return hip_fail(e, "hipEventCreate");
     }
     const ci_tuning start = b->tune;
@@ -1128,8 +1128,8 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                 have = true;
             }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != CI_OK) {
         b->tune = start;
         return rc;

@@ -53,7 +53,7 @@ hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps,
     if (e != hipSuccess) return e;
     e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return e;
     }
     const int64_t n = (int64_t)(bytes / sizeof(u32x4));
@@ -81,8 +81,8 @@ hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps,
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms_popc, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     *store_bps = (double)reps * (double)n * sizeof(u32x4) / (ms_store * 1e-3);
     *steps_per_s = (double)pgrid * 256 * iters * kChains / (ms_popc * 1e-3);

@@ -573,7 +573,7 @@ hipError_t threebody_upload(ThreeBodyHost& h)
 
 void threebody_release(ThreeBodyHost& h)
 {
-    if (h.arena) hipFree(h.arena);
+    if (h.arena) (void)hipFree(h.arena);
     h.arena = nullptr;
 }
 
