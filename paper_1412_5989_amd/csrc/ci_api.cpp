@@ -4,10 +4,12 @@
 
 #include <algorithm>
 #include <cstring>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -177,6 +179,50 @@ static hipError_t staging_fence(hipStream_t s, int device)
     return hipSuccess;
 }
 
+// A second stream per device (default priority) for host-to-device copies
+// that overlap the kernels of the caller's stream, created on first use and
+// kept until the process ends; the caller's stream waits for such a copy
+// through a per-thread event before it uses the data.
+static hipError_t copy_stream(int device, hipStream_t* out)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = streams.find(device);
+    if (it != streams.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    hipStream_t st = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    streams[device] = st;
+    *out = st;
+    return hipSuccess;
+}
+
+static thread_local StagingFence t_copy_done;
+
+// Copies bytes host -> device on the device's copy stream and makes stream s
+// wait for the copy.
+static hipError_t copy_beside(void* dst, const void* src, size_t bytes, hipStream_t s, int device)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = copy_stream(device, &cs);
+    if (e != hipSuccess) return e;
+    if (!t_copy_done.ev || t_copy_done.device != device) {
+        if (t_copy_done.ev) (void)hipEventDestroy(t_copy_done.ev);
+        t_copy_done.ev = nullptr;
+        e = hipEventCreateWithFlags(&t_copy_done.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        t_copy_done.device = device;
+    }
+    e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, cs);
+    if (e == hipSuccess) e = hipEventRecord(t_copy_done.ev, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, t_copy_done.ev, 0);
+    return e;
+}
+
 static char* pinned_staging(size_t bytes)
 {
     struct Buf {
@@ -308,6 +354,62 @@ bool same_species(const HostBasis& A, int sa, const HostBasis& B, int sb)
            a.key_m2 == b.key_m2 && a.sd == b.sd;
 }
 
+// The two-body pair indexes of the unique problems of a build, on a helper
+// thread (they need only the orbits, and the calling thread meanwhile
+// enumerates the determinants and starts the device); once the calling
+// thread names where the device form goes (set_targets), the helper writes it
+// there too.  The destructor joins, so every return path of the build waits
+// for the thread.
+class PairIndexer {
+public:
+    explicit PairIndexer(const std::vector<std::shared_ptr<HostBasis>>& ub)
+        : ub_(ub), rc_(ub.size(), CI_OK), err_(ub.size())
+    {
+        std::future<std::vector<uint64_t*>> dst = dst_.get_future();
+        th_ = std::thread([this](std::future<std::vector<uint64_t*>> d) {
+            for (size_t u = 0; u < ub_.size(); u++) rc_[u] = plan_tbme_index(*ub_[u], err_[u]);
+            const std::vector<uint64_t*> out = d.get();  // empty: the build gave up
+            for (size_t u = 0; u < out.size() && u < ub_.size(); u++)
+                if (rc_[u] == CI_OK) write_pair64(*ub_[u], out[u]);
+        }, std::move(dst));
+    }
+    ~PairIndexer()
+    {
+        release({});
+        if (th_.joinable()) th_.join();
+    }
+    // Where the device form of each problem's index goes (host memory that
+    // stays valid until wait() returns).
+    void set_targets(const std::vector<uint64_t*>& out) { release(out); }
+    // Joins; CI_OK, or the first failure with its problem's position and message.
+    int wait(size_t* bad, std::string& err)
+    {
+        release({});
+        if (th_.joinable()) th_.join();
+        for (size_t u = 0; u < ub_.size(); u++)
+            if (rc_[u] != CI_OK) {
+                *bad = u;
+                err = err_[u];
+                return rc_[u];
+            }
+        return CI_OK;
+    }
+
+private:
+    void release(const std::vector<uint64_t*>& out)
+    {
+        if (sent_) return;
+        sent_ = true;
+        dst_.set_value(out);
+    }
+    std::vector<std::shared_ptr<HostBasis>> ub_;
+    std::vector<int> rc_;
+    std::vector<std::string> err_;
+    std::promise<std::vector<uint64_t*>> dst_;
+    bool sent_ = false;
+    std::thread th_;
+};
+
 }  // namespace
 
 namespace {
@@ -417,11 +519,16 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             continue;
         }
         auto hb = std::make_shared<HostBasis>();
-        rc = plan_structure(probs[b], *hb, err);  // the pair index follows, overlapped with the device
+        rc = plan_orbits(probs[b], *hb, err);
         if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
         which[b] = (int)ub.size();
         uniq[key_of(probs[b])] = which[b];
         ub.push_back(hb);
+    }
+    PairIndexer pairs(ub);
+    for (size_t u = 0; u < ub.size(); u++) {
+        const int rc = plan_determinants(*ub[u], err);
+        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(u) + ": " + err);
     }
 
     // Species tables with equal content (protons and neutrons of an N = Z
@@ -596,6 +703,11 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     put(o_row0, row0.data(), row0.size() * 8);
     put(o_first, first.data(), first.size() * 8);
     put(o_last, last.data(), last.size() * 8);
+    {
+        std::vector<uint64_t*> out(ub.size());
+        for (size_t u = 0; u < ub.size(); u++) out[u] = (uint64_t*)(mirror + uo[u].pair);
+        pairs.set_targets(out);
+    }
     e = hipMemcpyAsync(h->arena, mirror, pair_start, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index tables)");
 
@@ -635,17 +747,6 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
                 (e = launch_copy_i64(a.l12_ptr + a.nsd, tot + 2 * sidx + 1, s)) != hipSuccess)
                 return hip_fail(e, "partner totals");
         }
-    // two-body pair index on the host while the partner kernels run
-    for (size_t u = 0; u < ub.size(); u++) {
-        const int rc = plan_tbme_index(*ub[u], err);
-        if (rc != CI_OK) {
-            (void)hipStreamSynchronize(s);
-            return fail(rc, "problem " + std::to_string(u) + ": " + err);
-        }
-        write_pair64(*ub[u], (uint64_t*)(mirror + uo[u].pair));
-    }
-    e = hipMemcpyAsync(dev + pair_start, mirror + pair_start, host_bytes - pair_start, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pair index)");
     int64_t* tot_pinned = (int64_t*)(mirror + tot_off);
     for (size_t u = 0; u < ub.size(); u++) {
         e = hipMemcpyAsync(tot_pinned + 4 * u, D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -684,6 +785,20 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
             if ((e = launch_partner_fill(a, totals[4 * u + 2 * sidx], totals[4 * u + 2 * sidx + 1], s)) != hipSuccess)
                 return hip_fail(e, "partner fill");
         }
+    // two-body pair indexes (helper thread) while the partner lists fill
+    {
+        size_t bad = 0;
+        const int rc = pairs.wait(&bad, err);
+        if (rc != CI_OK) {
+            (void)hipStreamSynchronize(s);
+            return fail(rc, "problem " + std::to_string(bad) + ": " + err);
+        }
+    }
+    // its upload (1.4 MB for 6Li Nmax = 6, tens of microseconds over PCIe)
+    // overlaps the partner-list kernels; the stream waits for it before the
+    // row kernels that read it
+    e = copy_beside(dev + pair_start, mirror + pair_start, host_bytes - pair_start, s, h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pair index)");
 
     // ---- per-problem descriptors
     std::vector<BasisDev> bd(n_probs);

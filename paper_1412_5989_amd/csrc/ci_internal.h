@@ -139,9 +139,12 @@ int validate_problem(const ci_problem& p, std::string& err);
 // Host tables: orbits, species determinants, keys, blocks, table sectors and
 // pair index (the partner lists are built on the device).
 int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err);
-// The same in two parts: orbits, determinants, keys and blocks; then the
-// two-body sectors and pair index (needs only the orbits).
-int plan_structure(const ci_problem& p, HostBasis& hb, std::string& err);
+// The same in parts: the orbits (validates the problem first); the
+// determinants, keys and blocks (needs the orbits); the two-body sectors and
+// pair index (needs only the orbits, so it can run on another thread while
+// the determinants are enumerated: the two parts write disjoint members).
+int plan_orbits(const ci_problem& p, HostBasis& hb, std::string& err);
+int plan_determinants(HostBasis& hb, std::string& err);
 int plan_tbme_index(HostBasis& hb, std::string& err);
 // Two-body keys (a, b, c, d) in table order.
 void tbme_keys(const HostBasis& hb, std::vector<int32_t>& abcd);

@@ -83,8 +83,8 @@ bool block_ok(const HostBasis& hb, int nqp, int m2p, int nqn, int m2n)
     return m2p + m2n == hb.prob.two_m;
 }
 
-// Orbits, species determinants, keys, blocks.
-int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
+// Oscillator orbits and the lowest filling.
+int make_orbits(const ci_problem& p, HostBasis& hb, std::string& err)
 {
     hb.prob = p;
     hb.S = std::max(top_shell(p.Z), top_shell(p.N)) + p.nmax;
@@ -109,6 +109,13 @@ int make_structure(const ci_problem& p, HostBasis& hb, std::string& err)
     hb.N0p = lowest_quanta(p.Z);
     hb.N0n = lowest_quanta(p.N);
     hb.N0 = hb.N0p + hb.N0n;
+    return CI_OK;
+}
+
+// Species determinants, keys, blocks (the orbits are set).
+int make_determinants(HostBasis& hb, std::string& err)
+{
+    const ci_problem& p = hb.prob;
     const int top = hb.N0 + p.nmax;
 
     // keys (Nq, 2M) of each species on a dense grid
@@ -245,9 +252,10 @@ int make_tbme_index(HostBasis& hb, std::string& err)
         auto slot = [&](int a, int b) {
             return (hb.orb_m2[a] + hb.orb_m2[b] + 2 * maxm) * 2 + ((hb.orb_n[a] + hb.orb_n[b]) & 1);
         };
+        // orbits ascend in N, so the valid partners b of a are a prefix of the
+        // loop and the search stops at the first invalid one
         for (int a = 0; a < n; a++)
-            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++)
-                if (valid(a, b)) cnt[slot(a, b)]++;
+            for (int b = (cls == 1 ? 0 : a + 1); b < n && valid(a, b); b++) cnt[slot(a, b)]++;
         for (int t = 0; t < 2 * nm; t++) {
             if (!cnt[t]) continue;
             const int sec = (int)hb.sec_n.size();
@@ -262,11 +270,10 @@ int make_tbme_index(HostBasis& hb, std::string& err)
             cnt[t] = 0;  // reused as the running position
         }
         for (int a = 0; a < n; a++)
-            for (int b = (cls == 1 ? 0 : a + 1); b < n; b++)
-                if (valid(a, b)) {
-                    const int t = slot(a, b);
-                    hb.pair[(size_t)cls * n * n + (size_t)a * n + b] = ((uint32_t)sid[t] << 16) | (uint32_t)cnt[t]++;
-                }
+            for (int b = (cls == 1 ? 0 : a + 1); b < n && valid(a, b); b++) {
+                const int t = slot(a, b);
+                hb.pair[(size_t)cls * n * n + (size_t)a * n + b] = ((uint32_t)sid[t] << 16) | (uint32_t)cnt[t]++;
+            }
     }
     hb.n_tbme = total;
     if (total >= ((int64_t)1 << 31)) {
@@ -311,18 +318,21 @@ int validate_problem(const ci_problem& p, std::string& err)
     return CI_OK;
 }
 
-int plan_structure(const ci_problem& p, HostBasis& hb, std::string& err)
+int plan_orbits(const ci_problem& p, HostBasis& hb, std::string& err)
 {
     int rc = validate_problem(p, err);
     if (rc != CI_OK) return rc;
-    return make_structure(p, hb, err);
+    return make_orbits(p, hb, err);
 }
+
+int plan_determinants(HostBasis& hb, std::string& err) { return make_determinants(hb, err); }
 
 int plan_tbme_index(HostBasis& hb, std::string& err) { return make_tbme_index(hb, err); }
 
 int plan_basis(const ci_problem& p, HostBasis& hb, std::string& err)
 {
-    int rc = plan_structure(p, hb, err);
+    int rc = plan_orbits(p, hb, err);
+    if (rc == CI_OK) rc = make_determinants(hb, err);
     if (rc != CI_OK) return rc;
     return plan_tbme_index(hb, err);
 }

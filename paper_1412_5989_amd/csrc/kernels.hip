@@ -439,9 +439,9 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
 
 // Occupied orbits of row (gP, gN) into L.occ, for the multi-term entries:
 // lane j < 2W holds determinant word j (protons, then neutrons), a wave scan
-// gives each word's first slot in occ, and the shells of the occupied orbits
-// give the single-particle sum.
-__device__ void row_occ(const BasisDev& B, WaveLds& L, RowView& R, int gP, int gN)
+// gives each word's first slot in occ, and (spe: for the fill's values) the
+// shells of the occupied orbits give the single-particle sum.
+__device__ void row_occ(const BasisDev& B, WaveLds& L, RowView& R, int gP, int gN, bool spe)
 {
     const int lane = threadIdx.x & 63;
     const SpeciesDev& SP = B.sp[0];
@@ -455,6 +455,7 @@ __device__ void row_occ(const BasisDev& B, WaveLds& L, RowView& R, int gP, int g
     const int obase = (lane < W ? lane : lane - W) * 64;
     for (uint64_t x = word; x; x &= x - 1) L.occ[t++] = (uint8_t)(obase + __ffsll((long long)x) - 1);
     wave_sync();
+    if (!spe) return;
     const int A = R.Z + R.NN;
     int shells = 0;
     for (int j0 = 0; j0 < A; j0 += 64) {
@@ -488,7 +489,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
     const gptr<int32_t> sN12 = glb(SN.seg12 + (int64_t)gN * (nkn + 1));
     const int self12 = uniform(cst(SN.self12)[gN]);
 
-    if (MODE != kCount) row_occ(B, L, R, gP, gN);
+    if (MODE != kCount) row_occ(B, L, R, gP, gN, MODE == kFill);
 
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
@@ -655,16 +656,24 @@ __device__ void do_row_keys(const BasisDev& B, WaveLds& L, int bi, int r, RowVie
     const cptr<int32_t> pkoff = cst(B.sp[0].key_off), nkoff = cst(B.sp[1].key_off);
     const int nKn = nkoff[kn + 1] - nkoff[kn];
     const int ip = uniform(r / nKn), in = uniform(r - ip * nKn);
-    row_occ(B, L, R, uniform(pkoff[kp] + ip), uniform(nkoff[kn] + in));
     const int64_t n = (end < R.cap ? end : R.cap) - R.pos0;
+    // software pipeline: the loads of the next 64 entries go out before the
+    // current ones are accumulated (the first ones before the occupied orbits)
+    uint32_t kn_ = 0;
+    float gn_ = 0.0f;
+    if (lane < n) {
+        kn_ = glb(R.keys)[R.pos0 + lane];
+        gn_ = glb(R.gval)[R.pos0 + lane];
+    }
+    row_occ(B, L, R, uniform(pkoff[kp] + ip), uniform(nkoff[kn] + in), false);
     int qn = 0;
     for (int64_t e0 = 0; e0 < n; e0 += 64) {
         const int64_t e = e0 + lane;
-        uint32_t k = 0;
-        float g = 0.0f;
-        if (e < n) {
-            k = glb(R.keys)[R.pos0 + e];
-            g = glb(R.gval)[R.pos0 + e];
+        const uint32_t k = kn_;
+        const float g = gn_;
+        if (e + 64 < n) {
+            kn_ = glb(R.keys)[R.pos0 + e + 64];
+            gn_ = glb(R.gval)[R.pos0 + e + 64];
         }
         const bool special = e < n && (k & kKeySpecial);
         if (e < n && !special && (k & kKeyPos) != kKeyNone) adj_add(R, (int)(k & kKeyPos), (k & kKeyNeg) ? -g : g);
