@@ -366,12 +366,15 @@ public:
         : ub_(ub), rc_(ub.size(), CI_OK), err_(ub.size())
     {
         std::future<std::vector<uint64_t*>> dst = dst_.get_future();
-        th_ = std::thread([this](std::future<std::vector<uint64_t*>> d) {
-            for (size_t u = 0; u < ub_.size(); u++) rc_[u] = plan_tbme_index(*ub_[u], err_[u]);
-            const std::vector<uint64_t*> out = d.get();  // empty: the build gave up
-            for (size_t u = 0; u < out.size() && u < ub_.size(); u++)
-                if (rc_[u] == CI_OK) write_pair64(*ub_[u], out[u]);
-        }, std::move(dst));
+        try {
+            th_ = std::thread([this](std::future<std::vector<uint64_t*>> d) {
+                index_all();
+                write_all(d.get());  // empty: the build gave up
+            }, std::move(dst));
+        } catch (...) {
+            inline_ = true;  // no thread to be had: the same work on the calling thread
+            index_all();
+        }
     }
     ~PairIndexer()
     {
@@ -396,17 +399,30 @@ public:
     }
 
 private:
+    void index_all()
+    {
+        for (size_t u = 0; u < ub_.size(); u++) rc_[u] = plan_tbme_index(*ub_[u], err_[u]);
+    }
+    void write_all(const std::vector<uint64_t*>& out)
+    {
+        for (size_t u = 0; u < out.size() && u < ub_.size(); u++)
+            if (rc_[u] == CI_OK) write_pair64(*ub_[u], out[u]);
+    }
     void release(const std::vector<uint64_t*>& out)
     {
         if (sent_) return;
         sent_ = true;
-        dst_.set_value(out);
+        if (inline_)
+            write_all(out);
+        else
+            dst_.set_value(out);
     }
     std::vector<std::shared_ptr<HostBasis>> ub_;
     std::vector<int> rc_;
     std::vector<std::string> err_;
     std::promise<std::vector<uint64_t*>> dst_;
     bool sent_ = false;
+    bool inline_ = false;
     std::thread th_;
 };
 
