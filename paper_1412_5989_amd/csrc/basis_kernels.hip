@@ -97,8 +97,12 @@ __device__ uint64_t partner_record(const uint64_t* x, const uint64_t* y, int W, 
 // against all of them).  The count pass writes the number of partners of each
 // x in each key; a per-x scan turns those into segment offsets; the fill pass
 // writes each key's records at its offset.
-constexpr int kGroups = 8;
-constexpr int kXB = 4;
+// Sizes from a sweep of the 6Li Nmax = 6 build (determinants per wavefront x
+// key groups, 1..16 x 1..16): 2 x 4 gave the shortest step; larger blocks hold
+// their determinants in scalar registers that spill, and more groups only add
+// wavefronts that scan few candidates each.
+constexpr int kGroups = 4;
+constexpr int kXB = 2;
 
 // keys [k0, k1) of group g: those whose first determinant lies in the g-th slice
 __device__ __forceinline__ void key_group(const __attribute__((address_space(4))) int32_t* key_off, int nk,
