@@ -114,7 +114,7 @@ typedef struct ci_basis ci_basis; /* opaque */
  * determinants times tp = max(1, adj_rows / tn) proton determinants -- whose
  * contributions are summed in one shared-memory table before they reach the
  * FP64 accumulators; the adjoint from stored words (ci_hamiltonian_vjp_keys)
- * has its own tile fields, adjk_rows and adjk_tile_n (default 64 and 8),
+ * has its own tile fields, adjk_rows and adjk_tile_n (default 96 and 8),
  * which ci_hamiltonian_tune leaves as they are. */
 typedef struct {
     int32_t row_waves;      /* wavefronts per workgroup of count and fill: 4 or 8 */

@@ -461,7 +461,7 @@ std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 64, 8}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
