@@ -80,10 +80,11 @@ typedef void* ci_stream; /* hipStream_t */
 /* One problem: Z protons, N neutrons, Nmax excitation quanta above the lowest
  * filling, total 2M (two_m + Z + N must be even), parity +1 / -1, hw in MeV.
  * kinetic = 0: the one-body term is the oscillator energy (N + 3/2) hw of each
- * occupied orbit (diagonal); kinetic = 1: plus the off-diagonal part of the
- * oscillator kinetic energy, (hw/2) sqrt((n+1)(n+l+3/2)) between radial
- * quantum numbers n and n + 1 of the same (l, j, m) (one-nucleon
- * differences only; the paper's one-body kinetic term, Sec. 2). */
+ * occupied orbit (diagonal); kinetic = 1: the one-body term is the oscillator
+ * kinetic energy T (the paper's kinetic term, Sec. 2): on the diagonal
+ * (hw/2)(2n + l + 3/2) per occupied orbit, and (hw/2) sqrt((n+1)(n+l+3/2))
+ * between radial quantum numbers n and n + 1 of the same (l, j, m)
+ * (one-nucleon differences). */
 typedef struct {
     int32_t Z, N, nmax, two_m, parity;
     int32_t kinetic;

@@ -99,8 +99,11 @@ class BruteBasis:
         self.index = {s: i for i, s in enumerate(self.states)}
         self.dim = len(self.states)
 
-    def spe(self, a: int) -> float:
-        return (self.orb[a % self.nsps][0] + 1.5) * self.hw
+    def spe(self, a: int, kinetic: bool = False) -> float:
+        """Diagonal one-body energy of orbit a: the oscillator energy (N + 3/2) hw,
+        or with the kinetic term the diagonal of T, (hw/2)(2n + l + 3/2)."""
+        N, n, l = self.orb[a % self.nsps][:3]
+        return 0.5 * (2 * n + l + 1.5) * self.hw if kinetic else (N + 1.5) * self.hw
 
     def state_words(self, W: int) -> np.ndarray:
         """[D, 2W] uint64 words (proton then neutron), for comparison."""
@@ -145,7 +148,8 @@ def hamiltonian(basis: BruteBasis, keys: np.ndarray, values: np.ndarray, kinetic
 
     `keys[t] = (a, b, c, d)` with a<b, c<d is the two-body table as a list of
     canonical elements V_{ab,cd} = V_{cd,ab}; anything not listed is zero.
-    kinetic: add sum_{a != b} t_ab a+_a a_b (kinetic_offdiag)."""
+    kinetic: the one-body term is the oscillator kinetic energy T, its
+    diagonal (spe) plus sum_{a != b} t_ab a+_a a_b (kinetic_offdiag)."""
     D = basis.dim
     H = np.zeros((D, D))
     if kinetic:
@@ -170,7 +174,7 @@ def hamiltonian(basis: BruteBasis, keys: np.ndarray, values: np.ndarray, kinetic
         if (a, b) != (c, d):
             by_ket.setdefault((a, b), []).append((c, d, v))
     for j, phi in enumerate(basis.states):
-        H[j, j] += sum(basis.spe(a) for a in phi)
+        H[j, j] += sum(basis.spe(a, kinetic) for a in phi)
         for c, d in itertools.combinations(phi, 2):  # c < d, both occupied
             for a, b, v in by_ket.get((c, d), ()):
                 x, s1 = _annihilate(phi, c)

@@ -40,7 +40,7 @@ typedef struct {
 typedef struct {
     /* problem */
     int Z, NN, nmax, two_m, parity;
-    int kinetic; /* 1: off-diagonal harmonic-oscillator kinetic elements in the one-body term */
+    int kinetic; /* 1: the one-body term is the oscillator kinetic energy T (diagonal and off-diagonal) */
     double hw;
     /* orbits */
     int S, nsps, W;
@@ -481,10 +481,11 @@ static int count_below(const int* L, int n, int v)
  * output (g != NULL) it instead adds w * d<H_ij>/dV_k into g[k] for every
  * two-body term, and returns 0. */
 /* Off-diagonal one-body element t_ab between combined orbits a != b of one
- * species: the harmonic-oscillator kinetic energy connects radial quantum
- * numbers n and n + 1 of the same (l, j, m), with <n+1 l|T|n l> =
- * (hw/2) sqrt((n+1)(n+l+3/2)) (radial functions positive near the origin);
- * everything else is 0. */
+ * species: the oscillator kinetic energy T = -(hw/2) nabla^2 (lengths in
+ * oscillator units) connects radial quantum numbers n and n + 1 of the same
+ * (l, j, m), with <n+1 l|T|n l> = (hw/2) sqrt((n+1)(n+l+3/2)) (radial
+ * functions positive near the origin); everything else is 0.  Its diagonal
+ * (hw/2)(2n + l + 3/2) is in spe. */
 static double onebody_offdiag(const orc_ctx* c, int a, int b)
 {
     if (!c->kinetic || a == b || (a < c->nsps) != (b < c->nsps)) return 0.0;
@@ -677,7 +678,9 @@ void* orc_new(int Z, int N, int nmax, int two_m, int parity, double hw, int kine
     c->orb = (orc_orbit*)malloc((size_t)c->nsps * sizeof(orc_orbit));
     make_orbits(c->S, c->orb);
     c->spe = (double*)malloc((size_t)2 * c->nsps * sizeof(double));
-    for (int a = 0; a < 2 * c->nsps; a++) c->spe[a] = (corb(c, a)->N + 1.5) * hw;
+    /* diagonal one-body energy: (N + 3/2) hw (oscillator energy), or with the
+     * kinetic term <n l|T|n l> = (hw/2)(2n + l + 3/2) = (hw/2)(N + 3/2) */
+    for (int a = 0; a < 2 * c->nsps; a++) c->spe[a] = (corb(c, a)->N + 1.5) * hw * (kinetic ? 0.5 : 1.0);
     c->N0p = n0(Z);
     c->N0n = n0(N);
     c->N0 = c->N0p + c->N0n;

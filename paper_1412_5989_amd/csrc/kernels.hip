@@ -462,7 +462,9 @@ __device__ void row_occ(const BasisDev& B, WaveLds& L, RowView& R, int gP, int g
         const int j = j0 + lane;
         shells += lane63(wave_incl_scan(j < A ? glb(B.orb_n)[L.occ[j]] : 0));
     }
-    R.spe_sum = ((double)shells + 1.5 * A) * B.hw;
+    // oscillator energies (N + 3/2) hw; with the kinetic term the diagonal of
+    // T, (hw/2)(N + 3/2)
+    R.spe_sum = ((double)shells + 1.5 * A) * B.hw * (B.kinetic ? 0.5 : 1.0);
 }
 
 // One row: count (returns the number of entries), fill or adjoint.

@@ -203,7 +203,7 @@ __device__ double entry_value(const BasisDev& B, const float* tb, const V3Param&
     if (d == 0) {
         for (int a = 0; a < A; a++) {
             const int oa = occ[a];
-            v += (B.orb_n[oa < n ? oa : oa - n] + 1.5) * B.hw;
+            v += (B.orb_n[oa < n ? oa : oa - n] + 1.5) * B.hw * (B.kinetic ? 0.5 : 1.0);
             for (int b = a + 1; b < A; b++) {
                 v += v2_any(B, tb, oa, occ[b], oa, occ[b]);
                 if (v3.kind)

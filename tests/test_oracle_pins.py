@@ -8,6 +8,8 @@ symmetry, conservation laws, and exact linearity of the two-body dependence.
 import itertools
 
 import numpy as np
+from scipy.integrate import quad
+from scipy.special import genlaguerre
 import pytest
 
 import seeded_inputs as si
@@ -324,7 +326,7 @@ def test_spectrum_invariant_under_orbit_relabeling():
     b.index = {s: i for i, s in enumerate(b.states)}
     spe = b.spe
     inv = {int(perm[a]): a for a in range(n)}
-    b.spe = lambda a: spe(inv[a] if a < n else a)
+    b.spe = lambda a, kinetic=False: spe(inv[a] if a < n else a, kinetic)
     H2 = brute.hamiltonian(b, np.array(keys2), np.array(vals2))
     np.testing.assert_allclose(np.linalg.eigvalsh(H2), ev, rtol=0, atol=1e-10)
 
@@ -509,35 +511,105 @@ def test_kinetic_matrix_equals_operator_application(p):
                     x &= x - 1
                     q += orbs[w * 64 + b][0]
         nq.add(q)
+    # the diagonal one-body part is halved: (hw/2)(N + 3/2) per orbit
+    H0 = o0.dense()
+    off = H - H0
+    np.fill_diagonal(off, 0.0)
     if len(nq) > 1:
-        assert np.abs(H - o0.dense()).max() > 1.0
+        assert np.abs(off).max() > 1.0
     else:
-        assert np.abs(H - o0.dense()).max() == 0.0
+        assert np.abs(off).max() == 0.0
+    o00 = Oracle(Problem(*p))
+    o00.set_tbme(np.zeros(o00.n_tbme))
+    assert np.abs(np.diag(H) - np.diag(H0) + 0.5 * np.diag(o00.dense())).max() <= 1e-9
 
 
-def test_kinetic_single_nucleon_closed_form():
-    # one proton: the matrix is the one-body operator itself on the allowed
-    # orbits, (N + 3/2) hw on the diagonal and (hw/2) sqrt((n+1)(n+l+3/2))
-    # between radial quantum numbers n, n+1 of the same (l, j, m)
-    p = (1, 0, 4, 1, 1)
+def _oscillator_radial(n, l):
+    """Oscillator radial function R_nl(r) (lengths in oscillator units) and
+    its derivative, normalized by quadrature and positive near the origin:
+    r^l exp(-r^2/2) L_n^(l+1/2)(r^2) with scipy's generalized Laguerre
+    polynomial."""
+    L = genlaguerre(n, l + 0.5)
+    dL = L.deriv()
+
+    def f(r):
+        return r ** l * np.exp(-0.5 * r * r) * L(r * r)
+
+    def df(r):
+        lead = l * r ** (l - 1) if l > 0 else 0.0
+        return np.exp(-0.5 * r * r) * ((lead - r ** (l + 1)) * L(r * r) + 2.0 * r ** (l + 1) * dL(r * r))
+
+    norm = np.sqrt(quad(lambda r: (f(r) * r) ** 2, 0.0, np.inf, limit=200)[0])
+    return (lambda r: f(r) / norm), (lambda r: df(r) / norm)
+
+
+def _kinetic_quadrature(n1, n2, l, hw):
+    """<n1 l|T|n2 l> for T = -(hw/2) nabla^2 in oscillator units, as the
+    quadratic form (hw/2) int (R1' R2' + l(l+1) R1 R2 / r^2) r^2 dr."""
+    f1, d1 = _oscillator_radial(n1, l)
+    f2, d2 = _oscillator_radial(n2, l)
+    v = quad(lambda r: d1(r) * d2(r) * r * r + l * (l + 1) * f1(r) * f2(r), 0.0, np.inf, limit=200)[0]
+    return 0.5 * hw * v
+
+
+@pytest.mark.parametrize("parity", [1, -1])
+def test_kinetic_single_nucleon_equals_quadrature(parity):
+    # One proton in shells 0..7 (every (n, l) the workloads reach: 6Li Nmax=6
+    # and the batch go up to shell 7): the matrix is the one-body operator
+    # itself, here the kinetic energy T of the oscillator orbits.  Every
+    # element, diagonal and off-diagonal, against T computed by quadrature
+    # of the radial functions (no closed form used): this fails for a
+    # missing hw/2, for n + l + 1/2 in place of n + l + 3/2, or for a
+    # diagonal of (N + 3/2) hw.
+    p = (1, 0, 7, 1, parity)
     o = Oracle(Problem(*p, kinetic=1))
     o.set_tbme(np.zeros(o.n_tbme))
     H = o.dense()
     orbs = brute.orbits(o.shell_max)
-    states = [a for a, (N, n, l, j2, m2) in enumerate(orbs) if m2 == 1 and N % 2 == 0 and N <= 4]
+    want_par = 0 if parity == 1 else 1
+    states = [a for a, (N, n, l, j2, m2) in enumerate(orbs) if m2 == 1 and N % 2 == want_par and N <= 7]
     assert o.dim == len(states)
+    assert max(orbs[a][0] for a in states) >= 6
     T = np.zeros((o.dim, o.dim))
+    cache = {}
     for x, a in enumerate(states):
         for y, b in enumerate(states):
             Na, na, la, ja, ma = orbs[a]
             Nb, nb, lb, jb, mb = orbs[b]
-            if a == b:
-                T[x, y] = (Na + 1.5) * 15.0
-            elif (la, ja, ma) == (lb, jb, mb) and abs(na - nb) == 1:
-                n = min(na, nb)
-                T[x, y] = 7.5 * np.sqrt((n + 1) * (n + la + 1.5))
+            if (la, ja, ma) != (lb, jb, mb):
+                continue  # T is a scalar: no element between different (l, j, m)
+            key = (min(na, nb), max(na, nb), la)
+            if key not in cache:
+                cache[key] = _kinetic_quadrature(key[0], key[1], la, 15.0)
+            T[x, y] = cache[key]
     # the basis order of one proton is the orbit order (colex of one bit)
-    assert np.abs(H - T).max() <= 1e-12
+    assert np.abs(H - T).max() <= 1e-9 * np.abs(T).max()
+    # the quadrature itself sees no element two radial quanta apart
+    assert abs(_kinetic_quadrature(0, 2, 1, 15.0)) < 1e-9
+
+
+def test_kinetic_term_is_oscillator_energy_minus_potential():
+    # the same one-nucleon matrix, rebuilt from h_HO = T + r^2/2 hw: T equals
+    # the oscillator energy on the diagonal minus (hw/2) <r^2>, with <r^2>
+    # by quadrature (a second route to T, through the potential)
+    p = (1, 0, 6, 1, 1)
+    o = Oracle(Problem(*p, kinetic=1))
+    o.set_tbme(np.zeros(o.n_tbme))
+    H = o.dense()
+    orbs = brute.orbits(o.shell_max)
+    states = [a for a, (N, n, l, j2, m2) in enumerate(orbs) if m2 == 1 and N % 2 == 0 and N <= 6]
+    for x, a in enumerate(states):
+        for y, b in enumerate(states):
+            Na, na, la, ja, ma = orbs[a]
+            Nb, nb, lb, jb, mb = orbs[b]
+            if (la, ja, ma) != (lb, jb, mb):
+                assert H[x, y] == 0.0
+                continue
+            f1, _ = _oscillator_radial(na, la)
+            f2, _ = _oscillator_radial(nb, la)
+            r2 = quad(lambda r: f1(r) * f2(r) * r ** 4, 0.0, np.inf, limit=200)[0]
+            want = (Na + 1.5) * 15.0 * (a == b) - 0.5 * 15.0 * r2
+            assert abs(H[x, y] - want) <= 1e-9 * 15.0 * (Na + 1.5)
 
 
 def test_kinetic_leaves_the_gradient_unchanged():
