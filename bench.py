@@ -71,25 +71,32 @@ class EventTimer:
         return float(np.mean([a.elapsed_time(b) for a, b in self.pairs])) if self.pairs else 0.0
 
 
-def measured_traffic(kernel_file: str):
-    """HBM bytes per launch from the committed counter summary of this kernel
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the kernel
-    source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", kernel_file)
+def measured_counters(profile: str):
+    """Per-launch figures from a committed counter summary under profiles/
+    (lines "name: value"), or None when the kernel source named in it has
+    changed since the counters were taken (its SHA-256 no longer matches)."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
-    csrc = os.path.join(ROOT, "paper_1412_5989_amd", "csrc")
-    digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                     for f in ("kernels.hip", "ci_internal.h"))).hexdigest()
     fields = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            if ":" in line and not line.startswith(("|", "#", " ")):
                 k, v = line.split(":", 1)
-                fields[k] = v.strip()
-    if fields.get("kernel_source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+                fields[k.strip()] = v.strip()
+    files = fields.get("kernel_source_files", "kernels.hip ci_internal.h").split()
+    csrc = os.path.join(ROOT, "paper_1412_5989_amd", "csrc")
+    try:
+        digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in files)).hexdigest()
+    except OSError:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    out = {}
+    for k in ("traffic_bytes_per_launch", "valu_insts_per_launch"):
+        if k in fields:
+            out[k] = int(float(fields[k]))
+    return out
 
 
 def cpu_baseline(problem, tbme_seed, psi_seed, budget_s=15.0):
@@ -322,8 +329,9 @@ def run_three_body_term(ci, torch, prob, tbme_seed, with_oracle, reps=3):
     return res
 
 
-def run_batched(ci, torch, steps, warmup, stored):
-    """64 bases in one handle; fill + vjp captured in one HIP graph."""
+def run_batched(ci, torch, steps, warmup, stored, tuning_text=None):
+    """64 bases in one handle; fill + vjp of all of them captured in one HIP
+    graph and replayed.  Launch shapes from the library's autotuner."""
     import seeded_inputs as si
 
     probs, tseeds, pseeds = si.batch_problems()
@@ -346,9 +354,13 @@ def run_batched(ci, torch, steps, warmup, stored):
                                        torch.from_numpy(np.diff(seg)).cuda())
         G[seg[0]: seg[-1]] = (ps[rows] * ps[col[seg[0]: seg[-1]].long()]).float()
     gt = torch.empty(b.n_tbme, dtype=torch.float32, device="cuda")
-    work = torch.empty(b.vjp_work_bytes(), dtype=torch.uint8, device="cuda")
+    work = torch.empty(max(b.vjp_work_bytes(), 8), dtype=torch.uint8, device="cuda")
     t0 = time.perf_counter()
-    tuning = ci.ci_hamiltonian_tune(b, tb, rp, col, val, G, gt, work, reps=2)
+    if tuning_text:
+        b.tuning = parse_tuning(tuning_text)
+        tuning = b.tuning
+    else:
+        tuning = ci.ci_hamiltonian_tune(b, tb, rp, col, val, G, gt, work, reps=2)
     t_tune = time.perf_counter() - t0
     keys = torch.empty(tot if stored else 0, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
@@ -380,67 +392,61 @@ def run_batched(ci, torch, steps, warmup, stored):
     e.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(e) / steps
-    out = {"bases": len(probs), "dim_total": int(sum(i["dim"] for i in b.info)), "nnz_total": tot,
+    dim_total = int(sum(i["dim"] for i in b.info))
+    # algorithmic bytes of one replay: fill (8 B per entry + 8 B per row) and
+    # adjoint (4 B per entry + 8 B per row + 4 B per table element) of every basis
+    alg = 12 * tot + 16 * (dim_total + len(probs)) + 4 * b.n_tbme
+    achieved = alg / (ms * 1e-3) / 1e9
+    out = {"bases": len(probs), "dim_total": dim_total, "nnz_total": tot, "n_tbme_total": b.n_tbme,
            "ms_per_replay": ms, "nnz_per_s": tot / (ms * 1e-3), "setup_s": t_setup,
            "graph": "fill + vjp of all bases, one capture", "adjoint": "stored" if stored else "walk",
-           "tuning": dict(tuning, tune_s=t_tune)}
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_replay": alg},
+           "tuning": dict(tuning, tune_s=t_tune, source="fixed" if tuning_text else "autotuner")}
     b.free()
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="li6_nmax6")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--only-threebody", action="store_true",
-                    help="run only the three-body decoupling section (for counter and trace runs of its kernels)")
-    ap.add_argument("--only-three-body-term", action="store_true",
-                    help="run only the section of the matrix with a three-body term (counter and trace runs)")
-    ap.add_argument("--only-step", action="store_true",
-                    help="run only the timed construction steps (no ceiling probes, Lanczos, three-body or "
-                         "batched sections): for counter and trace runs of the step's kernels")
-    ap.add_argument("--tuning", default=None, metavar="W,G,R,N,P",
-                    help="fixed launch shapes row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent"
-                         "[,adjk_rows,adjk_tile_n] instead "
-                         "of the autotuner (for profiling runs)")
-    ap.add_argument("--adjoint", choices=("stored", "walk"), default="stored",
-                    help="stored: the fill stores one structure word per entry and the adjoint reads them; "
-                         "walk: the adjoint walks the partner lists again")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="after the timed steps, copy MIB MiB device to device three times (a plain "
-                         "copy of known size, to scale hardware byte counters under rocprofv3)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the construction path here runs on a single "
-              "MI355X (multi-GPU sharding is described in the design notes, not run).", file=sys.stderr)
-        sys.exit(2)
+VALU_PEAK = 256 * 4 * 2.4e9  # VALU wave-instructions/s: one per SIMD per cycle, 256 CUs x 4 SIMDs x 2.4 GHz
 
-    import torch
 
+def leg(ms, nnz, alg_bytes, profile):
+    """nonzeros/s, the HBM roofline of the leg's kernel from its algorithmic
+    bytes, and the VALU issue fraction from the committed counters of that
+    kernel (null when its source changed since they were taken)."""
+    c = measured_counters(profile) if profile else None
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    out = {"ms": ms, "nnz_per_s": nnz / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes,
+                        "traffic": c.get("traffic_bytes_per_launch") if c else None,
+                        "profile": profile if c else None}}
+    insts = c.get("valu_insts_per_launch") if c else None
+    out["valu_issue"] = {"insts_per_launch": insts,
+                         "frac": insts / (ms * 1e-3) / VALU_PEAK if insts else None,
+                         "peak_wave_insts_per_s": VALU_PEAK, "profile": profile if insts else None}
+    return out
+
+
+def parse_tuning(text):
+    keys = ("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows", "adjk_tile_n")
+    if "=" in text:
+        return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
+    return dict(zip(keys, (int(x) for x in text.split(","))))
+
+
+def measure_step(ci, torch, workload, steps, warmup, adjoint, tuning_text):
+    """One step = basis build (size query, arena, build, list count, lists) +
+    count/scan + fill + adjoint for one problem, inputs (two-body table,
+    upstream gradient) resident in HBM.  Returns the timings and legs."""
     import seeded_inputs as si
 
-    ci = ensure_library()
-    if args.only_threebody:
-        res = {"threebody": run_threebody(ci, torch, not args.no_cpu_baseline)}
-        copy_calibration(torch, args.copy_calibration)
-        print(json.dumps(res), flush=True)
-        return
-    w = si.WORKLOADS[args.workload]
+    w = si.WORKLOADS[workload]
     prob = w["problem"]
     stream = torch.cuda.current_stream()
-    if args.only_three_body_term:
-        res = {"three_body_term": run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)}
-        copy_calibration(torch, args.copy_calibration)
-        print(json.dumps(res), flush=True)
-        return
-
     # inputs resident in HBM before the timed region: the two-body table and
     # the upstream gradient (which needs the structure, so one setup pass)
-    log("setup", args.workload, prob)
+    log("setup", workload, prob)
     b = ci.ci_basis_build([prob])
     rp, nnz = ci.ci_hamiltonian_count(b)
     nnz = nnz[0]
@@ -449,19 +455,17 @@ def main():
     tbme = torch.from_numpy(si.tbme_f32(w["tbme_seed"], n_tbme)).cuda()
     col, val = ci.ci_hamiltonian_fill(b, tbme, rp)
     rows = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp))
-    ps = torch.from_numpy(si.psi(si.PSI_SEED.get(args.workload, 0), D)).cuda()
+    ps = torch.from_numpy(si.psi(si.PSI_SEED.get(workload, 0), D)).cuda()
     G = (ps[rows] * ps[col.long()]).float()
     del rows
     gt = torch.empty(n_tbme, dtype=torch.float32, device="cuda")
-    work = torch.empty(8 * n_tbme, dtype=torch.uint8, device="cuda")
+    work = torch.empty(max(b.vjp_work_bytes(), 8), dtype=torch.uint8, device="cuda")
     # launch shapes picked once by the library's autotuner; the handles built
     # in the timed steps start from them (process-wide cache per problem)
     fixed = None
     t0 = time.perf_counter()
-    if args.tuning:
-        fixed = dict(zip(("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows",
-                          "adjk_tile_n"),
-                         (int(x) for x in args.tuning.split(","))))
+    if tuning_text:
+        fixed = parse_tuning(tuning_text)
         b.tuning = fixed
         tuning = b.tuning
     else:
@@ -469,9 +473,10 @@ def main():
     t_tune = time.perf_counter() - t0
     log("launch shapes", tuning, "in %.2f s" % t_tune)
     b.free()
+    del col, val
     col = torch.empty(nnz, dtype=torch.int32, device="cuda")
     val = torch.empty(nnz, dtype=torch.float32, device="cuda")
-    stored = args.adjoint == "stored"
+    stored = adjoint == "stored"
     keys = torch.empty(nnz if stored else 0, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
 
@@ -511,79 +516,150 @@ def main():
         torch.cuda.synchronize()
         h.free()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = (time.perf_counter() - t0) / steps
+    fill_ms, vjp_ms = ev_fill.mean_ms(), ev_vjp.mean_ms()
+    # algorithmic HBM bytes per launch: the fill writes col + val (8 B per
+    # stored entry) and reads row_ptr (8 B per row); the adjoint reads the
+    # upstream value (4 B per entry) and row_ptr and writes the FP32 table
+    # gradient (4 B per table element).  A stored structure word is traffic,
+    # not algorithmic bytes.
+    fill_alg = 8 * nnz + 8 * (D + 1)
+    vjp_alg = 4 * nnz + 8 * (D + 1) + 4 * n_tbme
+    fwd = leg(fill_ms, nnz, fill_alg, ("row_kernel_fill_keys_%s.md" if stored else "row_kernel_fill_%s.md")
+              % workload)
+    adj = leg(vjp_ms, nnz, vjp_alg, ("adjoint_stored_kernel_%s.md" if stored else "adjoint_kernel_%s.md")
+              % workload)
+    return {"prob": prob, "dim": D, "nnz": nnz, "n_tbme": n_tbme, "sec": sec, "tuning": tuning,
+            "tune_s": t_tune, "fixed": fixed is not None,
+            "stages_ms": {"basis_build": 1e3 * float(np.mean(t_basis)),
+                          "count_scan_sync": 1e3 * float(np.mean(t_count)), "fill": fill_ms, "vjp": vjp_ms},
+            "fwd": fwd, "adjoint": adj, "adjoint_kind": "stored structure words" if stored else
+            "recomputed structure (partner-list walk)"}
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="b10_nmax4",
+                    help="headline workload: b10_nmax4 (Z=5, N=5, Nmax=4, 2M=0: forward + adjoint) by default")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-threebody", action="store_true",
+                    help="run only the three-body decoupling section (for counter and trace runs of its kernels)")
+    ap.add_argument("--only-three-body-term", action="store_true",
+                    help="run only the section of the matrix with a three-body term (counter and trace runs)")
+    ap.add_argument("--only-step", action="store_true",
+                    help="run only the timed construction steps of the headline workload (for counter and "
+                         "trace runs of the step's kernels)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched section (for counter and trace runs of its kernels)")
+    ap.add_argument("--tuning", default=None, metavar="SHAPES",
+                    help="fixed launch shapes instead of the autotuner (for profiling runs): "
+                         "row_waves,row_grab,adj_rows,adj_tile_n,adj_persistent[,adjk_rows,adjk_tile_n] "
+                         "or name=value pairs")
+    ap.add_argument("--adjoint", choices=("walk", "stored"), default="walk",
+                    help="walk (default): the adjoint recomputes the pair and phase structure by walking the "
+                         "partner lists; stored: the fill stores one structure word per entry and the adjoint "
+                         "reads them")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy MIB MiB device to device three times (a plain "
+                         "copy of known size, to scale hardware byte counters under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the construction path here runs on a single "
+              "MI355X (multi-GPU sharding is described in the design notes, not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import seeded_inputs as si
+
+    ci = ensure_library()
+    if args.only_threebody:
+        res = {"threebody": run_threebody(ci, torch, not args.no_cpu_baseline)}
+        copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(res), flush=True)
+        return
+    w = si.WORKLOADS[args.workload]
+    prob = w["problem"]
+    if args.only_three_body_term:
+        res = {"three_body_term": run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)}
+        copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(res), flush=True)
+        return
+    if args.only_batched:
+        res = {"batched": run_batched(ci, torch, max(2, args.steps), args.warmup, args.adjoint == "stored",
+                                      args.tuning)}
+        copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(res), flush=True)
+        return
+
+    m = measure_step(ci, torch, args.workload, args.steps, args.warmup, args.adjoint, args.tuning)
     copy_calibration(torch, args.copy_calibration)
-
-    fill_ms = ev_fill.mean_ms()
-    vjp_ms = ev_vjp.mean_ms()
-    # dominant kernel: the fill writes 8 B per stored entry (int32 col + FP32
-    # val; 12 B with the stored word) and reads 8 B per row of row_ptr; that
-    # is its algorithmic traffic
-    dom, dom_ms = ("fill", fill_ms) if fill_ms >= vjp_ms else ("vjp", vjp_ms)
-    if dom == "fill":
-        alg_bytes = (12 if stored else 8) * nnz + 8 * (D + 1)
-        traffic = measured_traffic("row_kernel_fill_%s.md" % args.workload)
-    else:  # reads 4 B of upstream gradient (and 4 B of stored word) per entry + row_ptr, writes the table
-        alg_bytes = (8 if stored else 4) * nnz + 8 * (D + 1) + 4 * n_tbme
-        traffic = measured_traffic(("adjoint_stored_kernel_%s.md" if stored else "adjoint_kernel_%s.md")
-                                   % args.workload)
-    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    nnz, D = m["nnz"], m["dim"]
+    dom = "fwd" if m["fwd"]["ms"] >= m["adjoint"]["ms"] else "adjoint"
+    r = m[dom]["roofline"]
     res = {
         "metric": "Hamiltonian nonzeros/sec (fwd, adjoint, batched) + roofline fraction, 1 MI355X",
-        "value": nnz / sec,
+        "value": nnz / m["sec"],
         "unit": "nonzeros/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": m["sec"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32+f32 (f64 accumulation)",
         "data": "synthetic: seeded N(0,1) MeV two-body table, seeded psi for the upstream gradient",
         "config": {"workload": args.workload, "Z": prob[0], "N": prob[1], "nmax": prob[2],
-                   "two_m": prob[3], "parity": prob[4], "dim": D, "nnz": nnz, "n_tbme": n_tbme,
-                   "step": "basis build + count/scan + fill + vjp",
-                   "adjoint": "stored structure words" if stored else "partner-list walk"},
-        "stages_ms": {"basis_build": 1e3 * float(np.mean(t_basis)), "count_scan_sync": 1e3 * float(np.mean(t_count)),
-                      "fill": fill_ms, "vjp": vjp_ms},
-        "tuning": dict(tuning, tune_s=t_tune, source="fixed" if fixed else "autotuner"),
-        "fwd_nnz_per_s": nnz / (fill_ms * 1e-3),
-        "adjoint_nnz_per_s": nnz / (vjp_ms * 1e-3),
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes},
+                   "two_m": prob[3], "parity": prob[4], "dim": D, "nnz": nnz, "n_tbme": m["n_tbme"],
+                   "step": "basis build + count/scan + fill + adjoint (vjp)", "adjoint": m["adjoint_kind"]},
+        "stages_ms": m["stages_ms"],
+        "tuning": dict(m["tuning"], tune_s=m["tune_s"], source="fixed" if m["fixed"] else "autotuner"),
+        "fwd": m["fwd"],
+        "adjoint": m["adjoint"],
+        "roofline": {"kernel": "fill" if dom == "fwd" else "vjp", "bound": "hbm", "achieved": r["achieved"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r["frac"], "traffic": r["traffic"],
+                     "alg_bytes_per_launch": r["alg_bytes_per_launch"]},
     }
     if args.only_step:
         print(json.dumps(res), flush=True)
         return
+    # the 6Li Nmax=6 workload (W = 4 words per species, 3.97e6 table elements)
+    log("li6")
+    m6 = measure_step(ci, torch, "li6_nmax6", max(3, args.steps // 2), 1, args.adjoint, None)
+    res["li6_nmax6"] = {"dim": m6["dim"], "nnz": m6["nnz"], "n_tbme": m6["n_tbme"],
+                        "step_nnz_per_s": m6["nnz"] / m6["sec"], "ms_per_step": m6["sec"] * 1e3,
+                        "stages_ms": m6["stages_ms"], "fwd": m6["fwd"], "adjoint": m6["adjoint"],
+                        "tuning": m6["tuning"]}
     # measured machine ceilings (streaming stores; XOR + popcount issue rate)
     ceil = ci.ci_probe_ceilings(1024)
-    fill_bytes = (12 if stored else 8) * nnz + 8 * (D + 1)  # col + val (+ stored word) per entry, row_ptr
     res["measured_ceilings"] = {
         "store_GBps": ceil["store_GBps"],
         "xor_popcount_steps_per_s": ceil["xor_popcount_steps_per_s"],
         "valu_lane_ops_per_s": 5 * ceil["xor_popcount_steps_per_s"],
-        "fill_store_GBps": fill_bytes / (fill_ms * 1e-3) / 1e9,
-        "fill_frac_of_measured_store": fill_bytes / (fill_ms * 1e-3) / 1e9 / ceil["store_GBps"],
+        "fill_frac_of_measured_store": m["fwd"]["roofline"]["achieved"] / ceil["store_GBps"],
     }
+    if not args.no_batched:
+        log("batched")
+        res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1, args.adjoint == "stored", None)
     log("lanczos")
-    res["lanczos"] = run_lanczos(ci, torch, prob, w["tbme_seed"])
+    res["lanczos"] = run_lanczos(ci, torch, si.WORKLOADS["li6_nmax6"]["problem"], si.WORKLOADS["li6_nmax6"]["tbme_seed"])
     log("three-body")
     res["threebody"] = run_threebody(ci, torch, not args.no_cpu_baseline)
     log("three-body term")
-    res["three_body_term"] = run_three_body_term(ci, torch, prob, w["tbme_seed"], not args.no_cpu_baseline)
-    if not args.no_batched:
-        log("batched")
-        res["batched"] = run_batched(ci, torch, max(3, args.steps // 2), 1, stored)
+    res["three_body_term"] = run_three_body_term(ci, torch, si.WORKLOADS["li6_nmax6"]["problem"],
+                                                 si.WORKLOADS["li6_nmax6"]["tbme_seed"], not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(prob, w["tbme_seed"], si.PSI_SEED.get(args.workload, 0))

@@ -49,10 +49,17 @@
  *   start at T_b = sum_{c<b} n_tbme_c.
  *
  * Memory: every array argument marked "device" is caller-owned device memory
- * (for example a torch tensor on the GPU).  ci_basis_build allocates the index
- * tables on the current device and keeps them in the handle until
- * ci_basis_free.  No call keeps a pointer to a caller array after it returns.
- * All launches go to the given stream (hipStream_t; NULL = the null stream).
+ * (for example a torch tensor on the GPU).  The two-body path allocates no
+ * device memory: the index tables of a basis live in an arena the caller
+ * passes to ci_basis_build, its partner lists in memory the caller passes to
+ * ci_basis_build_lists (sizes from a size query and from ci_basis_list_bytes),
+ * and the handle keeps pointers to these two buffers until ci_basis_free; the
+ * caller keeps them alive (and unused by anything else) until the last call
+ * on the handle has run.  No other call keeps a pointer to a caller array
+ * after it returns.  All launches go to the given stream (hipStream_t; NULL =
+ * the null stream).  The calls that read a count back and so synchronize the
+ * stream are ci_basis_list_bytes, ci_hamiltonian_count(_full), the
+ * three-body counts, ci_lanczos, ci_hamiltonian_tune and ci_probe_ceilings.
  *
  * Errors: every call returns CI_OK (0) or a negative CI_E* code; the message
  * of the last failure on the calling thread is ci_last_error().  Validation
@@ -100,7 +107,9 @@ typedef struct {
     int64_t n_tbme;       /* two-body table length */
     int64_t row_ptr_offset; /* R_b */
     int64_t tbme_offset;    /* T_b */
-    int64_t index_bytes;    /* device bytes of this basis' index tables */
+    int64_t index_bytes;    /* device bytes of this basis' index tables (-1 until the lists are counted) */
+    int64_t arena_bytes;    /* bytes of the arena of the whole build (the same in every entry) */
+    int64_t list_bytes;     /* bytes of the partner lists of the whole build (-1 until counted) */
 } ci_basis_info;
 
 typedef struct ci_basis ci_basis; /* opaque */
@@ -138,22 +147,35 @@ int ci_basis_plan(const ci_problem* probs, int32_t n_probs, ci_basis_info* info)
  * abcd [n_tbme][4] int32 host memory with room for cap rows. */
 int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap);
 
-/* Builds the basis indexing (Sec. 2) of n_probs problems: enumerates the
- * determinants, blocks and the two-body pair index on the host and moves the
- * host-built tables with one device allocation (Sec. 5.2); the one- and
- * two-nucleon partner lists are built on the device (one more allocation,
- * sized after a count pass that the build waits for).  info[n_probs] is
- * filled; *out receives the handle.  Returns while the partner lists are
- * still being filled on `stream`: later calls on the same stream are ordered
- * after them; work on another stream must first synchronize with it. */
-int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info,
-                   ci_basis** out, ci_stream stream);
+/* Builds the basis indexing (Sec. 2) of n_probs problems in three calls, the
+ * count-then-allocate pattern of Sec. 4.1 applied to the index itself:
+ *
+ * 1. ci_basis_build with arena = NULL (size query, host only, no device
+ *    call): plans the problems and fills info[n_probs]; info[b].arena_bytes is
+ *    the arena the build needs (n_tbme, tbme_offset, index_bytes and
+ *    list_bytes are -1 until the build).  The plan is kept for the calling
+ *    thread, so that the build that follows with the same problems does not
+ *    plan again.
+ * 2. ci_basis_build with an arena (device memory, caller owned, at least
+ *    arena_bytes, any contents): writes the host-built tables (determinants,
+ *    keys, blocks, two-body pair index) into it with one copy (Sec. 5.2) and
+ *    starts the count of the one- and two-nucleon partner lists on `stream`;
+ *    fills info and returns the handle in *out without waiting for the
+ *    device.  CI_ESPACE (and the plan kept) if arena_bytes is too small.
+ * 3. ci_basis_list_bytes (synchronizes the stream: it reads the list lengths
+ *    back) gives the bytes of the partner lists; ci_basis_build_lists fills
+ *    them into caller memory of at least that size (asynchronous).
+ *
+ * Every later call on the handle needs the lists (CI_EINVAL before).  Work on
+ * another stream than the build's must first synchronize with it. */
+int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info, void* arena,
+                   size_t arena_bytes, ci_basis** out, ci_stream stream);
+int ci_basis_list_bytes(ci_basis* b, size_t* bytes, ci_stream stream);
+int ci_basis_build_lists(ci_basis* b, void* lists, size_t bytes, ci_stream stream);
 
-/* Frees the handle (NULL is allowed).  Its two device blocks (index tables,
- * partner lists) go to a cache of the library after the device is
- * synchronized, and later builds of similar size on that device take them
- * instead of allocating; the cache keeps at most 8 blocks per device and
- * 4 GiB in all and frees the oldest beyond that. */
+/* Frees the handle's host memory (NULL is allowed); no device call.  The
+ * arena and the list memory stay the caller's: they may be reused once the
+ * work queued on the handle has run (stream order). */
 void ci_basis_free(ci_basis* b);
 
 /* Count pass (Sec. 4.1): row_ptr (device, int64, sum_b (D_b + 1)) receives

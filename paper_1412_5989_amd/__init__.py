@@ -51,7 +51,8 @@ class ci_basis_info(ctypes.Structure):
                 ("n_blocks", ctypes.c_int32), ("n_sectors", ctypes.c_int32),
                 ("n_psd", ctypes.c_int64), ("n_nsd", ctypes.c_int64), ("dim", ctypes.c_int64),
                 ("n_tbme", ctypes.c_int64), ("row_ptr_offset", ctypes.c_int64),
-                ("tbme_offset", ctypes.c_int64), ("index_bytes", ctypes.c_int64)]
+                ("tbme_offset", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("list_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -74,7 +75,8 @@ class ci_tuning(ctypes.Structure):
 
 
 # every symbol include/ci.h declares
-EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_free",
+EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_list_bytes",
+           "ci_basis_build_lists", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
            "ci_hamiltonian_fill_keys", "ci_hamiltonian_vjp_keys",
            "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill",
@@ -101,7 +103,9 @@ def load_library():
     L.ci_last_error.restype = ctypes.c_char_p
     L.ci_basis_plan.argtypes = [P(ci_problem), i32, P(ci_basis_info)]
     L.ci_tbme_keys.argtypes = [P(ci_problem), vp, i64]
-    L.ci_basis_build.argtypes = [P(ci_problem), i32, P(ci_basis_info), P(vp), vp]
+    L.ci_basis_build.argtypes = [P(ci_problem), i32, P(ci_basis_info), vp, sz, P(vp), vp]
+    L.ci_basis_list_bytes.argtypes = [vp, P(sz), vp]
+    L.ci_basis_build_lists.argtypes = [vp, vp, sz, vp]
     L.ci_basis_free.argtypes = [vp]
     L.ci_basis_free.restype = None
     L.ci_hamiltonian_count.argtypes = [vp, vp, vp, vp]
@@ -204,16 +208,32 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 class Basis:
-    """Handle of one or more bases built on the current device."""
+    """Handle of one or more bases built on the current device.
+
+    The device memory of the handle is two torch tensors owned here: the
+    arena of the index tables (size from the build's size query) and the
+    partner lists (size from ci_basis_list_bytes); the library allocates no
+    device memory.  Both live as long as this object."""
 
     def __init__(self, problems, stream=None):
         torch = _torch()
+        L = load_library()
         arr, n = _problems(problems)
         info = (ci_basis_info * n)()
-        h = ctypes.c_void_p()
-        _check(load_library().ci_basis_build(arr, n, info, ctypes.byref(h), _stream_ptr(stream)))
-        self._h = h
+        sp = _stream_ptr(stream)
         self.device = torch.device("cuda", torch.cuda.current_device())
+        _check(L.ci_basis_build(arr, n, info, None, 0, None, sp))  # size query (host only)
+        abytes = int(info[0].arena_bytes)
+        self._arena = torch.empty(max(abytes, 1), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(L.ci_basis_build(arr, n, info, _ptr(self._arena), abytes, ctypes.byref(h), sp))
+        self._h = h
+        lb = ctypes.c_size_t()
+        _check(L.ci_basis_list_bytes(h, ctypes.byref(lb), sp))
+        self._lists = torch.empty(max(int(lb.value), 1), dtype=torch.uint8, device=self.device)
+        _check(L.ci_basis_build_lists(h, _ptr(self._lists), int(lb.value), sp))
+        for k in range(n):  # index_bytes / list_bytes are known now
+            _check(L.ci_basis_get_info(h, k, ctypes.byref(info[k])))
         self.problems = [tuple(int(x) for x in (p.Z, p.N, p.nmax, p.two_m, p.parity)) for p in arr]
         self.info = [info[k].as_dict() for k in range(n)]
         self.n_probs = n
@@ -226,9 +246,13 @@ class Basis:
         return self._h
 
     def free(self):
+        """Frees the handle (host memory) and drops the tensors of its device
+        memory; torch's allocator reuses them in stream order."""
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().ci_basis_free(self._h)
             self._h = None
+        self._arena = None
+        self._lists = None
 
     def __del__(self):
         try:

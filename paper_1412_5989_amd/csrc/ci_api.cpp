@@ -62,94 +62,11 @@ static int hip_fail(hipError_t e, const char* where)
 }
 
 // ---------------------------------------------------------------------------
-// Device block cache of the handles' index memory.  A build takes two blocks
-// (index tables, partner lists); returning them with hipFree would synchronize
-// the device and cost tens of microseconds each, so a freed handle parks them
-// here and the next build of a similar problem takes them back.  A block enters
-// the cache only after its device has been synchronized (no kernel that reads
-// it can still be running); the cache holds at most kCacheBlocks blocks per
-// device and kCacheBytes in total, and frees the oldest beyond that.  A block
-// is reused for requests of between half its size and its size.
-namespace {
-constexpr int kCacheBlocks = 8;
-constexpr size_t kCacheBytes = size_t(4) << 30;
-struct CachedBlock {
-    int device;
-    void* p;
-    size_t bytes;
-};
-std::mutex g_cache_mu;
-std::vector<CachedBlock> g_cache;  // oldest first
-size_t g_cache_total = 0;
-}  // namespace
-
-static hipError_t dev_alloc(int device, size_t bytes, void** p, size_t* got)
-{
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        int best = -1;
-        for (int i = 0; i < (int)g_cache.size(); i++) {
-            const CachedBlock& c = g_cache[i];
-            if (c.device == device && c.bytes >= bytes && c.bytes / 2 <= bytes &&
-                (best < 0 || c.bytes < g_cache[best].bytes))
-                best = i;
-        }
-        if (best >= 0) {
-            *p = g_cache[best].p;
-            *got = g_cache[best].bytes;
-            g_cache_total -= *got;
-            g_cache.erase(g_cache.begin() + best);
-            return hipSuccess;
-        }
-    }
-    *got = bytes;
-    return hipMalloc(p, bytes);
-}
-
-static void dev_release(int device, void* p, size_t bytes)
-{
-    if (!p) return;
-    int cur = -1;
-    bool ok = bytes <= kCacheBytes && hipGetDevice(&cur) == hipSuccess;
-    if (ok && cur != device) ok = hipSetDevice(device) == hipSuccess;
-    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
-    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
-    if (!ok) {
-        (void)hipFree(p);
-        return;
-    }
-    std::vector<void*> evict;
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto count_dev = [&]() {
-            int n = 0;
-            for (const CachedBlock& c : g_cache) n += c.device == device;
-            return n;
-        };
-        while (!g_cache.empty() && (count_dev() >= kCacheBlocks || g_cache_total + bytes > kCacheBytes)) {
-            // the oldest block of this device, else the oldest of any
-            int v = 0;
-            for (int i = 0; i < (int)g_cache.size(); i++)
-                if (g_cache[i].device == device) {
-                    v = i;
-                    break;
-                }
-            evict.push_back(g_cache[v].p);
-            g_cache_total -= g_cache[v].bytes;
-            g_cache.erase(g_cache.begin() + v);
-        }
-        g_cache.push_back({device, p, bytes});
-        g_cache_total += bytes;
-    }
-    for (void* q : evict) (void)hipFree(q);
-}
-
-// Per-thread pinned staging buffer of the host-written tables, the list
-// lengths read back and the descriptors (grown as needed and kept): copies out
-// of pinned memory are asynchronous, so the host goes on while they run.  A
-// build returns before its last copy out of the buffer has run; an event
-// recorded after that copy is waited on before the next build on the thread
-// writes the buffer again.
+// Per-thread pinned staging buffer of the host-written tables and the
+// descriptors (host memory, grown as needed and kept): copies out of pinned
+// memory are asynchronous, so the host goes on while they run.  A build
+// returns before its last copy out of the buffer has run; an event recorded
+// after that copy is waited on before the buffer is written again.
 struct StagingFence {
     hipEvent_t ev = nullptr;
     int device = -1;
@@ -261,42 +178,6 @@ static int64_t* pinned_counts(size_t n)
     }
     return b.p;
 }
-
-struct ci_basis {
-    int device = 0;
-    std::vector<ci_basis_info> info;
-    std::vector<std::shared_ptr<HostBasis>> host;  // per problem (shared for equal problems)
-    void* arena = nullptr;                         // index tables
-    void* lists = nullptr;                         // partner lists
-    size_t arena_bytes = 0, list_bytes = 0;
-    BasisDev* d_bases = nullptr;
-    int64_t* d_basis_row0 = nullptr;  // first global row of each basis, [n + 1]
-    int64_t nrows = 0;                // sum of the dimensions
-    int64_t* d_seg_first = nullptr;   // R_b
-    int64_t* d_seg_last = nullptr;    // R_b + D_b
-    int64_t* d_scan_tmp = nullptr;
-    int64_t* d_nnz = nullptr;
-    unsigned long long* d_queue = nullptr;  // work counter of the persistent launches
-    int32_t* d_blk_basis = nullptr;         // global block list of the batch: problem, local block
-    int32_t* d_blk_local = nullptr;
-    int64_t* d_tile_off = nullptr;          // adjoint tiles per block (inclusive scan), [nblocks + 1]
-    int nblocks = 0;
-    ci_tuning tune{};
-    std::vector<ci_problem> probs;          // key of the process-wide tuning cache
-    int64_t n_rowptr = 0;
-    int64_t n_tbme = 0;
-    // neutron partner index of the three-body walk (built on first use):
-    // per basis (seg, ptr, rec) device pointers, and the allocations
-    std::vector<const void*> h3_index;
-    std::vector<void*> h3_mem;
-    ~ci_basis()
-    {
-        dev_release(device, arena, arena_bytes);
-        dev_release(device, lists, list_bytes);
-        for (void* m : h3_mem) (void)hipFree(m);
-    }
-};
-
 namespace {
 
 // Bump layout (256-byte aligned pieces) of one device allocation.
@@ -476,6 +357,237 @@ void remember_tuning(const std::vector<ci_problem>& p, const ci_tuning& t)
     g_tune[tune_key(p)] = t;
 }
 }  // namespace
+// The handle.  Its device memory is the caller's: the index tables live in
+// the arena given to ci_basis_build, the partner lists in the memory given to
+// ci_basis_build_lists; the library neither allocates nor frees device memory
+// for the two-body path.  Host memory: the planned tables of each problem.
+struct ci_basis {
+    int device = 0;
+    std::vector<ci_basis_info> info;
+    std::vector<std::shared_ptr<HostBasis>> host;  // per problem (shared for equal problems)
+    char* arena = nullptr;                         // caller's: index tables
+    char* lists = nullptr;                         // caller's: partner lists
+    size_t arena_bytes = 0, list_bytes = 0;
+    bool lists_counted = false;  // ci_basis_list_bytes has read the list lengths
+    bool ready = false;          // ci_basis_build_lists has placed the lists
+    // what the partner lists need after the build
+    std::vector<std::shared_ptr<HostBasis>> uniq;  // unique problems
+    std::vector<int> which;                        // problem -> unique problem
+    std::vector<int> canon;                        // species table 2u + s -> first equal table
+    std::vector<UOff> uo;                          // offsets of the unique problems' tables in the arena
+    std::vector<int64_t> totals;                   // list lengths (l1, l12) per species table
+    std::vector<size_t> lo1, lo12;                 // list offsets in the list memory
+    std::vector<BasisDev> bd;                      // descriptors (list pointers set when placed)
+    BasisDev* d_bases = nullptr;
+    int64_t* d_basis_row0 = nullptr;  // first global row of each basis, [n + 1]
+    int64_t nrows = 0;                // sum of the dimensions
+    int64_t* d_seg_first = nullptr;   // R_b
+    int64_t* d_seg_last = nullptr;    // R_b + D_b
+    int64_t* d_scan_tmp = nullptr;
+    int64_t* d_nnz = nullptr;
+    unsigned long long* d_queue = nullptr;  // work counter of the persistent launches
+    int32_t* d_blk_basis = nullptr;         // global block list of the batch: problem, local block
+    int32_t* d_blk_local = nullptr;
+    int64_t* d_tile_off = nullptr;          // adjoint tiles per block (inclusive scan), [nblocks + 1]
+    int nblocks = 0;
+    ci_tuning tune{};
+    std::vector<ci_problem> probs;          // key of the process-wide tuning cache
+    int64_t n_rowptr = 0;
+    int64_t n_tbme = 0;
+    // three-body partner indexes (built on first use; library allocations):
+    // per basis (seg, ptr, rec) device pointers, and the allocations
+    std::vector<const void*> h3_index;
+    std::vector<void*> h3_mem;
+    ~ci_basis()
+    {
+        for (void* m : h3_mem) (void)hipFree(m);
+    }
+};
+
+namespace {
+
+// Host plan of one build and the layout of its arena.  The size query of
+// ci_basis_build makes it and keeps it for the calling thread, so that the
+// build that follows with the same problems does not plan again.
+struct BuildPlan {
+    std::vector<Key> keys;  // the problem list
+    std::vector<ci_problem> probs;
+    std::vector<int> which;
+    std::vector<std::shared_ptr<HostBasis>> ub;
+    std::unique_ptr<PairIndexer> pairs;  // two-body pair indexes, on a helper thread
+    std::vector<int> canon;
+    std::vector<UOff> uo;
+    size_t pair_start = 0, host_bytes = 0;
+    size_t o_row0 = 0, o_first = 0, o_last = 0, o_blk_basis = 0, o_blk_local = 0;
+    size_t o_bases = 0, o_scan = 0, o_nnz = 0, o_queue = 0, o_tile_off = 0, bytes = 0;
+    int nblocks = 0;
+};
+
+thread_local std::unique_ptr<BuildPlan> t_pending;
+
+std::vector<Key> keys_of(const ci_problem* probs, int32_t n)
+{
+    std::vector<Key> k;
+    for (int32_t b = 0; b < n; b++) k.push_back(key_of(probs[b]));
+    return k;
+}
+
+// Validates and plans the problems (orbits, then the pair indexes on a helper
+// thread while the determinants are enumerated here) and lays out the arena.
+int plan_build(const ci_problem* probs, int32_t n_probs, BuildPlan& P, std::string& err)
+{
+    P.keys = keys_of(probs, n_probs);
+    P.probs.assign(probs, probs + n_probs);
+    std::map<Key, int> uniq;
+    P.which.assign(n_probs, 0);
+    for (int32_t b = 0; b < n_probs; b++) {
+        int rc = validate_problem(probs[b], err);
+        if (rc != CI_OK) return err = "problem " + std::to_string(b) + ": " + err, rc;
+        auto it = uniq.find(P.keys[b]);
+        if (it != uniq.end()) {
+            P.which[b] = it->second;
+            continue;
+        }
+        auto hb = std::make_shared<HostBasis>();
+        rc = plan_orbits(probs[b], *hb, err);
+        if (rc != CI_OK) return err = "problem " + std::to_string(b) + ": " + err, rc;
+        P.which[b] = (int)P.ub.size();
+        uniq[P.keys[b]] = P.which[b];
+        P.ub.push_back(hb);
+    }
+    P.pairs.reset(new PairIndexer(P.ub));
+    for (size_t u = 0; u < P.ub.size(); u++) {
+        const int rc = plan_determinants(*P.ub[u], err);
+        if (rc != CI_OK) return err = "problem " + std::to_string(u) + ": " + err, rc;
+    }
+    // Species tables with equal content (protons and neutrons of an N = Z
+    // nucleus, or one species shared by several problems of a batch) are
+    // stored once and get their partner lists once: canon[2u + s] is the
+    // first equal species table.
+    const std::vector<std::shared_ptr<HostBasis>>& ub = P.ub;
+    const int nsp = 2 * (int)ub.size();
+    P.canon.assign(nsp, 0);
+    for (int i = 0; i < nsp; i++) {
+        P.canon[i] = i;
+        for (int j = 0; j < i; j++)
+            if (P.canon[j] == j && same_species(*ub[i / 2], i % 2, *ub[j / 2], j % 2)) {
+                P.canon[i] = j;
+                break;
+            }
+    }
+    // Arena: tables the host writes first (mirrored and copied up), then the
+    // tables the device computes (never copied).
+    Layout L;
+    P.uo.assign(ub.size(), UOff{});
+    std::vector<size_t> ubytes(ub.size(), 0);
+    int64_t max_scan = 1;
+    for (size_t u = 0; u < ub.size(); u++) {
+        const HostBasis& hb = *ub[u];
+        for (int sidx = 0; sidx < 2; sidx++) {
+            if (P.canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
+            const HostSpecies& sp = hb.sp[sidx];
+            SpOff& o = P.uo[u].sp[sidx];
+            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
+            const size_t s0 = L.off;
+            o.sd = L.take<uint64_t>(sp.sd.size());
+            o.sdT = L.take<uint64_t>(sp.sd.size());
+            o.sd_key = L.take<int32_t>(nsd);
+            o.key_off = L.take<int32_t>(nk + 1);
+            o.key_nq = L.take<int32_t>(nk);
+            o.key_m2 = L.take<int32_t>(nk);
+            ubytes[u] += L.off - s0;
+        }
+        const size_t s0 = L.off;
+        P.uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
+        P.uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
+        P.uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
+        P.uo[u].blk = L.take<BlockInfo>(hb.blk_kp.size());
+        P.uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
+        P.uo[u].orb_qn = L.take<int32_t>(hb.orb_n.size());
+        ubytes[u] += L.off - s0;
+    }
+    P.o_row0 = L.take<int64_t>(n_probs + 1);
+    P.o_first = L.take<int64_t>(n_probs);
+    P.o_last = L.take<int64_t>(n_probs);
+    P.nblocks = 0;
+    for (int32_t b = 0; b < n_probs; b++) P.nblocks += ub[P.which[b]]->nblk();
+    P.o_blk_basis = L.take<int32_t>(std::max(P.nblocks, 1));
+    P.o_blk_local = L.take<int32_t>(std::max(P.nblocks, 1));
+    // the pair indices last: they are written after the partner kernels start
+    P.pair_start = L.off;
+    for (size_t u = 0; u < ub.size(); u++) {
+        const size_t n = (size_t)ub[u]->nsps;
+        P.uo[u].pair = L.take<uint64_t>(3 * n * n);
+        ubytes[u] += 3 * n * n * sizeof(uint64_t);
+    }
+    P.host_bytes = L.off;
+    for (size_t u = 0; u < ub.size(); u++) {
+        const HostBasis& hb = *ub[u];
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const int c = P.canon[2 * u + sidx];
+            SpOff& o = P.uo[u].sp[sidx];
+            if (c != (int)(2 * u + sidx)) {
+                o = P.uo[c / 2].sp[c % 2];
+                continue;
+            }
+            const HostSpecies& sp = hb.sp[sidx];
+            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
+            const size_t s0 = L.off;
+            o.l1_ptr = L.take<int64_t>(nsd + 1);
+            o.l12_ptr = L.take<int64_t>(nsd + 1);
+            o.seg1 = L.take<int32_t>(nsd * (nk + 1));
+            o.seg12 = L.take<int32_t>(nsd * (nk + 1));
+            o.self12 = L.take<int32_t>(nsd);
+            ubytes[u] += L.off - s0;
+            max_scan = std::max<int64_t>(max_scan, (int64_t)nsd + 1);
+        }
+        P.uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
+        P.uo[u].bytes = ubytes[u];
+    }
+    int64_t R = 0;
+    for (int32_t b = 0; b < n_probs; b++) R += ub[P.which[b]]->dim + 1;
+    max_scan = std::max(max_scan, R);
+    P.o_bases = L.take<BasisDev>(n_probs);
+    P.o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
+    P.o_nnz = L.take<int64_t>(n_probs);
+    P.o_queue = L.take<unsigned long long>(1);
+    P.o_tile_off = L.take<int64_t>(P.nblocks + 1);
+    P.bytes = L.bytes();
+    return CI_OK;
+}
+
+// Arguments of the partner-list kernels of unique problem u, species sidx.
+PartnerArgs partner_args(const ci_basis& h, size_t u, int sidx)
+{
+    const HostSpecies& sp = h.uniq[u]->sp[sidx];
+    const SpOff& o = h.uo[u].sp[sidx];
+    char* dev = h.arena;
+    PartnerArgs a{};
+    a.sd = (const uint64_t*)(dev + o.sd);
+    a.sdT = (const uint64_t*)(dev + o.sdT);
+    a.sd_key = (const int32_t*)(dev + o.sd_key);
+    a.key_off = (const int32_t*)(dev + o.key_off);
+    a.key_nq = (const int32_t*)(dev + o.key_nq);
+    a.key_m2 = (const int32_t*)(dev + o.key_m2);
+    a.l1_ptr = (int64_t*)(dev + o.l1_ptr);
+    a.l12_ptr = (int64_t*)(dev + o.l12_ptr);
+    a.seg1 = (int32_t*)(dev + o.seg1);
+    a.seg12 = (int32_t*)(dev + o.seg12);
+    a.self12 = (int32_t*)(dev + o.self12);
+    a.nsd = (int32_t)sp.nsd();
+    a.nk = sp.nk();
+    a.W = h.uniq[u]->W;
+    return a;
+}
+
+int need_ready(const ci_basis* b)
+{
+    if (!b) return fail(CI_EINVAL, "null pointer");
+    if (!b->ready) return fail(CI_EINVAL, "the basis has no partner lists yet (ci_basis_list_bytes, ci_basis_build_lists)");
+    return CI_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -485,15 +597,21 @@ int ci_basis_plan(const ci_problem* probs, int32_t n_probs, ci_basis_info* info)
 {
     if (!probs || !info || n_probs <= 0) return fail(CI_EINVAL, "null pointer or n_probs <= 0");
     std::string err;
+    BuildPlan P;
+    int rc = plan_build(probs, n_probs, P, err);
+    if (rc != CI_OK) return fail(rc, err);
+    size_t bad = 0;
+    rc = P.pairs->wait(&bad, err);
+    if (rc != CI_OK) return fail(rc, "problem " + std::to_string(bad) + ": " + err);
     int64_t R = 0, T = 0;
     for (int32_t b = 0; b < n_probs; b++) {
-        HostBasis hb;
-        int rc = plan_basis(probs[b], hb, err);
-        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
+        const HostBasis& hb = *P.ub[P.which[b]];
         fill_info(hb, info[b]);
         info[b].row_ptr_offset = R;
         info[b].tbme_offset = T;
-        info[b].index_bytes = -1;  // known after the partner lists are built
+        info[b].index_bytes = -1;  // known after the partner lists are counted
+        info[b].arena_bytes = (int64_t)P.bytes;
+        info[b].list_bytes = -1;
         R += hb.dim + 1;
         T += hb.n_tbme;
     }
@@ -514,146 +632,57 @@ int ci_tbme_keys(const ci_problem* prob, int32_t* abcd, int64_t cap)
     return CI_OK;
 }
 
-int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info, ci_basis** out,
-                   ci_stream stream)
+int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info, void* arena,
+                   size_t arena_bytes, ci_basis** out, ci_stream stream)
 {
-    if (!probs || !info || !out || n_probs <= 0) return fail(CI_EINVAL, "null pointer or n_probs <= 0");
-    *out = nullptr;
+    if (!probs || !info || n_probs <= 0) return fail(CI_EINVAL, "null pointer or n_probs <= 0");
+    if (out) *out = nullptr;
+    std::string err;
+    // the plan of a size query with the same problems on this thread, else a new one
+    std::unique_ptr<BuildPlan> P;
+    if (t_pending && t_pending->keys == keys_of(probs, n_probs)) P = std::move(t_pending);
+    t_pending.reset();
+    if (!P) {
+        P.reset(new BuildPlan());
+        const int rc = plan_build(probs, n_probs, *P, err);
+        if (rc != CI_OK) return fail(rc, err);
+    }
+    const std::vector<std::shared_ptr<HostBasis>>& ub = P->ub;
+    if (!arena) {
+        // size query: no device call; the table sizes follow the build
+        int64_t R = 0;
+        for (int32_t b = 0; b < n_probs; b++) {
+            const HostBasis& hb = *ub[P->which[b]];
+            fill_info(hb, info[b]);
+            info[b].n_tbme = -1;
+            info[b].row_ptr_offset = R;
+            info[b].tbme_offset = -1;
+            info[b].index_bytes = -1;
+            info[b].arena_bytes = (int64_t)P->bytes;
+            info[b].list_bytes = -1;
+            R += hb.dim + 1;
+        }
+        t_pending = std::move(P);
+        return CI_OK;
+    }
+    if (!out) return fail(CI_EINVAL, "null pointer");
+    if (arena_bytes < P->bytes) {
+        t_pending = std::move(P);  // a retry with a larger arena plans nothing again
+        return fail(CI_ESPACE, "the arena needs " + std::to_string(t_pending->bytes) + " bytes");
+    }
     hipStream_t s = (hipStream_t)stream;
     std::unique_ptr<ci_basis> h(new ci_basis());
-    std::string err;
-    // host tables; equal problems share one set of device tables
-    std::map<Key, int> uniq;
-    std::vector<int> which(n_probs);
-    std::vector<std::shared_ptr<HostBasis>> ub;
-    for (int32_t b = 0; b < n_probs; b++) {
-        int rc = validate_problem(probs[b], err);
-        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
-        auto it = uniq.find(key_of(probs[b]));
-        if (it != uniq.end()) {
-            which[b] = it->second;
-            continue;
-        }
-        auto hb = std::make_shared<HostBasis>();
-        rc = plan_orbits(probs[b], *hb, err);
-        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(b) + ": " + err);
-        which[b] = (int)ub.size();
-        uniq[key_of(probs[b])] = which[b];
-        ub.push_back(hb);
-    }
-    PairIndexer pairs(ub);
-    for (size_t u = 0; u < ub.size(); u++) {
-        const int rc = plan_determinants(*ub[u], err);
-        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(u) + ": " + err);
-    }
-
-    // Species tables with equal content (protons and neutrons of an N = Z
-    // nucleus, or one species shared by several problems of a batch) are
-    // stored once and get their partner lists once: canon[2u + s] is the
-    // first equal species table.
-    const int nsp = 2 * (int)ub.size();
-    std::vector<int> canon(nsp);
-    for (int i = 0; i < nsp; i++) {
-        canon[i] = i;
-        for (int j = 0; j < i; j++)
-            if (canon[j] == j && same_species(*ub[i / 2], i % 2, *ub[j / 2], j % 2)) {
-                canon[i] = j;
-                break;
-            }
-    }
-
-    // ---- allocation 1: index tables, per-problem descriptors, small buffers.
-    // Tables the host writes come first (they are mirrored and copied up);
-    // tables the device computes follow (never copied).
-    Layout L;
-    std::vector<UOff> uo(ub.size());
-    std::vector<size_t> ubytes(ub.size(), 0);
-    int64_t max_scan = 1;
-    for (size_t u = 0; u < ub.size(); u++) {
-        const HostBasis& hb = *ub[u];
-        for (int sidx = 0; sidx < 2; sidx++) {
-            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
-            const HostSpecies& sp = hb.sp[sidx];
-            SpOff& o = uo[u].sp[sidx];
-            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
-            const size_t s0 = L.off;
-            o.sd = L.take<uint64_t>(sp.sd.size());
-            o.sdT = L.take<uint64_t>(sp.sd.size());
-            o.sd_key = L.take<int32_t>(nsd);
-            o.key_off = L.take<int32_t>(nk + 1);
-            o.key_nq = L.take<int32_t>(nk);
-            o.key_m2 = L.take<int32_t>(nk);
-            ubytes[u] += L.off - s0;
-        }
-        const size_t s0 = L.off;
-        uo[u].blk_kp = L.take<int32_t>(hb.blk_kp.size());
-        uo[u].blk_kn = L.take<int32_t>(hb.blk_kn.size());
-        uo[u].blk_off = L.take<int64_t>(hb.blk_off.size());
-        uo[u].blk = L.take<BlockInfo>(hb.blk_kp.size());
-        uo[u].orb_n = L.take<int32_t>(hb.orb_n.size());
-        uo[u].orb_qn = L.take<int32_t>(hb.orb_n.size());
-        ubytes[u] += L.off - s0;
-    }
-    const size_t o_row0 = L.take<int64_t>(n_probs + 1);
-    const size_t o_first = L.take<int64_t>(n_probs);
-    const size_t o_last = L.take<int64_t>(n_probs);
-    int nblocks = 0;
-    for (int32_t b = 0; b < n_probs; b++) nblocks += ub[which[b]]->nblk();
-    const size_t o_blk_basis = L.take<int32_t>(std::max(nblocks, 1));
-    const size_t o_blk_local = L.take<int32_t>(std::max(nblocks, 1));
-    // the pair indices last: they are written after the partner kernels start
-    const size_t pair_start = L.off;
-    for (size_t u = 0; u < ub.size(); u++) {
-        const size_t n = (size_t)ub[u]->nsps;
-        uo[u].pair = L.take<uint64_t>(3 * n * n);
-        ubytes[u] += 3 * n * n * sizeof(uint64_t);
-    }
-    const size_t host_bytes = L.off;
-    for (size_t u = 0; u < ub.size(); u++) {
-        const HostBasis& hb = *ub[u];
-        for (int sidx = 0; sidx < 2; sidx++) {
-            const int c = canon[2 * u + sidx];
-            SpOff& o = uo[u].sp[sidx];
-            if (c != (int)(2 * u + sidx)) {
-                o = uo[c / 2].sp[c % 2];
-                continue;
-            }
-            const HostSpecies& sp = hb.sp[sidx];
-            const size_t nsd = (size_t)sp.nsd(), nk = (size_t)sp.nk();
-            const size_t s0 = L.off;
-            o.l1_ptr = L.take<int64_t>(nsd + 1);
-            o.l12_ptr = L.take<int64_t>(nsd + 1);
-            o.seg1 = L.take<int32_t>(nsd * (nk + 1));
-            o.seg12 = L.take<int32_t>(nsd * (nk + 1));
-            o.self12 = L.take<int32_t>(nsd);
-            ubytes[u] += L.off - s0;
-            max_scan = std::max<int64_t>(max_scan, (int64_t)nsd + 1);
-        }
-        uo[u].totals = L.take<int64_t>(4);  // list lengths: l1, l12 of each species
-        uo[u].bytes = ubytes[u];
-    }
-    int64_t R = 0, T = 0;  // T (table offsets) is known once the pair index is built
-    for (int32_t b = 0; b < n_probs; b++) R += ub[which[b]]->dim + 1;
-    max_scan = std::max(max_scan, R);
-    const size_t o_bases = L.take<BasisDev>(n_probs);
-    const size_t o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
-    const size_t o_nnz = L.take<int64_t>(n_probs);
-    const size_t o_queue = L.take<unsigned long long>(1);
-    const size_t o_tile_off = L.take<int64_t>(nblocks + 1);
-    const size_t bytes = L.bytes();
-
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    e = dev_alloc(h->device, bytes, &h->arena, &h->arena_bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(index tables)");
-    char* dev = (char*)h->arena;
+    h->arena = (char*)arena;
+    h->arena_bytes = P->bytes;
+    char* dev = h->arena;
     auto D = [&](size_t off) { return (void*)(dev + off); };
+    const size_t host_bytes = P->host_bytes, pair_start = P->pair_start;
 
-    // host mirror of the host-written tables, then the list lengths, then the
-    // descriptors (pinned)
-    const size_t tot_off = (host_bytes + 255) / 256 * 256;
-    const size_t bd_off = (tot_off + 4 * ub.size() * sizeof(int64_t) + 255) / 256 * 256;
-    char* mirror = pinned_staging(bd_off + n_probs * sizeof(BasisDev));
+    // host mirror of the host-written tables (pinned staging), then the list
+    // lengths read back later
+    char* mirror = pinned_staging(host_bytes);
     if (!mirror) return fail(CI_EHIP, "hipHostMalloc(staging buffer)");
     auto put = [&](size_t off, const void* src, size_t n) {
         if (n) std::memcpy(mirror + off, src, n);
@@ -661,26 +690,27 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     for (size_t u = 0; u < ub.size(); u++) {
         const HostBasis& hb = *ub[u];
         for (int sidx = 0; sidx < 2; sidx++) {
-            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
+            if (P->canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
             const HostSpecies& sp = hb.sp[sidx];
-            const SpOff& o = uo[u].sp[sidx];
+            const SpOff& o = P->uo[u].sp[sidx];
             put(o.sd, sp.sd.data(), sp.sd.size() * 8);
             {
                 const int64_t nsd = sp.nsd();
-                uint64_t* T = (uint64_t*)(mirror + o.sdT);
+                uint64_t* Tw = (uint64_t*)(mirror + o.sdT);
                 for (int64_t x = 0; x < nsd; x++)
-                    for (int w = 0; w < hb.W; w++) T[(int64_t)w * nsd + x] = sp.sd[x * hb.W + w];
+                    for (int w = 0; w < hb.W; w++) Tw[(int64_t)w * nsd + x] = sp.sd[x * hb.W + w];
             }
             put(o.sd_key, sp.sd_key.data(), sp.sd_key.size() * 4);
             put(o.key_off, sp.key_off.data(), sp.key_off.size() * 4);
             put(o.key_nq, sp.key_nq.data(), sp.key_nq.size() * 4);
             put(o.key_m2, sp.key_m2.data(), sp.key_m2.size() * 4);
         }
-        put(uo[u].blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
-        put(uo[u].blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
-        put(uo[u].blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
+        const UOff& U = P->uo[u];
+        put(U.blk_kp, hb.blk_kp.data(), hb.blk_kp.size() * 4);
+        put(U.blk_kn, hb.blk_kn.data(), hb.blk_kn.size() * 4);
+        put(U.blk_off, hb.blk_off.data(), hb.blk_off.size() * 8);
         {
-            BlockInfo* bk = (BlockInfo*)(mirror + uo[u].blk);
+            BlockInfo* bk = (BlockInfo*)(mirror + U.blk);
             for (int k = 0; k < hb.nblk(); k++) {
                 const HostSpecies& N = hb.sp[1];
                 bk[k].kp = hb.blk_kp[k];
@@ -689,165 +719,112 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
                 bk[k].nkn = N.key_off[hb.blk_kn[k] + 1] - N.key_off[hb.blk_kn[k]];
             }
         }
-        put(uo[u].orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
+        put(U.orb_n, hb.orb_n.data(), hb.orb_n.size() * 4);
         {
-            int32_t* q = (int32_t*)(mirror + uo[u].orb_qn);
+            int32_t* q = (int32_t*)(mirror + U.orb_qn);
             for (int o = 0; o < hb.nsps; o++)
                 q[o] = ((hb.orb_n[o] - hb.orb_l[o]) / 2) | (hb.orb_l[o] << 8) | (hb.orb_j2[o] << 16) |
                        ((hb.orb_m2[o] + 64) << 24);
         }
     }
     std::vector<int64_t> first(n_probs), last(n_probs), row0(n_probs + 1, 0);
-    R = 0;
+    int64_t R = 0;
     for (int32_t b = 0; b < n_probs; b++) {
-        const HostBasis& hb = *ub[which[b]];
+        const HostBasis& hb = *ub[P->which[b]];
         first[b] = R;
         last[b] = R + hb.dim;
         row0[b + 1] = row0[b] + hb.dim;
         R += hb.dim + 1;
     }
     {
-        int32_t* bb = (int32_t*)(mirror + o_blk_basis);
-        int32_t* bl = (int32_t*)(mirror + o_blk_local);
+        int32_t* bb = (int32_t*)(mirror + P->o_blk_basis);
+        int32_t* bl = (int32_t*)(mirror + P->o_blk_local);
         int gb = 0;
         for (int32_t b = 0; b < n_probs; b++)
-            for (int k = 0; k < ub[which[b]]->nblk(); k++, gb++) {
+            for (int k = 0; k < ub[P->which[b]]->nblk(); k++, gb++) {
                 bb[gb] = b;
                 bl[gb] = k;
             }
     }
-    put(o_row0, row0.data(), row0.size() * 8);
-    put(o_first, first.data(), first.size() * 8);
-    put(o_last, last.data(), last.size() * 8);
+    put(P->o_row0, row0.data(), row0.size() * 8);
+    put(P->o_first, first.data(), first.size() * 8);
+    put(P->o_last, last.data(), last.size() * 8);
     {
-        std::vector<uint64_t*> out(ub.size());
-        for (size_t u = 0; u < ub.size(); u++) out[u] = (uint64_t*)(mirror + uo[u].pair);
-        pairs.set_targets(out);
+        std::vector<uint64_t*> outp(ub.size());
+        for (size_t u = 0; u < ub.size(); u++) outp[u] = (uint64_t*)(mirror + P->uo[u].pair);
+        P->pairs->set_targets(outp);
     }
-    e = hipMemcpyAsync(h->arena, mirror, pair_start, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(dev, mirror, pair_start, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(index tables)");
 
-    // ---- partner lists on the device: count, scan, read the lengths back
-    auto args = [&](size_t u, int sidx) {
-        const HostSpecies& sp = ub[u]->sp[sidx];
-        const SpOff& o = uo[u].sp[sidx];
-        PartnerArgs a{};
-        a.sd = (const uint64_t*)D(o.sd);
-        a.sdT = (const uint64_t*)D(o.sdT);
-        a.sd_key = (const int32_t*)D(o.sd_key);
-        a.key_off = (const int32_t*)D(o.key_off);
-        a.key_nq = (const int32_t*)D(o.key_nq);
-        a.key_m2 = (const int32_t*)D(o.key_m2);
-        a.l1_ptr = (int64_t*)D(o.l1_ptr);
-        a.l12_ptr = (int64_t*)D(o.l12_ptr);
-        a.seg1 = (int32_t*)D(o.seg1);
-        a.seg12 = (int32_t*)D(o.seg12);
-        a.self12 = (int32_t*)D(o.self12);
-        a.nsd = (int32_t)sp.nsd();
-        a.nk = sp.nk();
-        a.W = ub[u]->W;
-        return a;
-    };
-    int64_t* scan_tmp = (int64_t*)D(o_scan);
+    // what the partner lists need later
+    h->uniq = ub;
+    h->which = P->which;
+    h->canon = P->canon;
+    h->uo = P->uo;
+
+    // ---- partner lists on the device: count and scan (the lengths are read
+    // back by ci_basis_list_bytes)
+    int64_t* scan_tmp = (int64_t*)D(P->o_scan);
     for (size_t u = 0; u < ub.size(); u++)
         for (int sidx = 0; sidx < 2; sidx++) {
-            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
-            PartnerArgs a = args(u, sidx);
+            if (P->canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
+            PartnerArgs a = partner_args(*h, u, sidx);
             if ((e = launch_partner_count(a, s)) != hipSuccess) return hip_fail(e, "partner count");
             // the count pass leaves l*_ptr[0] = 0; the inclusive scan gives offsets
             if ((e = launch_inclusive_scan(a.l1_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess ||
                 (e = launch_inclusive_scan(a.l12_ptr, a.nsd + 1, scan_tmp, s)) != hipSuccess)
                 return hip_fail(e, "partner scan");
-            int64_t* tot = (int64_t*)D(uo[u].totals);
+            int64_t* tot = (int64_t*)D(P->uo[u].totals);
             if ((e = launch_copy_i64(a.l1_ptr + a.nsd, tot + 2 * sidx, s)) != hipSuccess ||
                 (e = launch_copy_i64(a.l12_ptr + a.nsd, tot + 2 * sidx + 1, s)) != hipSuccess)
                 return hip_fail(e, "partner totals");
         }
-    int64_t* tot_pinned = (int64_t*)(mirror + tot_off);
-    for (size_t u = 0; u < ub.size(); u++) {
-        e = hipMemcpyAsync(tot_pinned + 4 * u, D(uo[u].totals), 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(list lengths)");
-    }
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(partner count)");
-    std::vector<int64_t> totals(tot_pinned, tot_pinned + 4 * ub.size());
-    for (int i = 0; i < nsp; i++) {
-        const int c = canon[i];
-        totals[2 * i] = totals[2 * c];
-        totals[2 * i + 1] = totals[2 * c + 1];
-    }
-
-    // ---- allocation 2: the partner lists; fill them
-    Layout LL;
-    std::vector<size_t> lo1(2 * ub.size()), lo12(2 * ub.size());
-    for (int i = 0; i < nsp; i++) {
-        if (canon[i] != i) {
-            lo1[i] = lo1[canon[i]];
-            lo12[i] = lo12[canon[i]];
-            continue;
-        }
-        lo1[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i], 1));
-        lo12[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i + 1], 1));
-    }
-    e = dev_alloc(h->device, LL.bytes(), &h->lists, &h->list_bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(partner lists)");
-    char* ldev = (char*)h->lists;
-    for (size_t u = 0; u < ub.size(); u++)
-        for (int sidx = 0; sidx < 2; sidx++) {
-            if (canon[2 * u + sidx] != (int)(2 * u + sidx)) continue;
-            PartnerArgs a = args(u, sidx);
-            a.l1 = (uint64_t*)(ldev + lo1[2 * u + sidx]);
-            a.l12 = (uint64_t*)(ldev + lo12[2 * u + sidx]);
-            if ((e = launch_partner_fill(a, totals[4 * u + 2 * sidx], totals[4 * u + 2 * sidx + 1], s)) != hipSuccess)
-                return hip_fail(e, "partner fill");
-        }
-    // two-body pair indexes (helper thread) while the partner lists fill
+    // two-body pair indexes (helper thread) while the partner lists are counted
     {
         size_t bad = 0;
-        const int rc = pairs.wait(&bad, err);
-        if (rc != CI_OK) {
-            (void)hipStreamSynchronize(s);
-            return fail(rc, "problem " + std::to_string(bad) + ": " + err);
-        }
+        const int rc = P->pairs->wait(&bad, err);
+        if (rc != CI_OK) return fail(rc, "problem " + std::to_string(bad) + ": " + err);
     }
     // its upload (1.4 MB for 6Li Nmax = 6, tens of microseconds over PCIe)
     // overlaps the partner-list kernels; the stream waits for it before the
     // row kernels that read it
     e = copy_beside(dev + pair_start, mirror + pair_start, host_bytes - pair_start, s, h->device);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(pair index)");
+    e = staging_fence(s, h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
 
-    // ---- per-problem descriptors
-    std::vector<BasisDev> bd(n_probs);
+    // ---- per-problem descriptors (uploaded with the partner lists)
+    h->bd.assign(n_probs, BasisDev{});
     R = 0;
-    T = 0;
+    int64_t T = 0;
     h->info.resize(n_probs);
     for (int32_t b = 0; b < n_probs; b++) {
-        const size_t u = (size_t)which[b];
+        const size_t u = (size_t)P->which[b];
         const HostBasis& hb = *ub[u];
-        BasisDev& d = bd[b];
+        BasisDev& d = h->bd[b];
         std::memset(&d, 0, sizeof d);
         for (int sidx = 0; sidx < 2; sidx++) {
-            const SpOff& o = uo[u].sp[sidx];
+            const SpOff& o = P->uo[u].sp[sidx];
             SpeciesDev& sd = d.sp[sidx];
             sd.sd = (const uint64_t*)D(o.sd);
             sd.key_off = (const int32_t*)D(o.key_off);
             sd.l1_ptr = (const int64_t*)D(o.l1_ptr);
             sd.l12_ptr = (const int64_t*)D(o.l12_ptr);
-            sd.l1 = (const uint64_t*)(ldev + lo1[2 * u + sidx]);
-            sd.l12 = (const uint64_t*)(ldev + lo12[2 * u + sidx]);
             sd.seg1 = (const int32_t*)D(o.seg1);
             sd.seg12 = (const int32_t*)D(o.seg12);
             sd.self12 = (const int32_t*)D(o.self12);
             sd.nsd = (int32_t)hb.sp[sidx].nsd();
             sd.nk = hb.sp[sidx].nk();
         }
-        d.blk_kp = (const int32_t*)D(uo[u].blk_kp);
-        d.blk_kn = (const int32_t*)D(uo[u].blk_kn);
-        d.blk_off = (const int64_t*)D(uo[u].blk_off);
-        d.blk = (const BlockInfo*)D(uo[u].blk);
-        d.pair = (const uint64_t*)D(uo[u].pair);
-        d.orb_n = (const int32_t*)D(uo[u].orb_n);
-        d.orb_qn = (const int32_t*)D(uo[u].orb_qn);
+        const UOff& U = P->uo[u];
+        d.blk_kp = (const int32_t*)D(U.blk_kp);
+        d.blk_kn = (const int32_t*)D(U.blk_kn);
+        d.blk_off = (const int64_t*)D(U.blk_off);
+        d.blk = (const BlockInfo*)D(U.blk);
+        d.pair = (const uint64_t*)D(U.pair);
+        d.orb_n = (const int32_t*)D(U.orb_n);
+        d.orb_qn = (const int32_t*)D(U.orb_qn);
         d.kinetic = hb.prob.kinetic;
         d.dim = hb.dim;
         d.row0 = R;
@@ -862,43 +839,128 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         fill_info(hb, info[b]);
         info[b].row_ptr_offset = R;
         info[b].tbme_offset = T;
-        int64_t lb = 0;
-        for (int sidx = 0; sidx < 2; sidx++)
-            lb += 8 * (totals[4 * u + 2 * sidx] + totals[4 * u + 2 * sidx + 1]);
-        info[b].index_bytes = (int64_t)uo[u].bytes + lb;
+        info[b].index_bytes = -1;  // known once the lists are counted
+        info[b].arena_bytes = (int64_t)P->bytes;
+        info[b].list_bytes = -1;
         h->info[b] = info[b];
         h->host.push_back(ub[u]);
         R += hb.dim + 1;
         T += hb.n_tbme;
     }
-    std::memcpy(mirror + bd_off, bd.data(), bd.size() * sizeof(BasisDev));
-    e = hipMemcpyAsync(D(o_bases), mirror + bd_off, bd.size() * sizeof(BasisDev), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
-    e = staging_fence(s, h->device);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
-    h->d_bases = (BasisDev*)D(o_bases);
-    h->d_basis_row0 = (int64_t*)D(o_row0);
-    h->d_seg_first = (int64_t*)D(o_first);
-    h->d_seg_last = (int64_t*)D(o_last);
+    h->d_bases = (BasisDev*)D(P->o_bases);
+    h->d_basis_row0 = (int64_t*)D(P->o_row0);
+    h->d_seg_first = (int64_t*)D(P->o_first);
+    h->d_seg_last = (int64_t*)D(P->o_last);
     h->d_scan_tmp = scan_tmp;
-    h->d_nnz = (int64_t*)D(o_nnz);
-    h->d_queue = (unsigned long long*)D(o_queue);
-    h->d_blk_basis = (int32_t*)D(o_blk_basis);
-    h->d_blk_local = (int32_t*)D(o_blk_local);
-    h->d_tile_off = (int64_t*)D(o_tile_off);
-    h->nblocks = nblocks;
+    h->d_nnz = (int64_t*)D(P->o_nnz);
+    h->d_queue = (unsigned long long*)D(P->o_queue);
+    h->d_blk_basis = (int32_t*)D(P->o_blk_basis);
+    h->d_blk_local = (int32_t*)D(P->o_blk_local);
+    h->d_tile_off = (int64_t*)D(P->o_tile_off);
+    h->nblocks = P->nblocks;
     h->probs.assign(probs, probs + n_probs);
     h->tune = cached_tuning(h->probs);
     h->nrows = row0[n_probs];
     h->n_rowptr = R;
     h->n_tbme = T;
-    // the partner lists are still being filled on the stream: later work on
-    // it is ordered after them
+    // the partner lists are still being counted on the stream
     *out = h.release();
     return CI_OK;
 }
 
+int ci_basis_list_bytes(ci_basis* b, size_t* bytes, ci_stream stream)
+{
+    if (!b || !bytes) return fail(CI_EINVAL, "null pointer");
+    if (!b->lists_counted) {
+        hipStream_t s = (hipStream_t)stream;
+        const size_t nu = b->uniq.size();
+        int64_t* pin = pinned_counts(4 * nu);
+        if (!pin) return fail(CI_EHIP, "hipHostMalloc(counts)");
+        for (size_t u = 0; u < nu; u++) {
+            hipError_t e = hipMemcpyAsync(pin + 4 * u, b->arena + b->uo[u].totals, 4 * sizeof(int64_t),
+                                          hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(list lengths)");
+        }
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(partner count)");
+        std::vector<int64_t> totals(pin, pin + 4 * nu);
+        const int nsp = 2 * (int)nu;
+        for (int i = 0; i < nsp; i++) {
+            const int c = b->canon[i];
+            totals[2 * i] = totals[2 * c];
+            totals[2 * i + 1] = totals[2 * c + 1];
+        }
+        Layout LL;
+        b->lo1.assign(nsp, 0);
+        b->lo12.assign(nsp, 0);
+        for (int i = 0; i < nsp; i++) {
+            if (b->canon[i] != i) {
+                b->lo1[i] = b->lo1[b->canon[i]];
+                b->lo12[i] = b->lo12[b->canon[i]];
+                continue;
+            }
+            b->lo1[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i], 1));
+            b->lo12[i] = LL.take<uint64_t>(std::max<int64_t>(totals[2 * i + 1], 1));
+        }
+        b->totals = totals;
+        b->list_bytes = LL.bytes();
+        for (size_t p = 0; p < b->info.size(); p++) {
+            const size_t u = (size_t)b->which[p];
+            int64_t lb = 0;
+            for (int sidx = 0; sidx < 2; sidx++) lb += 8 * (totals[4 * u + 2 * sidx] + totals[4 * u + 2 * sidx + 1]);
+            b->info[p].index_bytes = (int64_t)b->uo[u].bytes + lb;
+            b->info[p].list_bytes = (int64_t)b->list_bytes;
+        }
+        b->lists_counted = true;
+    }
+    *bytes = b->list_bytes;
+    return CI_OK;
+}
+
+int ci_basis_build_lists(ci_basis* b, void* lists, size_t bytes, ci_stream stream)
+{
+    if (!b || !lists) return fail(CI_EINVAL, "null pointer");
+    if (!b->lists_counted) return fail(CI_EINVAL, "the lists are not counted yet (ci_basis_list_bytes)");
+    if (b->ready) return fail(CI_EINVAL, "the partner lists of this basis are already built");
+    if (bytes < b->list_bytes)
+        return fail(CI_ESPACE, "the partner lists need " + std::to_string(b->list_bytes) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    char* ldev = (char*)lists;
+    hipError_t e = hipSuccess;
+    for (size_t u = 0; u < b->uniq.size(); u++)
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const int i = 2 * (int)u + sidx;
+            if (b->canon[i] != i) continue;
+            PartnerArgs a = partner_args(*b, u, sidx);
+            a.l1 = (uint64_t*)(ldev + b->lo1[i]);
+            a.l12 = (uint64_t*)(ldev + b->lo12[i]);
+            if ((e = launch_partner_fill(a, b->totals[2 * i], b->totals[2 * i + 1], s)) != hipSuccess)
+                return hip_fail(e, "partner fill");
+        }
+    // descriptors with the list pointers, one copy out of the staging buffer
+    const size_t n = b->bd.size();
+    for (size_t p = 0; p < n; p++) {
+        const size_t u = (size_t)b->which[p];
+        for (int sidx = 0; sidx < 2; sidx++) {
+            const int i = 2 * (int)u + sidx;
+            b->bd[p].sp[sidx].l1 = (const uint64_t*)(ldev + b->lo1[i]);
+            b->bd[p].sp[sidx].l12 = (const uint64_t*)(ldev + b->lo12[i]);
+        }
+    }
+    char* mirror = pinned_staging(n * sizeof(BasisDev));
+    if (!mirror) return fail(CI_EHIP, "hipHostMalloc(staging buffer)");
+    std::memcpy(mirror, b->bd.data(), n * sizeof(BasisDev));
+    e = hipMemcpyAsync(b->d_bases, mirror, n * sizeof(BasisDev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
+    e = staging_fence(s, b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
+    b->lists = ldev;
+    b->ready = true;
+    return CI_OK;
+}
+
 void ci_basis_free(ci_basis* b) { delete b; }
+
 
 int32_t ci_basis_count(const ci_basis* b) { return b ? (int32_t)b->info.size() : 0; }
 
@@ -913,6 +975,7 @@ int ci_basis_get_info(const ci_basis* b, int32_t prob, ci_basis_info* info)
 static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int full, hipStream_t s)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
     const int n = (int)b->info.size();
     hipError_t e = launch_count(b->d_bases, n, b->d_basis_row0, b->nrows, row_ptr, b->n_rowptr, b->d_seg_first,
                                 b->d_scan_tmp, b->tune, b->d_queue, full, s);
@@ -932,7 +995,9 @@ static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int ful
 static int fill_impl(const ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
                      uint32_t* keys, int full, hipStream_t s)
 {
-    if (!b || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !row_ptr) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
+    if (!tbme && b->n_tbme > 0) return fail(CI_EINVAL, "null pointer");
     hipError_t e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr,
                                b->n_rowptr, col, val, keys, b->tune, b->d_queue, full, s);
     if (e != hipSuccess) return hip_fail(e, "fill launch");
@@ -1054,6 +1119,7 @@ static std::vector<int> h3_words(const ci_basis* b)
 static int h3_count_impl(ci_basis* b, int64_t* row_ptr, int64_t* nnz, int full, ci_stream stream)
 {
     if (!b || !row_ptr || !nnz) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
     if (int rc = h3_check(b)) return rc;
     hipStream_t s = (hipStream_t)stream;
     if (int rc = h3_build_index(b, s)) return rc;
@@ -1080,8 +1146,10 @@ static int h3_count_impl(ci_basis* b, int64_t* row_ptr, int64_t* nnz, int full, 
 static int h3_fill_impl(ci_basis* b, const float* tbme, const ci_v3* v3, const int64_t* row_ptr, int32_t* col,
                         float* val, int full, ci_stream stream)
 {
-    if (!b || !v3 || !row_ptr || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !v3 || !row_ptr) return fail(CI_EINVAL, "null pointer");
     if (v3->kind < CI_V3_NONE || v3->kind > CI_V3_IDENTITY) return fail(CI_EINVAL, "unknown three-body kind");
+    if (int rc = need_ready(b)) return rc;
+    if (!tbme && b->n_tbme > 0) return fail(CI_EINVAL, "null pointer");
     if (int rc = h3_check(b)) return rc;
     if (int rc = h3_build_index(b, (hipStream_t)stream)) return rc;
     const std::vector<int64_t> dims = h3_dims(b);
@@ -1150,7 +1218,9 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
                        void* work, size_t work_bytes, ci_stream stream)
 {
     // every row stores its diagonal, so grad_val may be null only without rows
-    if (!b || !row_ptr || (!grad_val && b->nrows > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !row_ptr) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
+    if (!grad_val && b->nrows > 0) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
@@ -1162,7 +1232,9 @@ int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* g
 int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uint32_t* keys, const float* grad_val,
                             float* grad_tbme, void* work, size_t work_bytes, ci_stream stream)
 {
-    if (!b || !row_ptr || ((!grad_val || !keys) && b->nrows > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !row_ptr) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
+    if ((!grad_val || !keys) && b->nrows > 0) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (!keys_fit(b)) return fail(CI_EUNSUPPORTED, "two-body table too large for the stored words");
     if (work_bytes < ci_vjp_work_bytes(b))
@@ -1200,7 +1272,9 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                         const float* grad_val, float* grad_tbme, void* work, size_t work_bytes, int32_t reps,
                         ci_stream stream)
 {
-    if (!b || !row_ptr || !grad_val || (!tbme && b->n_tbme > 0)) return fail(CI_EINVAL, "null pointer");
+    if (!b || !row_ptr || !grad_val) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
+    if (!tbme && b->n_tbme > 0) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (reps < 1) return fail(CI_EINVAL, "reps must be >= 1");
     if (work_bytes < ci_vjp_work_bytes(b))

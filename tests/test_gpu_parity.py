@@ -74,6 +74,63 @@ def run_forward(ci, problems, seeds):
     return b, row_ptr.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), tb
 
 
+def test_build_into_torch_memory_through_the_c_abi(ci):
+    # The two-body path allocates no device memory: the index tables go into
+    # an arena and the partner lists into a second buffer, both torch tensors
+    # (filled with 0xFF first, so nothing may rely on their contents), sized
+    # by the size query and by ci_basis_list_bytes.  The matrix built that way
+    # equals the oracle's; calls before the lists exist are refused.
+    import ctypes
+
+    import torch
+
+    L = ci.load_library()
+    probs = [(2, 2, 4, 0, 1), (3, 2, 2, 1, 1)]
+    say("raw build", probs)
+    arr, n = ci._problems(probs)
+    info = (ci.ci_basis_info * n)()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.ci_basis_build(arr, n, info, None, 0, None, s) == ci.CI_OK
+    need = int(info[0].arena_bytes)
+    arena = torch.full((need,), 255, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    assert L.ci_basis_build(arr, n, info, ctypes.c_void_p(arena.data_ptr()), need - 256, ctypes.byref(h), s) \
+        == ci.CI_ESPACE
+    assert L.ci_basis_build(arr, n, info, ctypes.c_void_p(arena.data_ptr()), need, ctypes.byref(h), s) == ci.CI_OK
+    rows = sum(info[k].dim + 1 for k in range(n))
+    rp = torch.empty(rows, dtype=torch.int64, device="cuda")
+    nnz = np.zeros(n, np.int64)
+    assert L.ci_hamiltonian_count(h, ctypes.c_void_p(rp.data_ptr()), nnz.ctypes.data_as(ctypes.c_void_p), s) \
+        == ci.CI_EINVAL  # no partner lists yet
+    lb = ctypes.c_size_t()
+    assert L.ci_basis_list_bytes(h, ctypes.byref(lb), s) == ci.CI_OK
+    lists = torch.full((int(lb.value),), 255, dtype=torch.uint8, device="cuda")
+    assert L.ci_basis_build_lists(h, ctypes.c_void_p(lists.data_ptr()), int(lb.value) - 8, s) == ci.CI_ESPACE
+    assert L.ci_basis_build_lists(h, ctypes.c_void_p(lists.data_ptr()), int(lb.value), s) == ci.CI_OK
+    assert L.ci_hamiltonian_count(h, ctypes.c_void_p(rp.data_ptr()), nnz.ctypes.data_as(ctypes.c_void_p), s) \
+        == ci.CI_OK
+    ntb = sum(info[k].n_tbme for k in range(n))
+    seeds = [5, 6]
+    tb = torch.from_numpy(np.concatenate([si.tbme_f32(sd, info[k].n_tbme) for k, sd in enumerate(seeds)])).cuda()
+    assert tb.numel() == ntb
+    col = torch.empty(int(nnz.sum()), dtype=torch.int32, device="cuda")
+    val = torch.empty(int(nnz.sum()), dtype=torch.float32, device="cuda")
+    assert L.ci_hamiltonian_fill(h, ctypes.c_void_p(tb.data_ptr()), ctypes.c_void_p(rp.data_ptr()),
+                                 ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()), s) == ci.CI_OK
+    torch.cuda.synchronize()
+    L.ci_basis_free(h)
+    rpc, colc, valc = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    for k, (p, sd) in enumerate(zip(probs, seeds)):
+        r0 = int(info[k].row_ptr_offset)
+        r = rpc[r0: r0 + info[k].dim + 1]
+        o = Oracle(Problem(*p))
+        o.set_tbme(si.tbme_f32(sd, o.n_tbme).astype(np.float64))
+        rpo, co, vo = o.csr()
+        assert np.array_equal(r - r[0], rpo)
+        assert np.array_equal(colc[r[0]: r[-1]], co)
+        assert np.abs(valc[r[0]: r[-1]].astype(np.float64) - vo).max() <= VAL_TOL * np.abs(vo).max()
+
+
 def split(b, rp, col, val, k):
     i = b.info[k]
     r = rp[i["row_ptr_offset"]: i["row_ptr_offset"] + i["dim"] + 1]

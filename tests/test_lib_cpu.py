@@ -107,6 +107,32 @@ def test_argument_errors_before_any_device_call():
     assert L.ci_vjp_work_bytes(None) == 0 and L.ci_basis_count(None) == 0
 
 
+def test_build_size_query_is_host_only():
+    # arena = NULL: the size query plans on the host and needs no device; a
+    # short arena is refused before any device call (the placeholder address
+    # is never touched), and so are the list calls without a handle
+    L = ci.load_library()
+    c = ci.ctypes
+    for probs in ([(3, 3, 6, 2, 1)], [(2, 2, 2, 0, 1), (2, 3, 4, 1, 1), (2, 2, 2, 0, 1)]):
+        arr, n = ci._problems(probs)
+        info = (ci.ci_basis_info * n)()
+        assert L.ci_basis_build(arr, n, info, None, 0, None, None) == ci.CI_OK
+        need = info[0].arena_bytes
+        assert need > 0 and all(info[k].arena_bytes == need for k in range(n))
+        assert all(info[k].n_tbme == -1 and info[k].list_bytes == -1 for k in range(n))
+        plan = ci.ci_basis_plan(probs)
+        for k in range(n):
+            assert info[k].dim == plan[k]["dim"] and info[k].n_blocks == plan[k]["n_blocks"]
+            assert plan[k]["arena_bytes"] == need
+        h = c.c_void_p()
+        assert L.ci_basis_build(arr, n, info, c.c_void_p(256), need - 1, c.byref(h), None) == ci.CI_ESPACE
+        assert not h.value
+        assert str(need) in L.ci_last_error().decode()
+    sz = c.c_size_t()
+    assert L.ci_basis_list_bytes(None, c.byref(sz), None) == ci.CI_EINVAL
+    assert L.ci_basis_build_lists(None, None, 0, None) == ci.CI_EINVAL
+
+
 def test_kinetic_flag_validation():
     with pytest.raises(ci.CIError) as e:
         ci.ci_basis_plan([(2, 2, 2, 0, 1, ci.HW_MEV, 2)])
