@@ -359,10 +359,11 @@ def run_batched(ci, torch, steps, warmup, stored, tuning_text=None):
     if tuning_text:
         b.tuning = parse_tuning(tuning_text)
         tuning = b.tuning
-    else:
-        tuning = ci.ci_hamiltonian_tune(b, tb, rp, col, val, G, gt, work, reps=2)
-    t_tune = time.perf_counter() - t0
     keys = torch.empty(tot if stored else 0, dtype=torch.int32, device="cuda")
+    if not tuning_text:
+        tuning = ci.ci_hamiltonian_tune(b, tb, rp, col, val, G, gt, None, reps=2, keys=keys if stored else None)
+    t_tune = time.perf_counter() - t0
+    work = torch.empty(max(b.vjp_work_bytes(), 8), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
 
     def one():
@@ -429,7 +430,8 @@ def leg(ms, nnz, alg_bytes, profile):
 
 
 def parse_tuning(text):
-    keys = ("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows", "adjk_tile_n")
+    keys = ("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows", "adjk_tile_n",
+            "adjk_persistent")
     if "=" in text:
         return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
     return dict(zip(keys, (int(x) for x in text.split(","))))
@@ -469,9 +471,12 @@ def measure_step(ci, torch, workload, steps, warmup, adjoint, tuning_text):
         b.tuning = fixed
         tuning = b.tuning
     else:
-        tuning = ci.ci_hamiltonian_tune(b, tbme, rp, col, val, G, gt, work, reps=3)
+        kt = torch.empty(nnz, dtype=torch.int32, device="cuda") if adjoint == "stored" else None
+        tuning = ci.ci_hamiltonian_tune(b, tbme, rp, col, val, G, gt, None, reps=3, keys=kt)
+        del kt
     t_tune = time.perf_counter() - t0
     log("launch shapes", tuning, "in %.2f s" % t_tune)
+    work = torch.empty(max(b.vjp_work_bytes(), 8), dtype=torch.uint8, device="cuda")
     b.free()
     del col, val
     col = torch.empty(nnz, dtype=torch.int32, device="cuda")

@@ -134,6 +134,7 @@ typedef struct {
     int32_t adj_persistent; /* adjoint: 0 one workgroup per tile, 1 persistent workgroups */
     int32_t adjk_rows;      /* adjoint from stored words: target rows per tile, 1..4096 */
     int32_t adjk_tile_n;    /* adjoint from stored words: neutron determinants per tile, 1..4096 */
+    int32_t adjk_persistent; /* adjoint from stored words: 0 one workgroup per tile, 1 persistent */
 } ci_tuning;
 
 /* Thread-local text of the last error. */
@@ -295,16 +296,18 @@ size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter);
 size_t ci_vjp_work_bytes(const ci_basis* b);
 
 /* Autotuner (batched construction): times every candidate launch shape of
- * the fill and of the adjoint on the caller's buffers (one warm-up and `reps`
- * timed runs each, with HIP events on `stream`), keeps the fastest in the
- * handle, and remembers it for handles later built from the same problem
- * list in this process.  col, val and grad_tbme end up holding the results of
- * a normal fill / vjp.  Synchronizes the stream; not for use inside graph
- * capture.  CI_EINVAL for null pointers or reps < 1, CI_ESPACE for a short
- * work buffer. */
-int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col,
-                        float* val, const float* grad_val, float* grad_tbme, void* work,
-                        size_t work_bytes, int32_t reps, ci_stream stream);
+ * the fill and of both adjoints on the caller's buffers (one warm-up and
+ * `reps` timed runs each, with HIP events on `stream`), keeps the fastest in
+ * the handle, and remembers it for handles later built from the same problem
+ * list in this process.  keys (device uint32 [nnz], may be NULL): room for the
+ * stored words; with it the fill writes them once and the shapes of the
+ * adjoint from stored words are tuned as well, else they stay as they are.
+ * col, val (keys) and grad_tbme end up holding the results of a normal fill /
+ * vjp.  Synchronizes the stream; not for use inside graph capture.  CI_EINVAL
+ * for null pointers or reps < 1, CI_ESPACE for a short work buffer. */
+int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
+                        uint32_t* keys, const float* grad_val, float* grad_tbme, void* work, size_t work_bytes,
+                        int32_t reps, ci_stream stream);
 
 /* Current launch shapes of the handle; set them by hand (CI_EINVAL when a
  * field is out of range).  Calls on one handle share its work counter, so

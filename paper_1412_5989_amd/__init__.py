@@ -68,7 +68,7 @@ CI_V3_NONE, CI_V3_SYNTHETIC, CI_V3_IDENTITY = 0, 1, 2
 class ci_tuning(ctypes.Structure):
     _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
                 ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32), ("adjk_rows", ctypes.c_int32),
-                ("adjk_tile_n", ctypes.c_int32)]
+                ("adjk_tile_n", ctypes.c_int32), ("adjk_persistent", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -120,7 +120,7 @@ def load_library():
                              sz, vp]
     L.ci_lanczos_work_bytes.argtypes = [i64, i32]
     L.ci_lanczos_work_bytes.restype = sz
-    L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
+    L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
     L.ci_basis_get_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_basis_set_tuning.argtypes = [vp, P(ci_tuning)]
     L.ci_probe_ceilings.argtypes = [vp, sz, P(ctypes.c_double), P(ctypes.c_double), vp]
@@ -454,7 +454,7 @@ def ci_hamiltonian_vjp(basis: Basis, row_ptr, grad_val, grad_tbme=None, work=Non
     if grad_tbme is None:
         grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
     nwork = basis.vjp_work_bytes()
-    if work is None:
+    if work is None or work.numel() * work.element_size() < nwork:
         work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
     _check(load_library().ci_hamiltonian_vjp(basis.handle, _ptr(row_ptr), _ptr(grad_val), _ptr(grad_tbme),
                                              _ptr(work), work.numel() * work.element_size(),
@@ -495,7 +495,7 @@ def ci_hamiltonian_vjp_keys(basis: Basis, row_ptr, keys, grad_val, grad_tbme=Non
     if grad_tbme is None:
         grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
     nwork = basis.vjp_work_bytes()
-    if work is None:
+    if work is None or work.numel() * work.element_size() < nwork:
         work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
     _check(load_library().ci_hamiltonian_vjp_keys(basis.handle, _ptr(row_ptr), _ptr(keys), _ptr(grad_val),
                                                   _ptr(grad_tbme), _ptr(work), work.numel() * work.element_size(),
@@ -504,10 +504,12 @@ def ci_hamiltonian_vjp_keys(basis: Basis, row_ptr, keys, grad_val, grad_tbme=Non
 
 
 def ci_hamiltonian_tune(basis: Basis, tbme, row_ptr, col, val, grad_val, grad_tbme=None, work=None,
-                        reps: int = 3, stream=None) -> dict:
+                        reps: int = 3, keys=None, stream=None) -> dict:
     """Autotuner: times the launch shapes of fill and adjoint on these buffers,
     keeps the fastest in the handle (and for later handles of the same
-    problems); returns the chosen shapes."""
+    problems); returns the chosen shapes.  keys: an int32 tensor of nnz
+    elements to also tune the adjoint from stored words (it then holds the
+    words), or None."""
     torch = _torch()
     tot = sum(basis.nnz)
     _check_tensor(tbme, torch.float32, basis.n_tbme, "tbme")
@@ -515,12 +517,15 @@ def ci_hamiltonian_tune(basis: Basis, tbme, row_ptr, col, val, grad_val, grad_tb
     _check_tensor(col, torch.int32, tot, "col")
     _check_tensor(val, torch.float32, tot, "val")
     _check_tensor(grad_val, torch.float32, tot, "grad_val")
+    if keys is not None:
+        _check_tensor(keys, torch.int32, tot, "keys")
     if grad_tbme is None:
         grad_tbme = torch.empty(basis.n_tbme, dtype=torch.float32, device=basis.device)
     nwork = basis.vjp_work_bytes()
-    if work is None:
+    if work is None or work.numel() * work.element_size() < nwork:
         work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
     _check(load_library().ci_hamiltonian_tune(basis.handle, _ptr(tbme), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                              _ptr(keys) if keys is not None else None,
                                               _ptr(grad_val), _ptr(grad_tbme), _ptr(work),
                                               work.numel() * work.element_size(), int(reps),
                                               _stream_ptr(stream)))
@@ -628,12 +633,13 @@ def _make_autograd():
     class CIHamiltonian(torch.autograd.Function):
         """val = H(tbme) on a fixed structure; backward runs the adjoint kernel.
 
-        store_keys: the forward also stores one structure word per entry (4
-        bytes each, kept until backward) and the backward reads them instead
-        of walking the partner lists again."""
+        The backward recomputes the pair and phase structure by walking the
+        partner lists again (the default).  store_keys: the forward also
+        stores one structure word per entry (4 bytes each, kept until
+        backward) and the backward reads them instead."""
 
         @staticmethod
-        def forward(ctx, tbme, basis, row_ptr, col=None, store_keys=True):
+        def forward(ctx, tbme, basis, row_ptr, col=None, store_keys=False):
             ctx.basis = basis
             if store_keys:
                 _, val, keys = ci_hamiltonian_fill_keys(basis, tbme.detach().contiguous(), row_ptr, col=col)

@@ -25,10 +25,12 @@ hipError_t launch_nnz(const int64_t* row_ptr, const int64_t* first, const int64_
 hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
                        uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
-hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
-                      int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
-                      const float* gval, const uint32_t* keys, float* gtbme, double* gacc, int64_t ntbme,
-                      const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
+                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets,
+                      int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
+                      float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
+                      int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+int adjoint_slots(bool stored);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
@@ -342,7 +344,7 @@ std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8, 1}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
@@ -389,6 +391,9 @@ struct ci_basis {
     int32_t* d_blk_basis = nullptr;         // global block list of the batch: problem, local block
     int32_t* d_blk_local = nullptr;
     int64_t* d_tile_off = nullptr;          // adjoint tiles per block (inclusive scan), [nblocks + 1]
+    AdjBasis* d_adjb = nullptr;             // per-basis layout of the adjoint's tile records
+    unsigned long long* d_rec_count = nullptr;  // records written by the adjoint's tiles
+    mutable int64_t nnz_total = -1;         // stored entries of all bases (after the upper-triangle count)
     int nblocks = 0;
     ci_tuning tune{};
     std::vector<ci_problem> probs;          // key of the process-wide tuning cache
@@ -419,7 +424,8 @@ struct BuildPlan {
     std::vector<UOff> uo;
     size_t pair_start = 0, host_bytes = 0;
     size_t o_row0 = 0, o_first = 0, o_last = 0, o_blk_basis = 0, o_blk_local = 0;
-    size_t o_bases = 0, o_scan = 0, o_nnz = 0, o_queue = 0, o_tile_off = 0, bytes = 0;
+    size_t o_bases = 0, o_scan = 0, o_nnz = 0, o_queue = 0, o_rec_count = 0, o_tile_off = 0, o_adjb = 0;
+    size_t bytes = 0;
     int nblocks = 0;
 };
 
@@ -551,7 +557,9 @@ int plan_build(const ci_problem* probs, int32_t n_probs, BuildPlan& P, std::stri
     P.o_scan = L.take<int64_t>((max_scan + 4095) / 4096 + 1);
     P.o_nnz = L.take<int64_t>(n_probs);
     P.o_queue = L.take<unsigned long long>(1);
+    P.o_rec_count = L.take<unsigned long long>(1);
     P.o_tile_off = L.take<int64_t>(P.nblocks + 1);
+    P.o_adjb = L.take<AdjBasis>(n_probs);
     P.bytes = L.bytes();
     return CI_OK;
 }
@@ -829,6 +837,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
         d.dim = hb.dim;
         d.row0 = R;
         d.tbme0 = T;
+        d.ntbme = hb.n_tbme;
         d.W = hb.W;
         d.nsps = hb.nsps;
         d.nblk = hb.nblk();
@@ -854,9 +863,11 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     h->d_scan_tmp = scan_tmp;
     h->d_nnz = (int64_t*)D(P->o_nnz);
     h->d_queue = (unsigned long long*)D(P->o_queue);
+    h->d_rec_count = (unsigned long long*)D(P->o_rec_count);
     h->d_blk_basis = (int32_t*)D(P->o_blk_basis);
     h->d_blk_local = (int32_t*)D(P->o_blk_local);
     h->d_tile_off = (int64_t*)D(P->o_tile_off);
+    h->d_adjb = (AdjBasis*)D(P->o_adjb);
     h->nblocks = P->nblocks;
     h->probs.assign(probs, probs + n_probs);
     h->tune = cached_tuning(h->probs);
@@ -989,6 +1000,11 @@ static int count_impl(const ci_basis* b, int64_t* row_ptr, int64_t* nnz, int ful
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(count)");
     std::memcpy(nnz, pin, n * sizeof(int64_t));
+    if (!full) {
+        int64_t tot = 0;
+        for (int p = 0; p < n; p++) tot += nnz[p];
+        b->nnz_total = tot;
+    }
     return CI_OK;
 }
 
@@ -1183,36 +1199,102 @@ int ci_hamiltonian3_fill_full(ci_basis* b, const float* tbme, const ci_v3* v3, c
     return h3_fill_impl(b, tbme, v3, row_ptr, col, val, 1, stream);
 }
 
-// Number of adjoint tiles of the handle for shape t (the device computes the
-// same counts in tile_offsets).
-static int64_t count_tiles(const ci_basis* b, const ci_tuning& t, bool stored)
+// Adjoint tiles of basis p for shape t (the device computes the same counts
+// in tile_offsets).
+static int64_t count_tiles_of(const HostBasis& hb, const ci_tuning& t, bool stored)
 {
     const int64_t rows = stored ? t.adjk_rows : t.adj_rows, tile_n = stored ? t.adjk_tile_n : t.adj_tile_n;
     int64_t n = 0;
-    for (size_t p = 0; p < b->host.size(); p++) {
-        const HostBasis& hb = *b->host[p];
-        for (int bi = 0; bi < hb.nblk(); bi++) {
-            const HostSpecies &P = hb.sp[0], &N = hb.sp[1];
-            const int64_t nKp = P.key_off[hb.blk_kp[bi] + 1] - P.key_off[hb.blk_kp[bi]];
-            const int64_t nKn = N.key_off[hb.blk_kn[bi] + 1] - N.key_off[hb.blk_kn[bi]];
-            const int64_t tn = std::min<int64_t>(tile_n, nKn);
-            const int64_t tp = std::max<int64_t>(1, rows / tn);
-            n += ((nKp + tp - 1) / tp) * ((nKn + tn - 1) / tn);
-        }
+    for (int bi = 0; bi < hb.nblk(); bi++) {
+        const HostSpecies &P = hb.sp[0], &N = hb.sp[1];
+        const int64_t nKp = P.key_off[hb.blk_kp[bi] + 1] - P.key_off[hb.blk_kp[bi]];
+        const int64_t nKn = N.key_off[hb.blk_kn[bi] + 1] - N.key_off[hb.blk_kn[bi]];
+        const int64_t tn = std::min<int64_t>(tile_n, nKn);
+        const int64_t tp = std::max<int64_t>(1, rows / tn);
+        n += ((nKp + tp - 1) / tp) * ((nKn + tn - 1) / tn);
     }
     return n;
+}
+
+// Work buffer of one adjoint launch: FP64 accumulators of the contributions
+// that find no table slot (or no room in the record buffer) [n_tbme], the
+// tile records (uint64: table position | FP32 bits << 32), the per-tile bucket
+// histograms (int64 positions).  The record buffer holds at most as many
+// records as the tiles have slots, and no more than half the stored entries
+// (a tile writes one record per distinct table position it touched: about a
+// quarter to a third of the entries at the tuned shapes; a tile that finds
+// no room adds its sums to the accumulators instead).
+// Without records (histograms beyond kHistCap entries: tiny tiles) the tiles
+// add their sums to the accumulators directly.
+constexpr int64_t kHistCap = (int64_t)1 << 25;
+
+struct VjpLayout {
+    int64_t ntiles = 0, nbuckets = 0, rec_cap = 0;
+    bool records = false;
+    size_t recs = 0, hist = 0, bytes = 0;
+};
+
+static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored)
+{
+    VjpLayout v;
+    int64_t hist = 0;
+    for (size_t p = 0; p < b->host.size(); p++) {
+        const int64_t nt = count_tiles_of(*b->host[p], t, stored);
+        const int nb = adj_buckets(b->info[p].n_tbme);
+        v.ntiles += nt;
+        v.nbuckets += nb;
+        hist += nt * (nb + 1);
+    }
+    v.records = hist <= kHistCap && b->n_tbme < 0xffffffffLL;
+    Layout L;
+    (void)L.take<double>((size_t)b->n_tbme);
+    if (v.records) {
+        v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored);
+        if (b->nnz_total >= 0) v.rec_cap = std::min<int64_t>(v.rec_cap, b->nnz_total / 2 + 1);
+        v.recs = L.take<uint64_t>((size_t)v.rec_cap);
+        v.hist = L.take<int64_t>((size_t)std::max<int64_t>(hist, 1));
+    }
+    v.bytes = L.bytes();
+    return v;
+}
+
+// Launch shapes the autotuner tries for the adjoint (tile rows, neutron width).
+static const int kWalkTiles[][2] = {{32, 4}, {32, 8}, {64, 8}, {64, 16}, {128, 8}, {128, 16}};
+static const int kStoredTiles[][2] = {{64, 8}, {96, 8}, {128, 8}, {96, 16}, {192, 8}, {256, 16}};
+
+static size_t work_bytes_for(const ci_basis* b)
+{
+    size_t w = std::max(vjp_layout(b, b->tune, false).bytes, vjp_layout(b, b->tune, true).bytes);
+    ci_tuning t = b->tune;
+    for (const auto& tl : kWalkTiles) {
+        t.adj_rows = tl[0];
+        t.adj_tile_n = tl[1];
+        w = std::max(w, vjp_layout(b, t, false).bytes);
+    }
+    t = b->tune;
+    for (const auto& tl : kStoredTiles) {
+        t.adjk_rows = tl[0];
+        t.adjk_tile_n = tl[1];
+        w = std::max(w, vjp_layout(b, t, true).bytes);
+    }
+    return w;
 }
 
 static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
                              void* work, const ci_tuning& t, hipStream_t s, const uint32_t* keys = nullptr)
 {
-    return launch_vjp(b->d_bases, b->d_blk_basis, b->d_blk_local, b->nblocks, count_tiles(b, t, keys != nullptr),
-                      b->d_tile_off,
-                      b->nrows, row_ptr, b->n_rowptr, grad_val, keys, grad_tbme, (double*)work, b->n_tbme, t,
-                      b->d_queue, s);
+    const bool stored = keys != nullptr;
+    const VjpLayout v = vjp_layout(b, t, stored);
+    char* w = (char*)work;
+    ci_tuning tt = t;
+    if (stored) tt.adj_persistent = t.adjk_persistent;
+    return launch_vjp(b->d_bases, (int)b->info.size(), b->d_blk_basis, b->d_blk_local, b->nblocks, v.ntiles,
+                      b->d_tile_off, b->d_adjb, v.nbuckets, b->nrows, row_ptr, b->n_rowptr, grad_val, keys,
+                      grad_tbme, (double*)w, v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap,
+                      b->d_rec_count, v.records ? (int64_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, s);
 }
 
-size_t ci_vjp_work_bytes(const ci_basis* b) { return b ? (size_t)b->n_tbme * sizeof(double) : 0; }
+size_t ci_vjp_work_bytes(const ci_basis* b) { return (b && b->ready) ? work_bytes_for(b) : 0; }
 
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
                        void* work, size_t work_bytes, ci_stream stream)
@@ -1249,7 +1331,7 @@ static bool tuning_ok(const ci_tuning& t)
     return (t.row_waves == 4 || t.row_waves == 8) && t.row_grab >= 0 && t.row_grab <= 4096 && t.adj_rows >= 1 &&
            t.adj_rows <= 4096 && t.adj_tile_n >= 1 && t.adj_tile_n <= 4096 &&
            (t.adj_persistent == 0 || t.adj_persistent == 1) && t.adjk_rows >= 1 && t.adjk_rows <= 4096 &&
-           t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096;
+           t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096 && (t.adjk_persistent == 0 || t.adjk_persistent == 1);
 }
 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
@@ -1269,14 +1351,15 @@ int ci_basis_set_tuning(ci_basis* b, const ci_tuning* t)
 
 
 int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, int32_t* col, float* val,
-                        const float* grad_val, float* grad_tbme, void* work, size_t work_bytes, int32_t reps,
-                        ci_stream stream)
+                        uint32_t* keys, const float* grad_val, float* grad_tbme, void* work, size_t work_bytes,
+                        int32_t reps, ci_stream stream)
 {
     if (!b || !row_ptr || !grad_val) return fail(CI_EINVAL, "null pointer");
     if (int rc = need_ready(b)) return rc;
     if (!tbme && b->n_tbme > 0) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && (!grad_tbme || !work)) return fail(CI_EINVAL, "null pointer");
     if (reps < 1) return fail(CI_EINVAL, "reps must be >= 1");
+    if (keys && !keys_fit(b)) return fail(CI_EUNSUPPORTED, "two-body table too large for the stored words");
     if (work_bytes < ci_vjp_work_bytes(b))
         return fail(CI_ESPACE, "vjp work buffer needs " + std::to_string(ci_vjp_work_bytes(b)) + " bytes");
     hipStream_t s = (hipStream_t)stream;
@@ -1312,10 +1395,9 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                 have = true;
             }
         }
-    // adjoint: tile (rows, neutron width) x (grid, persistent)
+    // adjoint that walks the partner lists: tile (rows, neutron width) x (grid, persistent)
     have = false;
-    const int tiles[][2] = {{32, 32}, {32, 8}, {32, 4}, {64, 16}, {64, 8}};
-    for (const auto& tl : tiles)
+    for (const auto& tl : kWalkTiles)
         for (int pers : {0, 1}) {
             if (rc != CI_OK) break;
             b->tune = best;
@@ -1333,6 +1415,33 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
                 have = true;
             }
         }
+    // adjoint from stored words (when the caller gives room for them): the
+    // fill writes the words once, then its own tiles x (grid, persistent)
+    if (keys && rc == CI_OK) {
+        b->tune = best;
+        e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
+                        val, keys, b->tune, b->d_queue, 0, s);
+        if (e != hipSuccess) rc = hip_fail(e, "autotune fill with stored words");
+        have = false;
+        for (const auto& tl : kStoredTiles)
+            for (int pers : {0, 1}) {
+                if (rc != CI_OK) break;
+                b->tune = best;
+                b->tune.adjk_rows = tl[0];
+                b->tune.adjk_tile_n = tl[1];
+                b->tune.adjk_persistent = pers;
+                float ms = 0.0f;
+                rc = time_ms([&] { return vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s, keys); }, reps,
+                             s, e0, e1, &ms);
+                if (rc == CI_OK && (!have || ms < best_ms)) {
+                    best_ms = ms;
+                    best.adjk_rows = tl[0];
+                    best.adjk_tile_n = tl[1];
+                    best.adjk_persistent = pers;
+                    have = true;
+                }
+            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != CI_OK) {
@@ -1341,9 +1450,9 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     }
     b->tune = best;
     remember_tuning(b->probs, best);
-    // leave col / val / grad_tbme as the chosen shapes compute them
+    // leave col / val (/ keys) / grad_tbme as the chosen shapes compute them
     e = launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme, row_ptr, b->n_rowptr, col,
-                    val, nullptr, b->tune, b->d_queue, 0, s);
+                    val, keys, b->tune, b->d_queue, 0, s);
     if (e == hipSuccess) e = vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "autotune final run");

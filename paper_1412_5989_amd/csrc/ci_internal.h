@@ -81,11 +81,42 @@ struct BasisDev {
     int64_t dim;               // D
     int64_t row0;              // R_b: this basis' segment of row_ptr
     int64_t tbme0;             // T_b: this basis' slice of the two-body table
+    int64_t ntbme;             // length of this basis' table
     int32_t W, nsps, nblk, nsec, Z, NN;
     int32_t kinetic;           // off-diagonal oscillator kinetic term in the one-body part
     double hw;
 };
 
+
+// Adjoint: the table positions of one basis are cut into buckets of 2^bits
+// consecutive positions (bits >= kAdjBucketMinBits, chosen so that a basis has
+// at most kAdjMaxBuckets buckets).  Every adjoint tile writes the partial sums
+// of its shared-memory table as (position, value) records grouped by bucket,
+// and a histogram row of nb + 1 offsets; one workgroup per bucket then sums
+// the records of every tile of its basis.  Per basis, for one launch shape
+// (tile_offsets computes it on the device, the host the same sizes):
+struct AdjBasis {
+    int64_t tile0;    // first tile of the basis (global tile index)
+    int64_t ntiles;   // tiles of the basis
+    int64_t hist0;    // first histogram entry of the basis (ntiles rows of nb + 1)
+    int64_t bucket0;  // first bucket of the basis (global bucket index)
+    int32_t nb;       // buckets of the basis
+    int32_t bits;     // log2 of the positions per bucket
+};
+constexpr int kAdjBucketMinBits = 13;  // the reducing workgroup sums 2^13 positions at a time
+constexpr int kAdjMaxBuckets = 1024;
+
+CI_HD inline int adj_bucket_bits(int64_t ntbme)
+{
+    int bits = kAdjBucketMinBits;
+    while (((ntbme + ((int64_t)1 << bits) - 1) >> bits) > kAdjMaxBuckets) bits++;
+    return bits;
+}
+CI_HD inline int adj_buckets(int64_t ntbme)
+{
+    const int bits = adj_bucket_bits(ntbme);
+    return (int)((ntbme + ((int64_t)1 << bits) - 1) >> bits);
+}
 
 // ---------------------------------------------------------------------------
 // Host-side tables of one basis.

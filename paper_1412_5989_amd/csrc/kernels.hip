@@ -824,7 +824,8 @@ __device__ __forceinline__ void block_tile_shape(int nKp, int nKn, int rows, int
 __global__ void __launch_bounds__(256) tile_offsets(const BasisDev* __restrict__ bases,
                                                     const int32_t* __restrict__ blk_basis,
                                                     const int32_t* __restrict__ blk_local, int nblocks, int rows,
-                                                    int tile_n, int64_t* __restrict__ tile_off)
+                                                    int tile_n, int64_t* __restrict__ tile_off, int nbases,
+                                                    AdjBasis* __restrict__ adjb)
 {
     __shared__ int64_t part[4];
     int64_t carry = 0;
@@ -857,34 +858,65 @@ __global__ void __launch_bounds__(256) tile_offsets(const BasisDev* __restrict__
         carry += part[0] + part[1] + part[2] + part[3];
         __syncthreads();
     }
+    // per-basis layout of the tile records: the blocks of a basis are
+    // consecutive in the global block list, so are its tiles
+    if (adjb && threadIdx.x == 0) {
+        int blk0 = 0;
+        int64_t hist0 = 0, bucket0 = 0;
+        for (int x = 0; x < nbases; x++) {
+            const BasisDev& B = bases[x];
+            AdjBasis a;
+            a.tile0 = tile_off[blk0];
+            a.ntiles = tile_off[blk0 + B.nblk] - a.tile0;
+            a.hist0 = hist0;
+            a.bucket0 = bucket0;
+            a.bits = adj_bucket_bits(B.ntbme);
+            a.nb = adj_buckets(B.ntbme);
+            adjb[x] = a;
+            blk0 += B.nblk;
+            hist0 += a.ntiles * (a.nb + 1);
+            bucket0 += a.nb;
+        }
+    }
 }
 
 // Adjoint: a workgroup takes one tile of rows (above), its wavefronts take
 // the tile's rows one at a time from a shared counter, and the contributions
-// meet in the LDS accumulator table, which is added to the FP64 accumulator
-// and cleared when the tile is done.  persistent == 0: tile = workgroup
-// index; persistent == 1: a persistent grid takes tiles from the work counter
-// *queue (zero at launch).  use_table == 0 (global table positions do not fit
-// 32 bits): every contribution goes to the accumulator.
+// meet in the LDS accumulator table.  When the tile is done its occupied slots
+// are written out as (table position, FP32 partial sum) records, grouped by
+// bucket of the basis' table (a histogram row per tile gives each bucket's
+// segment), with plain stores; adjoint_reduce sums them.  No device-scope
+// atomic is issued except for a contribution that finds no slot within
+// kAdjProbes probes (it goes to the FP64 accumulator gacc directly).
+// persistent == 0: tile = workgroup index; persistent == 1: a persistent grid
+// takes tiles from the work counter *queue (zero at launch).  use_table == 0
+// (global table positions do not fit 32 bits): every contribution goes to
+// gacc and no record is written.
 template <int WAVES, int SLOT_BITS>
 __global__ void __launch_bounds__(64 * WAVES)
     adjoint_kernel(const BasisDev* __restrict__ bases, const int32_t* __restrict__ blk_basis,
                    const int32_t* __restrict__ blk_local, int nblocks, const int64_t* __restrict__ tile_off,
                    int rows, int tile_n, const int64_t* __restrict__ row_ptr, int64_t nrp,
                    const float* __restrict__ gval, const uint32_t* __restrict__ keys, double* __restrict__ gacc,
-                   int use_table, int persistent, unsigned long long* __restrict__ queue)
+                   int use_table, int persistent, unsigned long long* __restrict__ queue,
+                   const AdjBasis* __restrict__ adjb, uint64_t* __restrict__ recs, int64_t rec_cap,
+                   unsigned long long* __restrict__ rec_count, int64_t* __restrict__ hist)
 {
     constexpr int kSlots = 1 << SLOT_BITS;
+    constexpr int kThreads = 64 * WAVES;
     __shared__ WaveLds lds[WAVES];
     __shared__ uint32_t hkey[kSlots];
     __shared__ float hval[kSlots];
+    __shared__ int32_t bcur[kAdjMaxBuckets + 1];  // bucket counts, then cursors
     __shared__ int next_row;
     __shared__ int t_gb, t_ip0, t_in0, t_tp, t_tn, t_nKn, t_valid;
-    for (int s = threadIdx.x; s < kSlots; s += 64 * WAVES) {
+    __shared__ int64_t t_g, t_base;
+    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
         hkey[s] = kAdjEmpty;
         hval[s] = 0.0f;
     }
     const int wid = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int64_t ntiles = tile_off[nblocks];
     for (;;) {
         if (threadIdx.x == 0) {
@@ -893,6 +925,7 @@ __global__ void __launch_bounds__(64 * WAVES)
                                                                             __HIP_MEMORY_SCOPE_AGENT)
                                          : (int64_t)blockIdx.x;
             t_valid = g < ntiles;
+            t_g = g;
             if (g < ntiles) {
                 // block of the tile: largest gb with tile_off[gb] <= g
                 int lo = 0, hi = nblocks;
@@ -922,12 +955,14 @@ __global__ void __launch_bounds__(64 * WAVES)
         if (!t_valid) break;
         const int gb = uniform(t_gb), ip0 = uniform(t_ip0), in0 = uniform(t_in0), tp = uniform(t_tp),
                   tn = uniform(t_tn), nKn = uniform(t_nKn);
-        const BasisDev& B = bases[uniform(cst(blk_basis)[gb])];
+        const int64_t g = uniform64(t_g);
+        const int xb = uniform(cst(blk_basis)[gb]);
+        const BasisDev& B = bases[xb];
         const int bi = uniform(cst(blk_local)[gb]);
         const int cnt = tp * tn;
         for (;;) {
             int t = 0;
-            if ((threadIdx.x & 63) == 0) t = atomicAdd(&next_row, 1);
+            if (lane == 0) t = atomicAdd(&next_row, 1);
             t = uniform(t);
             if (t >= cnt) break;
             const int u = t / tn, v = t - u * tn;
@@ -938,9 +973,59 @@ __global__ void __launch_bounds__(64 * WAVES)
         }
         __syncthreads();
         if (use_table) {
-            for (int s = threadIdx.x; s < kSlots; s += 64 * WAVES) {
+            // records of the tile, grouped by bucket: count, reserve room in
+            // the record buffer (one device-scope atomic per tile), scan (one
+            // wavefront; the histogram row of absolute positions goes to
+            // global memory), scatter.  Without room (or without a record
+            // buffer) the slots go to the FP64 accumulators instead.
+            const AdjBasis A = adjb ? adjb[xb] : AdjBasis{};
+            const uint32_t base = (uint32_t)B.tbme0;
+            if (recs) {
+                for (int i = threadIdx.x; i <= A.nb; i += kThreads) bcur[i] = 0;
+                __syncthreads();
+                for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+                    const uint32_t k = hkey[s];
+                    if (k != kAdjEmpty) atomicAdd(&bcur[(k - base) >> A.bits], 1);
+                }
+                __syncthreads();
+                if (wid == 0) {
+                    int run = 0;
+                    for (int c0 = 0; c0 < A.nb; c0 += 64) {
+                        const int c = c0 + lane;
+                        const int v = c < A.nb ? bcur[c] : 0;
+                        const int incl = wave_incl_scan(v);
+                        if (c < A.nb) bcur[c] = run + incl - v;
+                        run += lane63(incl);
+                    }
+                    if (lane == 0) {
+                        int64_t at = (int64_t)__hip_atomic_fetch_add(glbw(rec_count), (unsigned long long)run,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (at + run > rec_cap) at = -1;
+                        t_base = at;
+                        bcur[A.nb] = run;
+                    }
+                }
+                __syncthreads();
+                const int64_t at = t_base;
+                const gmut<int64_t> hrow = glbw(hist) + A.hist0 + (g - A.tile0) * (A.nb + 1);
+                for (int c = threadIdx.x; c <= A.nb; c += kThreads) hrow[c] = at >= 0 ? at + bcur[c] : 0;
+                __syncthreads();
+                if (at >= 0) {
+                    const gmut<uint64_t> out = glbw(recs) + at;
+                    for (int s = threadIdx.x; s < kSlots; s += kThreads) {
+                        const uint32_t k = hkey[s];
+                        if (k != kAdjEmpty) {
+                            const int p = atomicAdd(&bcur[(k - base) >> A.bits], 1);
+                            out[p] = (uint64_t)k | ((uint64_t)__float_as_uint(hval[s]) << 32);
+                            hkey[s] = kAdjEmpty;
+                            hval[s] = 0.0f;
+                        }
+                    }
+                }
+            }
+            for (int s = threadIdx.x; s < kSlots; s += kThreads) {
                 const uint32_t k = hkey[s];
-                if (k != kAdjEmpty) {
+                if (k != kAdjEmpty) {  // no record buffer, or no room in it
                     atomic_add_f64(glbw(gacc) + k, (double)hval[s]);
                     hkey[s] = kAdjEmpty;
                     hval[s] = 0.0f;
@@ -949,6 +1034,57 @@ __global__ void __launch_bounds__(64 * WAVES)
         }
         __syncthreads();
         if (!persistent) break;
+    }
+}
+
+// Sum of the adjoint's tile records: one workgroup per bucket of a basis'
+// table; hist holds, per tile, the absolute record position where each bucket
+// of the tile starts (and where the last ends).  The bucket's 2^bits positions are summed 8192 at a time in an FP64
+// shared-memory array (one pass over the bucket's record segments of every
+// tile of the basis per 8192 positions), plus the direct contributions in gacc,
+// and written once as FP32.
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceWindow = 1 << kAdjBucketMinBits;
+
+__global__ void __launch_bounds__(kReduceThreads)
+    adjoint_reduce(const BasisDev* __restrict__ bases, const AdjBasis* __restrict__ adjb, int nbases,
+                   const uint64_t* __restrict__ recs, const int64_t* __restrict__ hist,
+                   const double* __restrict__ gacc, float* __restrict__ gtbme)
+{
+    __shared__ double acc[kReduceWindow];
+    const int64_t bucket = blockIdx.x;
+    // basis of the bucket: largest x with bucket0 <= bucket
+    int lo = 0, hi = nbases;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (adjb[mid].bucket0 <= bucket) lo = mid;
+        else hi = mid;
+    }
+    const int x = uniform(lo);
+    const AdjBasis A = adjb[x];
+    const int64_t tbme0 = bases[x].tbme0, ntbme = bases[x].ntbme;
+    const int j = (int)(bucket - A.bucket0);
+    const int64_t klo = (int64_t)j << A.bits;
+    const int64_t khi = (klo + ((int64_t)1 << A.bits)) < ntbme ? klo + ((int64_t)1 << A.bits) : ntbme;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int kWaves = kReduceThreads / 64;
+    for (int64_t w0 = klo; w0 < khi; w0 += kReduceWindow) {
+        const int64_t w1 = (w0 + kReduceWindow) < khi ? w0 + kReduceWindow : khi;
+        for (int i = threadIdx.x; i < kReduceWindow; i += kReduceThreads) acc[i] = 0.0;
+        __syncthreads();
+        for (int64_t t = wid; t < A.ntiles; t += kWaves) {
+            const cptr<int64_t> hr = cst(hist) + A.hist0 + t * (A.nb + 1);
+            const int64_t s0 = uniform64(hr[j]), s1 = uniform64(hr[j + 1]);
+            for (int64_t p = s0 + lane; p < s1; p += 64) {
+                const uint64_t r = glb(recs)[p];
+                const int64_t k = (int64_t)(uint32_t)r - tbme0;
+                if (k >= w0 && k < w1) atomicAdd(&acc[k - w0], (double)__uint_as_float((uint32_t)(r >> 32)));
+            }
+        }
+        __syncthreads();
+        for (int64_t k = w0 + threadIdx.x; k < w1; k += kReduceThreads)
+            gtbme[tbme0 + k] = (float)(acc[k - w0] + gacc[tbme0 + k]);
+        __syncthreads();
     }
 }
 
@@ -1157,22 +1293,25 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
                               t, queue, full, s);
 }
 
-hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int32_t* blk_local, int nblocks,
-                      int64_t ntiles, int64_t* tile_off, int64_t nrows, const int64_t* row_ptr, int64_t nrp,
-                      const float* gval, const uint32_t* keys, float* gtbme, double* gacc, int64_t ntbme,
-                      const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
+                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets,
+                      int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
+                      float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
+                      int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
-    if (nrows > 0 && ntiles > 0) {
-        const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
+    const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
+    const bool walked = nrows > 0 && ntiles > 0;
+    if (walked) {
         const int rows = keys ? t.adjk_rows : t.adj_rows, tile_n = keys ? t.adjk_tile_n : t.adj_tile_n;
         hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, rows, tile_n,
-                           tile_off);
+                           tile_off, nbases, adjb);
         const void* kern = keys ? (const void*)adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>
                                 : (const void*)adjoint_kernel<kAdjWaves, kAdjSlotBits>;
         const int threads = 64 * (keys ? kAdjKeysWaves : kAdjWaves);
         unsigned grid = (unsigned)ntiles;
+        if (recs) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, rec_count);
         if (t.adj_persistent) {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
             const unsigned res = resident_blocks(kern, threads, keys ? 7 : 6);
@@ -1181,14 +1320,24 @@ hipError_t launch_vjp(const BasisDev* bases, const int32_t* blk_basis, const int
         if (keys)
             hipLaunchKernelGGL((adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>), dim3(grid), dim3(threads), 0, s,
                                bases, blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys,
-                               gacc, use_table, t.adj_persistent ? 1 : 0, queue);
+                               gacc, use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count,
+                               hist);
         else
             hipLaunchKernelGGL((adjoint_kernel<kAdjWaves, kAdjSlotBits>), dim3(grid), dim3(threads), 0, s, bases,
                                blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys, gacc,
-                               use_table, t.adj_persistent ? 1 : 0, queue);
+                               use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count, hist);
     }
-    if (ntbme > 0) hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
+    if (ntbme > 0) {
+        if (use_table && walked && recs && nbuckets > 0)
+            hipLaunchKernelGGL(adjoint_reduce, dim3((unsigned)nbuckets), dim3(kReduceThreads), 0, s, bases, adjb,
+                               nbases, recs, hist, gacc, gtbme);
+        else
+            hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
+    }
     return hipGetLastError();
 }
+
+// Slots of the shared-memory table of each adjoint (the records a tile can write).
+int adjoint_slots(bool stored) { return stored ? (1 << kAdjKeysSlotBits) : (1 << kAdjSlotBits); }
 
 }  // namespace ci

@@ -414,14 +414,20 @@ def test_tuning_validation_and_tuner(ci):
     v = torch.empty(len(col), dtype=torch.float32, device="cuda")
     G = torch.ones(len(col), device="cuda")
     g_ref = ci.ci_hamiltonian_vjp(b, rp_t, G)
-    t = ci.ci_hamiltonian_tune(b, tbme, rp_t, c, v, G, reps=1)
+    kw = torch.empty(len(col), dtype=torch.int32, device="cuda")
+    t = ci.ci_hamiltonian_tune(b, tbme, rp_t, c, v, G, reps=1, keys=kw)
     say("tuned", t)
     assert t["row_waves"] in (4, 8) and t["row_grab"] in (0, 1, 4, 16)
-    assert (t["adj_rows"], t["adj_tile_n"]) in ((32, 32), (32, 8), (32, 4), (64, 16), (64, 8))
-    assert t["adj_persistent"] in (0, 1)
+    assert (t["adj_rows"], t["adj_tile_n"]) in ((32, 4), (32, 8), (64, 8), (64, 16), (128, 8), (128, 16))
+    assert (t["adjk_rows"], t["adjk_tile_n"]) in ((64, 8), (96, 8), (128, 8), (96, 16), (192, 8), (256, 16))
+    assert t["adj_persistent"] in (0, 1) and t["adjk_persistent"] in (0, 1)
     torch.cuda.synchronize()
     assert np.array_equal(c.cpu().numpy(), col)
     assert np.array_equal(v.cpu().numpy().view(np.int32), val.view(np.int32))
+    # the words the tuner left are the fill's: the stored-word adjoint agrees
+    gk = ci.ci_hamiltonian_vjp_keys(b, rp_t, kw, G)
+    torch.cuda.synchronize()
+    assert float((gk - g_ref).abs().max()) <= GRAD_TOL * float(g_ref.abs().max())
     # a new handle of the same problems starts from the tuned shapes
     b2 = ci.ci_basis_build(probs)
     assert b2.tuning == t
@@ -468,13 +474,13 @@ def test_batched_64_bases_sampled_rows(ci, stored):
         oracles.append(o)
         samples.append((rows, counts, cols, vals, pos, Gs))
     gt = torch.empty(b.n_tbme, dtype=torch.float32, device="cuda")
-    work = torch.empty(b.vjp_work_bytes(), dtype=torch.uint8, device="cuda")
+    keys = torch.empty(tot, dtype=torch.int32, device="cuda")
     say("batch tune")
-    ci.ci_hamiltonian_tune(b, tbme, rp_t, col, val, G, gt, work, reps=1)
+    ci.ci_hamiltonian_tune(b, tbme, rp_t, col, val, G, gt, None, reps=1, keys=keys if stored else None)
+    work = torch.empty(b.vjp_work_bytes(), dtype=torch.uint8, device="cuda")
     col.fill_(-1)
     val.fill_(float("nan"))
     gt.fill_(float("nan"))
-    keys = torch.empty(tot, dtype=torch.int32, device="cuda")
 
     def step():
         if stored:

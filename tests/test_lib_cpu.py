@@ -98,7 +98,7 @@ def test_argument_errors_before_any_device_call():
     t = ci.ci_tuning()
     assert L.ci_basis_get_tuning(None, c.byref(t)) == ci.CI_EINVAL
     assert L.ci_basis_set_tuning(None, c.byref(t)) == ci.CI_EINVAL
-    assert L.ci_hamiltonian_tune(None, None, None, None, None, None, None, None, 0, 1, None) == ci.CI_EINVAL
+    assert L.ci_hamiltonian_tune(None, None, None, None, None, None, None, None, None, 0, 1, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_fill(None, None, None, None, None, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_vjp(None, None, None, None, None, 0, None) == ci.CI_EINVAL
     assert L.ci_hamiltonian_count(None, None, None, None) == ci.CI_EINVAL
