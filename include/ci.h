@@ -135,6 +135,8 @@ typedef struct {
     int32_t adjk_rows;      /* adjoint from stored words: target rows per tile, 1..4096 */
     int32_t adjk_tile_n;    /* adjoint from stored words: neutron determinants per tile, 1..4096 */
     int32_t adjk_persistent; /* adjoint from stored words: 0 one workgroup per tile, 1 persistent */
+    int32_t row_xcd;        /* grids of rows or tiles (not persistent): 0 launch order; 1 each of the 8 XCDs */
+                            /* (workgroup g runs on XCD g mod 8) takes one contiguous eighth of the grid   */
 } ci_tuning;
 
 /* Thread-local text of the last error. */

@@ -344,7 +344,7 @@ std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8, 1}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8, 1, 0}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
@@ -1331,7 +1331,8 @@ static bool tuning_ok(const ci_tuning& t)
     return (t.row_waves == 4 || t.row_waves == 8) && t.row_grab >= 0 && t.row_grab <= 4096 && t.adj_rows >= 1 &&
            t.adj_rows <= 4096 && t.adj_tile_n >= 1 && t.adj_tile_n <= 4096 &&
            (t.adj_persistent == 0 || t.adj_persistent == 1) && t.adjk_rows >= 1 && t.adjk_rows <= 4096 &&
-           t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096 && (t.adjk_persistent == 0 || t.adjk_persistent == 1);
+           t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096 && (t.adjk_persistent == 0 || t.adjk_persistent == 1) &&
+           (t.row_xcd == 0 || t.row_xcd == 1);
 }
 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
@@ -1378,11 +1379,12 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     float best_ms = 0.0f;
     bool have = false;
     for (int waves : {4, 8})
-        for (int grab : {0, 1, 4, 16}) {
+        for (int grab : {-1, 0, 1, 4, 16}) {  // -1: grid in XCD-contiguous order
             if (rc != CI_OK) break;
             b->tune = start;
             b->tune.row_waves = waves;
-            b->tune.row_grab = grab;
+            b->tune.row_grab = grab < 0 ? 0 : grab;
+            b->tune.row_xcd = grab < 0 ? 1 : 0;
             float ms = 0.0f;
             rc = time_ms([&] { return launch_fill(b->d_bases, (int)b->info.size(), b->d_basis_row0, b->nrows, tbme,
                                                   row_ptr, b->n_rowptr, col, val, nullptr, b->tune, b->d_queue, 0,
@@ -1391,7 +1393,8 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
             if (rc == CI_OK && (!have || ms < best_ms)) {
                 best_ms = ms;
                 best.row_waves = waves;
-                best.row_grab = grab;
+                best.row_grab = b->tune.row_grab;
+                best.row_xcd = b->tune.row_xcd;
                 have = true;
             }
         }

@@ -114,6 +114,18 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs of the device in turn
+// (workgroup g runs on XCD g mod 8), and each XCD has its own L2.  With
+// this mapping XCD x runs the logical workgroups of one contiguous eighth of
+// the grid, so the rows (or tiles) that one L2 serves at a time are
+// neighbours and share their partner lists.  A bijection on [0, n).
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t g, int64_t n)
+{
+    constexpr int kXcds = 8;
+    const int64_t x = g % kXcds, slot = g / kXcds, q = n / kXcds, r = n % kXcds;
+    return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
 // LDS writes by one lane become visible to the other lanes of the wavefront
 __device__ __forceinline__ void wave_sync()
 {
@@ -782,12 +794,13 @@ __global__ void __launch_bounds__(64 * WAVES)
     row_kernel(const BasisDev* __restrict__ bases, int nb, const int64_t* __restrict__ basis_row0,
                int64_t nrows, const float* __restrict__ tbme, int64_t* __restrict__ row_ptr, int64_t nrp,
                int32_t* __restrict__ col, float* __restrict__ val, uint32_t* __restrict__ keys, int grab,
-               unsigned long long* __restrict__ queue, int full)
+               unsigned long long* __restrict__ queue, int full, int xcd)
 {
     __shared__ WaveLds lds[WAVES];
     const int wid = uniform(threadIdx.x >> 6);
     if (grab <= 0) {
-        const int64_t grow = (int64_t)blockIdx.x * WAVES + wid;
+        const int64_t wg = xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+        const int64_t grow = wg * WAVES + wid;
         if (grow < nrows)
             run_row<MODE>(bases, nb, basis_row0, grow, tbme, row_ptr, nrp, col, val, nullptr, nullptr, nullptr,
                           nullptr, false, full != 0, keys, lds[wid]);
@@ -900,7 +913,7 @@ __global__ void __launch_bounds__(64 * WAVES)
                    const float* __restrict__ gval, const uint32_t* __restrict__ keys, double* __restrict__ gacc,
                    int use_table, int persistent, unsigned long long* __restrict__ queue,
                    const AdjBasis* __restrict__ adjb, uint64_t* __restrict__ recs, int64_t rec_cap,
-                   unsigned long long* __restrict__ rec_count, int64_t* __restrict__ hist)
+                   unsigned long long* __restrict__ rec_count, int64_t* __restrict__ hist, int xcd)
 {
     constexpr int kSlots = 1 << SLOT_BITS;
     constexpr int kThreads = 64 * WAVES;
@@ -923,7 +936,7 @@ __global__ void __launch_bounds__(64 * WAVES)
             next_row = 0;
             const int64_t g = persistent ? (int64_t)__hip_atomic_fetch_add(glbw(queue), 1ull, __ATOMIC_RELAXED,
                                                                             __HIP_MEMORY_SCOPE_AGENT)
-                                         : (int64_t)blockIdx.x;
+                                         : (xcd ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
             t_valid = g < ntiles;
             t_g = g;
             if (g < ntiles) {
@@ -1236,7 +1249,7 @@ static unsigned resident_blocks(const void* kernel, int threads, int kind)
 template <int MODE, int WAVES>
 static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_row0, int64_t nrows,
                           const float* tbme, int64_t* row_ptr, int64_t nrp, int32_t* col, float* val, uint32_t* keys,
-                          int grab, unsigned long long* queue, int full, hipStream_t s)
+                          int grab, unsigned long long* queue, int full, int xcd, hipStream_t s)
 {
     unsigned grid = grid_for(nrows, WAVES);
     if (grab > 0) {
@@ -1247,7 +1260,7 @@ static void launch_rows_w(const BasisDev* bases, int nb, const int64_t* basis_ro
         grid = res < need ? res : need;
     }
     hipLaunchKernelGGL((row_kernel<MODE, WAVES>), dim3(grid), dim3(64 * WAVES), 0, s, bases, nb, basis_row0,
-                       nrows, tbme, row_ptr, nrp, col, val, keys, grab, queue, full);
+                       nrows, tbme, row_ptr, nrp, col, val, keys, grab, queue, full, xcd);
 }
 
 template <int MODE>
@@ -1258,10 +1271,10 @@ static hipError_t launch_rows(const BasisDev* bases, int nb, const int64_t* basi
     if (nrows <= 0) return hipSuccess;
     if (t.row_waves == 8)
         launch_rows_w<MODE, 8>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, keys, t.row_grab, queue,
-                               full, s);
+                               full, t.row_xcd, s);
     else
         launch_rows_w<MODE, 4>(bases, nb, basis_row0, nrows, tbme, row_ptr, nrp, col, val, keys, t.row_grab, queue,
-                               full, s);
+                               full, t.row_xcd, s);
     return hipGetLastError();
 }
 
@@ -1321,11 +1334,12 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
             hipLaunchKernelGGL((adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>), dim3(grid), dim3(threads), 0, s,
                                bases, blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys,
                                gacc, use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count,
-                               hist);
+                               hist, t.row_xcd);
         else
             hipLaunchKernelGGL((adjoint_kernel<kAdjWaves, kAdjSlotBits>), dim3(grid), dim3(threads), 0, s, bases,
                                blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys, gacc,
-                               use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count, hist);
+                               use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count, hist,
+                               t.row_xcd);
     }
     if (ntbme > 0) {
         if (use_table && walked && recs && nbuckets > 0)

@@ -363,9 +363,11 @@ def test_autograd_function(ci):
 
 # ------------------------------------------------------------------ launch shapes and batches
 
-SHAPES = [dict(row_waves=w, row_grab=g) for w in (4, 8) for g in (0, 1, 7)]
-ADJ_SHAPES = [dict(adj_rows=r, adj_tile_n=n, adj_persistent=q) for r, n in ((1, 1), (17, 5), (64, 16), (32, 64))
-              for q in (0, 1)]
+SHAPES = [dict(row_waves=w, row_grab=g, row_xcd=0) for w in (4, 8) for g in (0, 1, 7)] + \
+    [dict(row_waves=w, row_grab=0, row_xcd=1) for w in (4, 8)]
+ADJ_SHAPES = [dict(adj_rows=r, adj_tile_n=n, adj_persistent=q, row_xcd=0) for r, n in ((1, 1), (17, 5), (64, 16),
+                                                                                     (32, 64)) for q in (0, 1)] + \
+    [dict(adj_rows=r, adj_tile_n=n, adj_persistent=0, row_xcd=1) for r, n in ((17, 5), (128, 8))]
 
 
 def test_launch_shapes_give_the_same_result(ci):
@@ -405,7 +407,7 @@ def test_tuning_validation_and_tuner(ci):
     seeds = [300 + k for k in range(len(probs))]
     b, rp, col, val, tb = run_forward(ci, probs, seeds)
     for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_tile_n=0), dict(adj_persistent=2),
-                dict(adjk_rows=0), dict(adjk_tile_n=4097)):
+                dict(adjk_rows=0), dict(adjk_tile_n=4097), dict(row_xcd=2), dict(adjk_persistent=3)):
         with pytest.raises(ci.CIError):
             b.tuning = bad
     rp_t = torch.from_numpy(rp).cuda()
