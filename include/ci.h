@@ -217,6 +217,22 @@ int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uin
                             const float* grad_val, float* grad_tbme, void* work, size_t work_bytes,
                             ci_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * adjoint as ci_hamiltonian_vjp (same arguments without the work buffer, same
+ * result to rounding), with its scratch (FP64 accumulators, tile records and
+ * histograms) in a fixed device array of the library, 64 MiB per GPU
+ * (ci_vjp_noalloc_scratch_bytes), held from the first call on a GPU until the
+ * process ends.  Calls nothing that allocates.  The table of the handle must
+ * fit the scratch as FP64 accumulators (n_tbme * 8 bytes, with room to spare;
+ * else CI_ESPACE before any launch); the tile records get the rest (a tile
+ * that finds no room adds its sums to the accumulators).  Every call on one
+ * GPU shares the array: calls that overlap on one GPU (other streams, other
+ * threads) race and give wrong results; order them.  Asynchronous. */
+int ci_hamiltonian_vjp_noalloc(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
+                               ci_stream stream);
+size_t ci_vjp_noalloc_scratch_bytes(void);
+
 /* The same two passes for the FULL symmetric matrix (both triangles, every
  * (i, j) with d(i, j) <= 2, columns ascending in a row), as the eigensolver
  * needs it; same layout and batch conventions as above. */

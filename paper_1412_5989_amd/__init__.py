@@ -78,7 +78,8 @@ class ci_tuning(ctypes.Structure):
 EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "ci_basis_list_bytes",
            "ci_basis_build_lists", "ci_basis_free",
            "ci_hamiltonian_count", "ci_hamiltonian_fill", "ci_hamiltonian_vjp", "ci_vjp_work_bytes",
-           "ci_hamiltonian_fill_keys", "ci_hamiltonian_vjp_keys",
+           "ci_hamiltonian_fill_keys", "ci_hamiltonian_vjp_keys", "ci_hamiltonian_vjp_noalloc",
+           "ci_vjp_noalloc_scratch_bytes",
            "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill",
            "ci_hamiltonian3_count_full", "ci_hamiltonian3_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
            "ci_lanczos_work_bytes",
@@ -113,6 +114,9 @@ def load_library():
     L.ci_hamiltonian_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     L.ci_hamiltonian_fill_keys.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_vjp_keys.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.ci_hamiltonian_vjp_noalloc.argtypes = [vp, vp, vp, vp, vp]
+    L.ci_vjp_noalloc_scratch_bytes.argtypes = []
+    L.ci_vjp_noalloc_scratch_bytes.restype = sz
     L.ci_hamiltonian_count_full.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill_full.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_spmv.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
@@ -147,6 +151,7 @@ def load_library():
     L.ci_basis_states.argtypes = [vp, i32, vp, vp]
     for name in EXPORTS:
         if name not in ("ci_last_error", "ci_basis_free", "ci_vjp_work_bytes", "ci_basis_count",
+                        "ci_vjp_noalloc_scratch_bytes",
                         "ci_lanczos_work_bytes", "ci_threebody_free", "ci_threebody_work_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L

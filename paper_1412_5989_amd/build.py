@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libci.so")
-SOURCES = ["kernels.hip", "basis_kernels.hip", "lanczos.hip", "threebody.hip", "threebody_term.hip", "probe.hip", "ci_api.cpp",
+SOURCES = ["kernels.hip", "basis_kernels.hip", "lanczos.hip", "threebody.hip", "threebody_term.hip", "probe.hip", "noalloc.hip", "ci_api.cpp",
            "host_basis.cpp"]
 
 HIPCC_FLAGS = [

@@ -31,6 +31,8 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                       float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
                       int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 int adjoint_slots(bool stored);
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(void** p);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 hipError_t launch_partner_count(const PartnerArgs& a, hipStream_t s);
@@ -1234,7 +1236,7 @@ struct VjpLayout {
     size_t recs = 0, hist = 0, bytes = 0;
 };
 
-static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored)
+static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, size_t limit = 0)
 {
     VjpLayout v;
     int64_t hist = 0;
@@ -1251,8 +1253,19 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored)
     if (v.records) {
         v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored);
         if (b->nnz_total >= 0) v.rec_cap = std::min<int64_t>(v.rec_cap, b->nnz_total / 2 + 1);
-        v.recs = L.take<uint64_t>((size_t)v.rec_cap);
         v.hist = L.take<int64_t>((size_t)std::max<int64_t>(hist, 1));
+        if (limit) {  // a fixed buffer: the records get what is left of it
+            const size_t left = limit > L.bytes() + 256 ? limit - L.bytes() - 256 : 0;
+            v.rec_cap = std::min<int64_t>(v.rec_cap, (int64_t)(left / sizeof(uint64_t)));
+            if (v.rec_cap < 1 || L.bytes() > limit) v.records = false;
+        }
+        v.recs = L.take<uint64_t>((size_t)std::max<int64_t>(v.rec_cap, 1));
+    }
+    if (!v.records) {
+        v.rec_cap = 0;
+        v.recs = v.hist = 0;
+        L = Layout();
+        (void)L.take<double>((size_t)b->n_tbme);
     }
     v.bytes = L.bytes();
     return v;
@@ -1281,10 +1294,11 @@ static size_t work_bytes_for(const ci_basis* b)
 }
 
 static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
-                             void* work, const ci_tuning& t, hipStream_t s, const uint32_t* keys = nullptr)
+                             void* work, const ci_tuning& t, hipStream_t s, const uint32_t* keys = nullptr,
+                             size_t limit = 0)
 {
     const bool stored = keys != nullptr;
-    const VjpLayout v = vjp_layout(b, t, stored);
+    const VjpLayout v = vjp_layout(b, t, stored, limit);
     char* w = (char*)work;
     ci_tuning tt = t;
     if (stored) tt.adj_persistent = t.adjk_persistent;
@@ -1325,6 +1339,28 @@ int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uin
     if (e != hipSuccess) return hip_fail(e, "vjp launch");
     return CI_OK;
 }
+
+int ci_hamiltonian_vjp_noalloc(const ci_basis* b, const int64_t* row_ptr, const float* grad_val, float* grad_tbme,
+                               ci_stream stream)
+{
+    if (!b || !row_ptr) return fail(CI_EINVAL, "null pointer");
+    if (int rc = need_ready(b)) return rc;
+    if (!grad_val && b->nrows > 0) return fail(CI_EINVAL, "null pointer");
+    if (b->n_tbme > 0 && !grad_tbme) return fail(CI_EINVAL, "null pointer");
+    const size_t cap = noalloc_scratch_bytes();
+    // the FP64 accumulators must fit; the tile records take what is left
+    if ((size_t)b->n_tbme * sizeof(double) + 256 > cap)
+        return fail(CI_ESPACE, "the two-body tables of this handle (" + std::to_string(b->n_tbme) +
+                                   " elements) exceed the fixed scratch of " + std::to_string(cap) + " bytes");
+    void* scr = nullptr;
+    hipError_t e = noalloc_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    e = vjp_launch(b, row_ptr, grad_val, grad_tbme, scr, b->tune, (hipStream_t)stream, nullptr, cap);
+    if (e != hipSuccess) return hip_fail(e, "vjp launch");
+    return CI_OK;
+}
+
+size_t ci_vjp_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
 
 static bool tuning_ok(const ci_tuning& t)
 {
