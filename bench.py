@@ -3,20 +3,24 @@
 
 One step is the whole construction path for one problem, starting from the
 problem description and the two-body table resident in HBM:
-    ci_basis_build  (basis indexing, one upload)
+    ci_basis_build       (size query, arena, tables, partner lists)
     ci_hamiltonian_count (count + scan; one sync to read nnz)
-    ci_hamiltonian_fill_keys  (col/val of every stored entry, plus one
-                               structure word per entry for the adjoint)
-    ci_hamiltonian_vjp_keys   (adjoint onto the table, upstream G_e = psi_i psi_j)
-(--adjoint walk: ci_hamiltonian_fill + ci_hamiltonian_vjp, which walks the
-partner lists again instead of reading stored words.)
-value = nnz / (seconds per step).  The default workload is 6Li, Nmax = 6,
-2M = 2, positive parity (D = 186,894, 55.5 M stored entries).
+    ci_hamiltonian_fill  (col/val of every stored entry)
+    ci_hamiltonian_vjp   (adjoint onto the table, upstream G_e = psi_i psi_j;
+                          recomputes the pair and phase structure)
+(--adjoint stored: ci_hamiltonian_fill_keys + ci_hamiltonian_vjp_keys, where
+the fill stores one structure word per entry and the adjoint reads them.)
+value = nnz / (seconds per step).  The default workload is 10B, Z = N = 5,
+Nmax = 4, 2M = 0, positive parity (D = 581,740, 143.9 M stored entries):
+forward + adjoint.
 
-The JSON line also carries per-stage times, the roofline of the dominant
-kernel (timed with HIP events on the stream it runs on), the batched mode (64
-bases, one persistent graph-captured launch) and the FP64 oracle timed on the
-host cores on a bounded sample of rows.
+The JSON line also carries per-stage times, forward and adjoint legs each
+with nonzeros/s, an HBM roofline from the algorithmic bytes (timed with HIP
+events on the stream the kernels run on) and a VALU issue fraction from the
+committed counters, the 6Li Nmax = 6 workload, the batched mode (64 bases,
+fill + adjoint captured in one HIP graph), the eigensolver on the full and on
+the stored upper-triangle matrix, and the FP64 oracle timed on the host cores
+on a bounded sample of rows.
 """
 from __future__ import annotations
 
@@ -182,11 +186,34 @@ def run_lanczos(ci, torch, prob, tbme_seed):
     t0 = time.perf_counter()
     E, v, it = ci.ci_lanczos(b, 0, rp, col, val, max_iter=300, tol=1e-12)
     t_l = time.perf_counter() - t0
+    del col, val
+    # the same on the construction's own output, the stored upper triangle:
+    # every stored entry read once for both y_i and y_j (the transposed half
+    # by FP64 device atomics)
+    rpu, nnzu = ci.ci_hamiltonian_count(b)
+    colu, valu = ci.ci_hamiltonian_fill(b, tb, rpu)
+    eu = EventTimer(torch, stream)
+    for _ in range(10):
+        with eu:
+            ci.ci_hamiltonian_spmv_upper(b, 0, rpu, colu, valu, x, y)
+    spmv_u_ms = eu.mean_ms()
+    alg_u = 8 * nnzu[0] + 8 * (D + 1) + 16 * D
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Eu, _, itu = ci.ci_lanczos_upper(b, 0, rpu, colu, valu, max_iter=300, tol=1e-12)
+    t_lu = time.perf_counter() - t0
     b.free()
     return {"nnz_full": nnz[0], "fill_full_ms": fill_ms, "fill_full_nnz_per_s": nnz[0] / (fill_ms * 1e-3),
             "spmv_ms": spmv_ms, "spmv_GBps": alg / (spmv_ms * 1e-3) / 1e9,
             "spmv_frac_of_hbm_peak": alg / (spmv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E}
+            "lanczos_s": t_l, "lanczos_iters": it, "lowest_eigenvalue_MeV": E,
+            "upper": {"operand": "stored upper triangle (ci_hamiltonian_fill output)", "nnz": nnzu[0],
+                      "spmv_ms": spmv_u_ms,
+                      "spmv_roofline": {"bound": "hbm", "achieved": alg_u / (spmv_u_ms * 1e-3) / 1e9,
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": alg_u / (spmv_u_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                        "alg_bytes_per_launch": alg_u},
+                      "lanczos_s": t_lu, "lanczos_iters": itu, "lowest_eigenvalue_MeV": Eu}}
 
 
 def threebody_block_elements(t, req):
@@ -408,7 +435,10 @@ def run_batched(ci, torch, steps, warmup, stored, tuning_text=None):
     return out
 
 
-VALU_PEAK = 256 * 4 * 2.4e9  # VALU wave-instructions/s: one per SIMD per cycle, 256 CUs x 4 SIMDs x 2.4 GHz
+# VALU wave-instructions/s: a SIMD is 16 lanes wide, so one wave64 VALU
+# instruction occupies it for 4 cycles; 256 CUs x 4 SIMDs x 2.4 GHz / 4 =
+# 6.14e11/s (= 3.93e13 32-bit lane-ops/s, the published non-packed FP32 rate)
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def leg(ms, nnz, alg_bytes, profile):

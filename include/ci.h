@@ -307,6 +307,21 @@ int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const in
                const float* val, const double* x0, int32_t max_iter, double tol, double* eval,
                int32_t* iters, double* evec, void* work, size_t work_bytes, ci_stream stream);
 
+/* The same product and eigensolver on the matrix as the construction stores
+ * it: the upper triangle only (row_ptr, col, val from ci_hamiltonian_count /
+ * ci_hamiltonian_fill; half of the symmetric matrix, paper Sec. 2), with
+ * H = U + (U - diag U)^T.  Every stored off-diagonal entry (i, j) is read
+ * once and serves both y_i (a gather of x_j) and y_j (an FP64 device atomic
+ * adding U_ij x_i), so y is reproducible to rounding only, not bit for bit.
+ * ci_hamiltonian_spmv_upper overwrites y (it zeroes it first, on the
+ * stream).  Arguments, errors and work size as for ci_hamiltonian_spmv and
+ * ci_lanczos. */
+int ci_hamiltonian_spmv_upper(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                              const float* val, const double* x, double* y, ci_stream stream);
+int ci_lanczos_upper(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                     const float* val, const double* x0, int32_t max_iter, double tol, double* eval,
+                     int32_t* iters, double* evec, void* work, size_t work_bytes, ci_stream stream);
+
 /* Bytes of work for ci_lanczos: (max_iter + 1) vectors of D doubles plus small buffers. */
 size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter);
 

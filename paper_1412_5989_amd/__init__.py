@@ -82,7 +82,7 @@ EXPORTS = ["ci_last_error", "ci_basis_plan", "ci_tbme_keys", "ci_basis_build", "
            "ci_vjp_noalloc_scratch_bytes",
            "ci_hamiltonian_count_full", "ci_hamiltonian_fill_full", "ci_hamiltonian3_count", "ci_hamiltonian3_fill",
            "ci_hamiltonian3_count_full", "ci_hamiltonian3_fill_full", "ci_hamiltonian_spmv", "ci_lanczos",
-           "ci_lanczos_work_bytes",
+           "ci_hamiltonian_spmv_upper", "ci_lanczos_upper", "ci_lanczos_work_bytes",
            "ci_hamiltonian_tune", "ci_basis_get_tuning", "ci_basis_set_tuning", "ci_probe_ceilings",
            "ci_threebody_plan", "ci_threebody_build", "ci_threebody_free", "ci_threebody_info", "ci_threebody_keys",
            "ci_threebody_orbitals", "ci_threebody_decouple", "ci_threebody_work_bytes", "ci_clebsch_gordan",
@@ -120,8 +120,10 @@ def load_library():
     L.ci_hamiltonian_count_full.argtypes = [vp, vp, vp, vp]
     L.ci_hamiltonian_fill_full.argtypes = [vp, vp, vp, vp, vp, vp]
     L.ci_hamiltonian_spmv.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.ci_hamiltonian_spmv_upper.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.ci_lanczos.argtypes = [vp, i32, vp, vp, vp, vp, i32, ctypes.c_double, P(ctypes.c_double), P(i32), vp, vp,
                              sz, vp]
+    L.ci_lanczos_upper.argtypes = L.ci_lanczos.argtypes
     L.ci_lanczos_work_bytes.argtypes = [i64, i32]
     L.ci_lanczos_work_bytes.restype = sz
     L.ci_hamiltonian_tune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp]
@@ -393,22 +395,36 @@ def ci_hamiltonian3_fill_full(basis: Basis, tbme, v3, row_ptr, col=None, val=Non
     return _h3_fill(basis, tbme, v3, row_ptr, col, val, True, stream)
 
 
-def ci_hamiltonian_spmv(basis: Basis, prob: int, row_ptr, col, val, x, y=None, stream=None):
-    """y = H x (float64) for problem `prob`, H in full CSR form."""
+def ci_hamiltonian_spmv(basis: Basis, prob: int, row_ptr, col, val, x, y=None, stream=None, upper=False):
+    """y = H x (float64) for problem `prob`, H in full CSR form, or (upper=True)
+    the stored upper triangle of ci_hamiltonian_fill (ci_hamiltonian_spmv_upper)."""
     torch = _torch()
     D = basis.info[prob]["dim"]
     _check_tensor(x, torch.float64, D, "x")
     if y is None:
         y = torch.empty(D, dtype=torch.float64, device=basis.device)
     _check_tensor(y, torch.float64, D, "y")
-    _check(load_library().ci_hamiltonian_spmv(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x),
-                                              _ptr(y), _stream_ptr(stream)))
+    L = load_library()
+    fn = L.ci_hamiltonian_spmv_upper if upper else L.ci_hamiltonian_spmv
+    _check(fn(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y), _stream_ptr(stream)))
     return y
 
 
+def ci_hamiltonian_spmv_upper(basis: Basis, prob: int, row_ptr, col, val, x, y=None, stream=None):
+    """y = H x from the stored upper triangle (ci_hamiltonian_count / _fill output)."""
+    return ci_hamiltonian_spmv(basis, prob, row_ptr, col, val, x, y, stream, upper=True)
+
+
+def ci_lanczos_upper(basis: Basis, prob: int, row_ptr, col, val, x0=None, max_iter: int = 200, tol: float = 1e-12,
+                     stream=None):
+    """Lowest eigenpair of H from the stored upper triangle (ci_hamiltonian_fill output)."""
+    return ci_lanczos(basis, prob, row_ptr, col, val, x0, max_iter, tol, stream, upper=True)
+
+
 def ci_lanczos(basis: Basis, prob: int, row_ptr, col, val, x0=None, max_iter: int = 200, tol: float = 1e-12,
-               stream=None):
-    """Lowest eigenpair of H (full CSR): (eigenvalue, eigenvector float64 tensor, iterations)."""
+               stream=None, upper=False):
+    """Lowest eigenpair of H (full CSR, or upper=True: the stored upper
+    triangle): (eigenvalue, eigenvector float64 tensor, iterations)."""
     torch = _torch()
     D = basis.info[prob]["dim"]
     if x0 is None:
@@ -419,9 +435,10 @@ def ci_lanczos(basis: Basis, prob: int, row_ptr, col, val, x0=None, max_iter: in
     work = torch.empty(max(nwork, 8), dtype=torch.uint8, device=basis.device)
     evec = torch.empty(D, dtype=torch.float64, device=basis.device)
     ev, it = ctypes.c_double(), ctypes.c_int32()
-    _check(L.ci_lanczos(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x0), int(max_iter),
-                        float(tol), ctypes.byref(ev), ctypes.byref(it), _ptr(evec), _ptr(work),
-                        work.numel(), _stream_ptr(stream)))
+    fn = L.ci_lanczos_upper if upper else L.ci_lanczos
+    _check(fn(basis.handle, int(prob), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x0), int(max_iter),
+              float(tol), ctypes.byref(ev), ctypes.byref(it), _ptr(evec), _ptr(work),
+              work.numel(), _stream_ptr(stream)))
     return ev.value, evec, it.value
 
 

@@ -40,6 +40,8 @@ hipError_t launch_partner_fill(const PartnerArgs& a, int64_t n1, int64_t n12, hi
 hipError_t run_probes(void* buf, size_t bytes, hipStream_t s, double* store_bps, double* steps_per_s);
 hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x, double* y,
                        int64_t nrows, hipStream_t s);
+hipError_t launch_spmv_upper(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x,
+                             double* y, int64_t nrows, hipStream_t s);
 size_t lanczos_work_bytes(int64_t dim, int max_iter);
 hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int* words, const void* const* index,
                           int nb, const float* tbme, int v3_kind, uint64_t v3_seed, double v3_scale, int64_t* row_ptr,
@@ -47,7 +49,8 @@ hipError_t launch_h3_rows(const BasisDev* bases, const int64_t* dims, const int*
 hipError_t launch_h3_index(bool fill, const BasisDev* B, int species, int64_t nsd, int W, int32_t* seg, int64_t* ptr,
                            uint64_t* rec, hipStream_t s);
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
-                       int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s);
+                       int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s,
+                       bool upper);
 }  // namespace ci
 
 using namespace ci;
@@ -1498,16 +1501,29 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     return CI_OK;
 }
 
-int ci_hamiltonian_spmv(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
-                        const float* val, const double* x, double* y, ci_stream stream)
+static int spmv_any(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
+                    const double* x, double* y, ci_stream stream, bool upper)
 {
     if (!b || !row_ptr || !x || !y) return fail(CI_EINVAL, "null pointer");
     if (prob < 0 || prob >= (int32_t)b->info.size()) return fail(CI_EINVAL, "problem index out of range");
     const ci_basis_info& I = b->info[prob];
     if (I.dim > 0 && (!col || !val)) return fail(CI_EINVAL, "null pointer");
-    hipError_t e = launch_spmv(row_ptr + I.row_ptr_offset, col, val, x, y, I.dim, (hipStream_t)stream);
+    hipError_t e = upper ? launch_spmv_upper(row_ptr + I.row_ptr_offset, col, val, x, y, I.dim, (hipStream_t)stream)
+                         : launch_spmv(row_ptr + I.row_ptr_offset, col, val, x, y, I.dim, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "spmv launch");
     return CI_OK;
+}
+
+int ci_hamiltonian_spmv(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                        const float* val, const double* x, double* y, ci_stream stream)
+{
+    return spmv_any(b, prob, row_ptr, col, val, x, y, stream, false);
+}
+
+int ci_hamiltonian_spmv_upper(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col,
+                              const float* val, const double* x, double* y, ci_stream stream)
+{
+    return spmv_any(b, prob, row_ptr, col, val, x, y, stream, true);
 }
 
 size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter)
@@ -1515,9 +1531,9 @@ size_t ci_lanczos_work_bytes(int64_t dim, int32_t max_iter)
     return (dim > 0 && max_iter > 0) ? lanczos_work_bytes(dim, max_iter) : 0;
 }
 
-int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
-               const double* x0, int32_t max_iter, double tol, double* eval, int32_t* iters, double* evec,
-               void* work, size_t work_bytes, ci_stream stream)
+static int lanczos_any(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
+                       const double* x0, int32_t max_iter, double tol, double* eval, int32_t* iters, double* evec,
+                       void* work, size_t work_bytes, ci_stream stream, bool upper)
 {
     if (!b || !row_ptr || !col || !val || !x0 || !eval || !iters || !evec || !work)
         return fail(CI_EINVAL, "null pointer");
@@ -1530,11 +1546,27 @@ int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const in
                                    " bytes");
     int it = 0;
     hipError_t e = run_lanczos(row_ptr + I.row_ptr_offset, col, val, I.dim, x0, max_iter, tol, eval, &it, evec, work,
-                               (hipStream_t)stream);
+                               (hipStream_t)stream, upper);
     if (e == hipErrorInvalidValue) return fail(CI_EINVAL, "start vector is zero");
     if (e != hipSuccess) return hip_fail(e, "lanczos");
     *iters = it;
     return CI_OK;
+}
+
+int ci_lanczos(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
+               const double* x0, int32_t max_iter, double tol, double* eval, int32_t* iters, double* evec,
+               void* work, size_t work_bytes, ci_stream stream)
+{
+    return lanczos_any(b, prob, row_ptr, col, val, x0, max_iter, tol, eval, iters, evec, work, work_bytes, stream,
+                       false);
+}
+
+int ci_lanczos_upper(const ci_basis* b, int32_t prob, const int64_t* row_ptr, const int32_t* col, const float* val,
+                     const double* x0, int32_t max_iter, double tol, double* eval, int32_t* iters, double* evec,
+                     void* work, size_t work_bytes, ci_stream stream)
+{
+    return lanczos_any(b, prob, row_ptr, col, val, x0, max_iter, tol, eval, iters, evec, work, work_bytes, stream,
+                       true);
 }
 
 struct ci_threebody {

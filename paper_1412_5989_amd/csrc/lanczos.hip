@@ -2,7 +2,9 @@
 // (the step that follows the construction in a CI run: repeated products of
 // H with a vector plus orthogonalization, paper Sec. 1-2).  H is the full
 // symmetric matrix in CSR form (both triangles, from the full count / fill
-// passes), FP32 values; vectors are FP64.
+// passes), or the stored upper triangle of the construction itself (half the
+// bytes per product, a scatter for the transposed half), FP32 values; vectors
+// are FP64.
 //
 // Kernels: y = H x (one wavefront per row, fixed summation order, so the
 // product is reproducible bit for bit), c = V^T w over the Lanczos vectors,
@@ -55,6 +57,40 @@ __global__ void __launch_bounds__(64 * kSpmvWaves) spmv_kernel(const int64_t* __
     for (int64_t e = e0 + lane; e < e1; e += 64) acc += (double)glb(val)[e] * glb(x)[glb(col)[e]];
     acc = wave_sum_f64(acc);
     if (lane == 0) y[i] = acc;
+}
+
+// y = H x from the stored upper triangle U alone (row i holds the columns
+// j >= i, the diagonal included): y = U x + (U - diag U)^T x.  The row
+// product sum_j U_ij x_j is a gather as above; every off-diagonal entry also
+// adds U_ij x_i to y_j, a scatter into rows anywhere in the vector, done with
+// an FP64 device atomic.  y must be zero at launch (zero_f64 below).  The
+// order of the atomics is not fixed, so the product is reproducible to
+// rounding only.
+__global__ void __launch_bounds__(64 * kSpmvWaves) spmv_upper_kernel(const int64_t* __restrict__ row_ptr,
+                                                                    const int32_t* __restrict__ col,
+                                                                    const float* __restrict__ val,
+                                                                    const double* __restrict__ x,
+                                                                    double* __restrict__ y, int64_t nrows)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * kSpmvWaves + (threadIdx.x >> 6);
+    if (i >= nrows) return;
+    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+    const double xi = glb(x)[i];
+    double acc = 0.0;
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int j = glb(col)[e];
+        const double v = (double)glb(val)[e];
+        acc += v * glb(x)[j];
+        if (j != i) atomicAdd(y + j, v * xi);
+    }
+    acc = wave_sum_f64(acc);
+    if (lane == 0) atomicAdd(y + i, acc);
+}
+
+__global__ void __launch_bounds__(256) zero_f64(double* __restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = 0.0;
 }
 
 constexpr int kDotThreads = 256;
@@ -194,6 +230,17 @@ hipError_t launch_spmv(const int64_t* row_ptr, const int32_t* col, const float* 
     return hipGetLastError();
 }
 
+hipError_t launch_spmv_upper(const int64_t* row_ptr, const int32_t* col, const float* val, const double* x,
+                             double* y, int64_t nrows, hipStream_t s)
+{
+    if (nrows > 0) {
+        hipLaunchKernelGGL(zero_f64, dim3(stream_grid(nrows)), dim3(256), 0, s, y, nrows);
+        hipLaunchKernelGGL(spmv_upper_kernel, dim3((unsigned)((nrows + kSpmvWaves - 1) / kSpmvWaves)),
+                           dim3(64 * kSpmvWaves), 0, s, row_ptr, col, val, x, y, nrows);
+    }
+    return hipGetLastError();
+}
+
 size_t lanczos_work_bytes(int64_t dim, int max_iter)
 {
     const size_t m = (size_t)max_iter + 1;
@@ -201,9 +248,12 @@ size_t lanczos_work_bytes(int64_t dim, int max_iter)
 }
 
 // Lanczos with full reorthogonalization.  Returns hipSuccess or the first
-// HIP error; *eval, *iters and evec (device, unit norm) on success.
+// HIP error; *eval, *iters and evec (device, unit norm) on success.  upper:
+// (row_ptr, col, val) hold the stored upper triangle (symmetric product
+// above) instead of the full matrix.
 hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t D, const double* x0,
-                       int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s)
+                       int max_iter, double tol, double* eval, int* iters, double* evec, void* work, hipStream_t s,
+                       bool upper)
 {
     double* V = (double*)work;  // [max_iter + 1][D]
     double* w = V + (size_t)(max_iter + 1) * D;
@@ -228,7 +278,7 @@ hipError_t run_lanczos(const int64_t* row_ptr, const int32_t* col, const float* 
     int m = 0;
     for (int j = 0; j < max_iter; j++) {
         double* vj = V + (size_t)j * D;
-        e = launch_spmv(row_ptr, col, val, vj, w, D, s);
+        e = upper ? launch_spmv_upper(row_ptr, col, val, vj, w, D, s) : launch_spmv(row_ptr, col, val, vj, w, D, s);
         if (e != hipSuccess) return e;
         // two projections against v_0..v_j; alpha_j is the v_j component
         double a = 0.0;

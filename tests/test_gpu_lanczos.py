@@ -217,3 +217,109 @@ def test_lanczos_with_kinetic_term(ci, p):
     say("lanczos kinetic", p, E, E_ref)
     assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
     assert abs(float(v.cpu().numpy() @ v_ref)) >= 1.0 - 1e-6
+
+
+# ---------------------------------------------------------------- the stored upper triangle as the operand
+def upper_matrix(ci, p, seed):
+    """The construction's own output: the upper-triangle CSR of count + fill."""
+    import torch
+
+    b = ci.ci_basis_build([p])
+    rp, nnz = ci.ci_hamiltonian_count(b)
+    tb = torch.from_numpy(si.tbme_f32(seed, b.n_tbme)).cuda()
+    col, val = ci.ci_hamiltonian_fill(b, tb, rp)
+    torch.cuda.synchronize()
+    return b, rp, col, val, tb
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1), (1, 1, 2, 0, 1), (3, 3, 2, 0, 1)])
+def test_spmv_upper_small(ci, p):
+    import torch
+
+    b, rp, col, val, _ = upper_matrix(ci, p, 22)
+    o = oracle_for(p, 22)
+    x = np.random.default_rng(5).standard_normal(o.dim)
+    y = torch.full((o.dim,), float("nan"), dtype=torch.float64, device="cuda")  # overwritten, not accumulated
+    ci.ci_hamiltonian_spmv_upper(b, 0, rp, col, val, torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    assert rel(y.cpu().numpy(), o.dense() @ x) <= VAL_TOL
+
+
+def test_spmv_upper_matches_full_li6(ci):
+    # the same product from the stored upper triangle and from the full
+    # matrix (a separate fill): sampled rows against the oracle, and the two
+    # GPU products against each other on every row
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp, col, val, _ = upper_matrix(ci, w["problem"], w["tbme_seed"])
+    D = b.info[0]["dim"]
+    x = torch.from_numpy(np.random.default_rng(6).standard_normal(D)).cuda()
+    y = ci.ci_hamiltonian_spmv_upper(b, 0, rp, col, val, x)
+    y2 = ci.ci_hamiltonian_spmv_upper(b, 0, rp, col, val, x)  # a second call overwrites
+    bf, rpf, colf, valf, _ = full_matrix(ci, w["problem"], w["tbme_seed"])
+    yf = ci.ci_hamiltonian_spmv(bf, 0, rpf, colf, valf, x)
+    torch.cuda.synchronize()
+    yf = yf.cpu().numpy()
+    assert rel(y.cpu().numpy(), yf) <= 1e-12
+    assert rel(y2.cpu().numpy(), yf) <= 1e-12
+    o = oracle_for(w["problem"], w["tbme_seed"])
+    rows = si.sample_rows(D, 60, seed=33)
+    counts, cols, vals = o.rows_full(rows)
+    xh = x.cpu().numpy()
+    ref = np.add.reduceat(vals * xh[cols], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    assert rel(y.cpu().numpy()[rows], ref) <= VAL_TOL
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1), (3, 3, 2, 0, 1), (1, 1, 4, 2, 1)])
+def test_lanczos_upper_small(ci, p):
+    b, rp, col, val, _ = upper_matrix(ci, p, 23)
+    o = oracle_for(p, 23)
+    E_ref, v_ref = o.lowest_eigenpair()
+    E, v, it = ci.ci_lanczos_upper(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    say("lanczos upper", p, "D", o.dim, "iters", it, "E", E, "ref", E_ref)
+    v = v.cpu().numpy()
+    assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
+    assert abs(np.linalg.norm(v) - 1.0) <= 1e-10
+    assert abs(float(v @ v_ref)) >= 1.0 - 1e-6
+
+
+def test_lanczos_upper_li6(ci):
+    # eigenpair from the construction's upper triangle; residual checked with
+    # the full-matrix product (independent of the scatter)
+    import torch
+
+    w = si.WORKLOADS["li6_nmax6"]
+    b, rp, col, val, _ = upper_matrix(ci, w["problem"], w["tbme_seed"])
+    E, v, it = ci.ci_lanczos_upper(b, 0, rp, col, val, max_iter=300, tol=1e-12)
+    bf, rpf, colf, valf, _ = full_matrix(ci, w["problem"], w["tbme_seed"])
+    Hv = ci.ci_hamiltonian_spmv(bf, 0, rpf, colf, valf, v)
+    E_full, _, _ = ci.ci_lanczos(bf, 0, rpf, colf, valf, max_iter=300, tol=1e-12)
+    torch.cuda.synchronize()
+    r = float(torch.linalg.norm(Hv - E * v))
+    say("lanczos upper li6 iters", it, "E", E, "full", E_full, "residual", r)
+    assert r <= 1e-5 * abs(E)
+    assert abs(E - E_full) <= 1e-9 * abs(E_full)
+
+
+@pytest.mark.parametrize("p", [(2, 2, 2, 0, 1), (3, 2, 2, 1, 1), (2, 2, 4, 0, 1)])
+def test_hellmann_feynman_gradient_upper(ci, p):
+    # the loop closed on the construction's own output: upper CSR -> Lanczos
+    # -> psi -> G = psi_i psi_j (doubled off the diagonal) on the same stored
+    # entries -> adjoint; against the oracle's dense eigenvector and FP64 adjoint
+    import torch
+
+    b, rp, col, val, tb = upper_matrix(ci, p, 24)
+    E, psi, _ = ci.ci_lanczos_upper(b, 0, rp, col, val, max_iter=300, tol=1e-13)
+    D = b.info[0]["dim"]
+    rows = torch.repeat_interleave(torch.arange(D, device="cuda"), torch.diff(rp))
+    c = col.long()
+    G = (psi[rows] * psi[c] * torch.where(rows == c, 1.0, 2.0).double()).float()
+    g = ci.ci_hamiltonian_vjp(b, rp, G).cpu().numpy().astype(np.float64)
+    o = oracle_for(p, 24)
+    E_ref, psi_ref = o.lowest_eigenpair()
+    g_ref = o.hellmann_feynman(psi_ref)
+    scale = np.abs(g_ref).max()
+    say("hellmann-feynman upper", p, "max err / scale", np.abs(g - g_ref).max() / scale)
+    assert abs(E - E_ref) <= VAL_TOL * abs(E_ref)
+    assert np.abs(g - g_ref).max() <= 1e-4 * scale
