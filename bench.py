@@ -461,7 +461,7 @@ def leg(ms, nnz, alg_bytes, profile):
 
 def parse_tuning(text):
     keys = ("row_waves", "row_grab", "adj_rows", "adj_tile_n", "adj_persistent", "adjk_rows", "adjk_tile_n",
-            "adjk_persistent", "row_xcd")
+            "adjk_persistent", "row_xcd", "adj_wide", "adj_flush")
     if "=" in text:
         return {k: int(v) for k, v in (kv.split("=") for kv in text.split(","))}
     return dict(zip(keys, (int(x) for x in text.split(","))))

@@ -124,8 +124,8 @@ typedef struct ci_basis ci_basis; /* opaque */
  * determinants times tp = max(1, adj_rows / tn) proton determinants -- whose
  * contributions are summed in one shared-memory table before they reach the
  * FP64 accumulators; the adjoint from stored words (ci_hamiltonian_vjp_keys)
- * has its own tile fields, adjk_rows and adjk_tile_n (default 96 and 8),
- * which ci_hamiltonian_tune leaves as they are. */
+ * has its own tile fields, adjk_rows, adjk_tile_n and adjk_persistent, which
+ * ci_hamiltonian_tune tunes when it is given room for the words. */
 typedef struct {
     int32_t row_waves;      /* wavefronts per workgroup of count and fill: 4 or 8 */
     int32_t row_grab;       /* 0: one grid over all rows; 1..4096: persistent, rows per grab */
@@ -137,6 +137,11 @@ typedef struct {
     int32_t adjk_persistent; /* adjoint from stored words: 0 one workgroup per tile, 1 persistent */
     int32_t row_xcd;        /* grids of rows or tiles (not persistent): 0 launch order; 1 each of the 8 XCDs */
                             /* (workgroup g runs on XCD g mod 8) takes one contiguous eighth of the grid   */
+    int32_t adj_wide;       /* walking adjoint: 0 8 wavefronts sharing a 4096-slot table (three workgroups */
+                            /* per CU); 1 16 wavefronts sharing a 16384-slot table (one per CU)            */
+    int32_t adj_flush;      /* both adjoints: 0 each tile writes its table as records, summed per bucket by */
+                            /* a second kernel; 1 each tile adds its table to FP64 accumulators (device    */
+                            /* atomics), then one conversion to FP32                                        */
 } ci_tuning;
 
 /* Thread-local text of the last error. */

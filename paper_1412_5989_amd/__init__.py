@@ -68,7 +68,8 @@ CI_V3_NONE, CI_V3_SYNTHETIC, CI_V3_IDENTITY = 0, 1, 2
 class ci_tuning(ctypes.Structure):
     _fields_ = [("row_waves", ctypes.c_int32), ("row_grab", ctypes.c_int32), ("adj_rows", ctypes.c_int32),
                 ("adj_tile_n", ctypes.c_int32), ("adj_persistent", ctypes.c_int32), ("adjk_rows", ctypes.c_int32),
-                ("adjk_tile_n", ctypes.c_int32), ("adjk_persistent", ctypes.c_int32), ("row_xcd", ctypes.c_int32)]
+                ("adjk_tile_n", ctypes.c_int32), ("adjk_persistent", ctypes.c_int32), ("row_xcd", ctypes.c_int32),
+                ("adj_wide", ctypes.c_int32), ("adj_flush", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

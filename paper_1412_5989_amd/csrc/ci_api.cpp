@@ -26,11 +26,12 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
                        const float* tbme, const int64_t* row_ptr, int64_t nrp, int32_t* col, float* val,
                        uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
 hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
-                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets,
+                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets, int chunks,
+                      double* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
                       int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
-int adjoint_slots(bool stored);
+int adjoint_slots(bool wide);
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** p);
 hipError_t launch_inclusive_scan(int64_t* x, int64_t n, int64_t* tmp, hipStream_t s);
@@ -349,7 +350,7 @@ std::vector<std::tuple<int, int, int, int, int, double, int>> tune_key(const std
     return k;
 }
 
-ci_tuning default_tuning() { return ci_tuning{4, 0, 32, 4, 1, 96, 8, 1, 0}; }
+ci_tuning default_tuning() { return ci_tuning{4, 0, 64, 8, 1, 96, 8, 1, 0, 0, 0}; }
 
 ci_tuning cached_tuning(const std::vector<ci_problem>& p)
 {
@@ -1235,9 +1236,20 @@ constexpr int64_t kHistCap = (int64_t)1 << 25;
 
 struct VjpLayout {
     int64_t ntiles = 0, nbuckets = 0, rec_cap = 0;
+    int chunks = 1;  // tile chunks per bucket in the reduction (> 1: FP64 partial sums at part)
     bool records = false;
-    size_t recs = 0, hist = 0, bytes = 0;
+    size_t recs = 0, hist = 0, part = 0, bytes = 0;
 };
+
+// The reduction runs one workgroup per (bucket, chunk of tiles); with few
+// buckets the tiles are cut into chunks so that about 512 workgroups share the
+// work, each chunk's FP64 partial sums taking n_tbme doubles (at most 256 MiB).
+static int reduce_chunks(int64_t nbuckets, int64_t n_tbme)
+{
+    int c = (int)std::min<int64_t>(kAdjMaxChunks, std::max<int64_t>(1, 512 / std::max<int64_t>(nbuckets, 1)));
+    while (c > 1 && (int64_t)c * n_tbme * (int64_t)sizeof(double) > ((int64_t)256 << 20)) c--;
+    return c;
+}
 
 static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, size_t limit = 0)
 {
@@ -1250,13 +1262,16 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
         v.nbuckets += nb;
         hist += nt * (nb + 1);
     }
-    v.records = hist <= kHistCap && b->n_tbme < 0xffffffffLL;
+    v.records = t.adj_flush == 0 && hist <= kHistCap && b->n_tbme < 0xffffffffLL;
     Layout L;
     (void)L.take<double>((size_t)b->n_tbme);
     if (v.records) {
-        v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored);
+        v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored || t.adj_wide);
         if (b->nnz_total >= 0) v.rec_cap = std::min<int64_t>(v.rec_cap, b->nnz_total / 2 + 1);
         v.hist = L.take<int64_t>((size_t)std::max<int64_t>(hist, 1));
+        v.chunks = reduce_chunks(v.nbuckets, b->n_tbme);
+        if (limit && L.bytes() + (size_t)v.chunks * b->n_tbme * sizeof(double) + 4096 > limit) v.chunks = 1;
+        if (v.chunks > 1) v.part = L.take<double>((size_t)v.chunks * b->n_tbme);
         if (limit) {  // a fixed buffer: the records get what is left of it
             const size_t left = limit > L.bytes() + 256 ? limit - L.bytes() - 256 : 0;
             v.rec_cap = std::min<int64_t>(v.rec_cap, (int64_t)(left / sizeof(uint64_t)));
@@ -1266,7 +1281,8 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
     }
     if (!v.records) {
         v.rec_cap = 0;
-        v.recs = v.hist = 0;
+        v.chunks = 1;
+        v.recs = v.hist = v.part = 0;
         L = Layout();
         (void)L.take<double>((size_t)b->n_tbme);
     }
@@ -1275,19 +1291,25 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
 }
 
 // Launch shapes the autotuner tries for the adjoint (tile rows, neutron width).
-static const int kWalkTiles[][2] = {{32, 4}, {32, 8}, {64, 8}, {64, 16}, {128, 8}, {128, 16}};
+// walking adjoint: (rows, neutron width, wide table)
+static const int kWalkTiles[][3] = {{32, 8, 0}, {64, 8, 0}, {64, 16, 0}, {128, 16, 0},
+                                    {128, 16, 1}, {256, 16, 1}, {256, 32, 1}, {512, 32, 1}};
 static const int kStoredTiles[][2] = {{64, 8}, {96, 8}, {128, 8}, {96, 16}, {192, 8}, {256, 16}};
 
 static size_t work_bytes_for(const ci_basis* b)
 {
     size_t w = std::max(vjp_layout(b, b->tune, false).bytes, vjp_layout(b, b->tune, true).bytes);
     ci_tuning t = b->tune;
+    t.adj_flush = 0;  // the records need the larger buffer
+    w = std::max(w, std::max(vjp_layout(b, t, false).bytes, vjp_layout(b, t, true).bytes));
     for (const auto& tl : kWalkTiles) {
         t.adj_rows = tl[0];
         t.adj_tile_n = tl[1];
+        t.adj_wide = tl[2];
         w = std::max(w, vjp_layout(b, t, false).bytes);
     }
     t = b->tune;
+    t.adj_flush = 0;
     for (const auto& tl : kStoredTiles) {
         t.adjk_rows = tl[0];
         t.adjk_tile_n = tl[1];
@@ -1306,7 +1328,8 @@ static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const fl
     ci_tuning tt = t;
     if (stored) tt.adj_persistent = t.adjk_persistent;
     return launch_vjp(b->d_bases, (int)b->info.size(), b->d_blk_basis, b->d_blk_local, b->nblocks, v.ntiles,
-                      b->d_tile_off, b->d_adjb, v.nbuckets, b->nrows, row_ptr, b->n_rowptr, grad_val, keys,
+                      b->d_tile_off, b->d_adjb, v.nbuckets, v.chunks, v.chunks > 1 ? (double*)(w + v.part) : nullptr,
+                      b->nrows, row_ptr, b->n_rowptr, grad_val, keys,
                       grad_tbme, (double*)w, v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap,
                       b->d_rec_count, v.records ? (int64_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, s);
 }
@@ -1371,7 +1394,8 @@ static bool tuning_ok(const ci_tuning& t)
            t.adj_rows <= 4096 && t.adj_tile_n >= 1 && t.adj_tile_n <= 4096 &&
            (t.adj_persistent == 0 || t.adj_persistent == 1) && t.adjk_rows >= 1 && t.adjk_rows <= 4096 &&
            t.adjk_tile_n >= 1 && t.adjk_tile_n <= 4096 && (t.adjk_persistent == 0 || t.adjk_persistent == 1) &&
-           (t.row_xcd == 0 || t.row_xcd == 1);
+           (t.row_xcd == 0 || t.row_xcd == 1) && (t.adj_wide == 0 || t.adj_wide == 1) &&
+           (t.adj_flush == 0 || t.adj_flush == 1);
 }
 
 int ci_basis_get_tuning(const ci_basis* b, ci_tuning* t)
@@ -1440,23 +1464,28 @@ int ci_hamiltonian_tune(ci_basis* b, const float* tbme, const int64_t* row_ptr, 
     // adjoint that walks the partner lists: tile (rows, neutron width) x (grid, persistent)
     have = false;
     for (const auto& tl : kWalkTiles)
-        for (int pers : {0, 1}) {
-            if (rc != CI_OK) break;
-            b->tune = best;
-            b->tune.adj_rows = tl[0];
-            b->tune.adj_tile_n = tl[1];
-            b->tune.adj_persistent = pers;
-            float ms = 0.0f;
-            rc = time_ms([&] { return vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s); }, reps, s, e0,
-                         e1, &ms);
-            if (rc == CI_OK && (!have || ms < best_ms)) {
-                best_ms = ms;
-                best.adj_rows = tl[0];
-                best.adj_tile_n = tl[1];
-                best.adj_persistent = pers;
-                have = true;
+        for (int pers : {0, 1})
+            for (int flush : {0, 1}) {
+                if (rc != CI_OK) break;
+                b->tune = best;
+                b->tune.adj_rows = tl[0];
+                b->tune.adj_tile_n = tl[1];
+                b->tune.adj_wide = tl[2];
+                b->tune.adj_persistent = pers;
+                b->tune.adj_flush = flush;
+                float ms = 0.0f;
+                rc = time_ms([&] { return vjp_launch(b, row_ptr, grad_val, grad_tbme, work, b->tune, s); }, reps, s, e0,
+                             e1, &ms);
+                if (rc == CI_OK && (!have || ms < best_ms)) {
+                    best_ms = ms;
+                    best.adj_rows = tl[0];
+                    best.adj_tile_n = tl[1];
+                    best.adj_wide = tl[2];
+                    best.adj_persistent = pers;
+                    best.adj_flush = flush;
+                    have = true;
+                }
             }
-        }
     // adjoint from stored words (when the caller gives room for them): the
     // fill writes the words once, then its own tiles x (grid, persistent)
     if (keys && rc == CI_OK) {

@@ -103,8 +103,10 @@ struct AdjBasis {
     int32_t nb;       // buckets of the basis
     int32_t bits;     // log2 of the positions per bucket
 };
-constexpr int kAdjBucketMinBits = 13;  // the reducing workgroup sums 2^13 positions at a time
+constexpr int kAdjBucketMinBits = 13;  // at least 2^13 positions per bucket
 constexpr int kAdjMaxBuckets = 1024;
+constexpr int kAdjReduceBits = 13;     // the reducing workgroup sums 2^13 positions at a time
+constexpr int kAdjMaxChunks = 16;      // tile chunks per bucket in the reduction
 
 CI_HD inline int adj_bucket_bits(int64_t ntbme)
 {

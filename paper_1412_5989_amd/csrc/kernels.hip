@@ -104,7 +104,7 @@ constexpr int kAdjWaves = 8;
 constexpr int kAdjSlotBits = 12;
 constexpr int kAdjKeysWaves = 16;
 constexpr int kAdjKeysSlotBits = 14;
-constexpr int kAdjProbes = 8;
+constexpr int kAdjProbes = 16;
 constexpr uint32_t kAdjEmpty = 0xffffffffu;
 
 __device__ __forceinline__ int64_t uniform64(int64_t v)
@@ -148,6 +148,27 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 }
 
 __device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+
+// Inclusive running maximum over the 64 lanes of values >= 0, DPP as above
+// (a lane with no source reads 0, which changes no maximum).
+__device__ __forceinline__ int wave_incl_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true));  // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true));  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// FP64 sum over the 64 lanes in a fixed butterfly order (every lane ends with
+// the same value, bit for bit, whatever the launch shape)
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 // largest t in [0, 64) with a[t] <= x, for a[0] <= x < a[64], a non-decreasing
 __device__ __forceinline__ int seg_search64(const int32_t* a, int x)
@@ -206,9 +227,40 @@ __device__ __forceinline__ bool rec_neg(uint64_t r) { return (r >> 56) & 1; }
 struct WaveLds {
     int32_t qpos[kQueue];  // offset from the row's first entry
     uint32_t qrec[kQueue]; // kind (0 diagonal, 1 one proton moved, 2 one neutron moved) | h << 8 | p << 16 | neg << 24
-    int32_t toff[kQueue + 1];
+    union {
+        int32_t toff[kQueue + 1];  // first term of each queued entry
+        double tsum[64];           // fill: one term per lane, summed by the entry's first lane
+    };
+    int32_t mark[64];  // load balancing: mark[x] = the lane whose item starts at x of the round
     uint8_t occ[128];  // occupied orbits of the row: protons, then neutrons
 };
+
+// Load-balanced search: lanes hold consecutive non-overlapping ranges
+// [start, start + len) of a sequence (ascending in the lane index); for the
+// round of 64 items [x0, x0 + 64) every lane x learns the lane whose range holds
+// item x0 + x.  A lane whose range starts inside the round writes its index at
+// that offset of mark[], then a running maximum carries each owner over the
+// items of its range.  carry: the owner of item x0 - 1 (-1 before the first
+// round); mark[] must hold values <= carry outside this round's starts (-1
+// after clear_marks, then the owners of earlier rounds).  Returns the owner,
+// in [0, 64) for every item of the sequence.
+__device__ __forceinline__ void clear_marks(WaveLds& L)
+{
+    L.mark[threadIdx.x & 63] = -1;
+    wave_sync();
+}
+__device__ __forceinline__ int owner_of(WaveLds& L, int start, int len, int x0, int* carry)
+{
+    const int lane = threadIdx.x & 63;
+    const int rel = start - x0;
+    if (len > 0 && rel >= 0 && rel < 64) L.mark[rel] = lane;
+    wave_sync();
+    // owners are shifted by one so that "none" is 0, the identity of the maximum
+    const int o = wave_incl_max(max(L.mark[lane], *carry) + 1);
+    *carry = __builtin_amdgcn_readlane(o, 63) - 1;
+    wave_sync();
+    return o > 0 ? o - 1 : 0;
+}
 
 __device__ __forceinline__ int q_kind(uint32_t q) { return (int)(q & 3); }
 __device__ __forceinline__ int q_h(uint32_t q) { return (int)((q >> 8) & 255); }
@@ -375,12 +427,119 @@ __device__ __forceinline__ int queued_term(const RowView& R, const WaveLds& L, u
     return tb_pos(B, cls, a, b, a, b);
 }
 
-// Evaluate (fill) or scatter (adjoint) the queued multi-term entries.
+// The u-th term of a queued one-nucleon difference (kind 1: a proton moved,
+// kind 2: a neutron moved; p the row's orbit, h the column's): the spectators
+// of the moved nucleon's own species in ascending order, then those of the
+// other species; with the kinetic term, a last one-body term.  Written with
+// selects so that the lanes of one round, whatever their kinds, take one path.
+__device__ __forceinline__ int single_term(const RowView& R, const WaveLds& L, uint32_t q, int u, bool* neg,
+                                           double* ob)
+{
+    const int Z = R.Z, NN = R.NN;
+    const bool prot = q_kind(q) == 1;
+    const int h = q_h(q), p = q_p(q);
+    *ob = 0.0;
+    if (u == Z + NN - 1) {  // the kinetic term a+_p a_h
+        *neg = q_neg(q);
+        *ob = kinetic_offdiag(*R.B, p, h);
+        return -1;
+    }
+    const int X = prot ? Z : NN;
+    const uint8_t* own = prot ? L.occ : L.occ + Z;
+    const uint8_t* oth = prot ? L.occ + Z : L.occ;
+    int cls, a, b, c, d;
+    if (u < X - 1) {  // same species: the spectator kk, skipping p
+        const int kk = own[u] >= p ? own[u + 1] : own[u];
+        cls = prot ? 0 : 2;
+        a = p;
+        b = kk;
+        c = h;
+        d = kk;
+    } else {  // the other species: proton first in a proton-neutron pair
+        const int o = oth[u - (X - 1)];
+        cls = 1;
+        a = prot ? p : o;
+        b = prot ? o : p;
+        c = prot ? h : o;
+        d = prot ? o : h;
+    }
+    bool s;
+    const int k = tb_pos_any(*R.B, cls, a, b, c, d, &s);
+    *neg = s ^ q_neg(q);
+    return k;
+}
+
+// A queue that holds only one-nucleon differences (the walk treats the
+// diagonal on its own), each with the same number of terms nt = A - 1 (+1
+// with the kinetic term).  A round takes floor(64 / nt) entries and lane
+// k * nt + u takes term u of entry k.  Fill: the entry's first lane sums its nt
+// terms from LDS in order (FP64, rounded once).  Adjoint: every term lane adds
+// phase * G of its entry to the term's table position.  No search, one path.
 template <int MODE>
+__device__ void flush_singles(const RowView& R, WaveLds& L, int qn)
+{
+    const int lane = threadIdx.x & 63;
+    const int nt = R.Z + R.NN - 1 + R.B->kinetic;
+    if (nt == 0) {  // a single nucleon and no kinetic term: the difference is 0
+        if (MODE == kFill)
+            for (int q = lane; q < qn; q += 64) {
+                const int64_t p = R.pos0 + L.qpos[q];
+                if (p < R.cap) glbw(R.val)[p] = 0.0f;
+            }
+        wave_sync();
+        return;
+    }
+    const int per = 64 / nt;
+    const float inv = 1.0f / (float)nt;
+    const int k = (int)(((float)lane + 0.5f) * inv);  // exact: the fraction stays >= 0.5 / 64 from an integer
+    const int u = lane - k * nt;
+    for (int q0 = 0; q0 < qn; q0 += per) {
+        const int q = q0 + k;
+        const bool act = k < per && q < qn;
+        if (MODE == kAdjoint) {
+            if (act) {
+                bool neg;
+                double ob;
+                const int kk = single_term(R, L, L.qrec[q], u, &neg, &ob);
+                const int64_t p = R.pos0 + L.qpos[q];
+                if (kk >= 0 && p < R.cap) {
+                    const float g = glb(R.gval)[p];
+                    adj_add(R, kk, neg ? -g : g);
+                }
+            }
+            continue;
+        }
+        double v = 0.0;
+        if (act) {
+            bool neg;
+            double ob;
+            const int kk = single_term(R, L, L.qrec[q], u, &neg, &ob);
+            const double x = kk >= 0 ? (double)glb(R.tbme)[kk] : ob;
+            v = neg ? -x : x;
+        }
+        L.tsum[lane] = v;
+        wave_sync();
+        if (act && u == 0) {
+            double sum = 0.0;
+            for (int i = 0; i < nt; i++) sum += L.tsum[lane + i];
+            const int64_t p = R.pos0 + L.qpos[q];
+            if (p < R.cap) glbw(R.val)[p] = (float)sum;
+        }
+        wave_sync();
+    }
+}
+
+// Evaluate (fill) or scatter (adjoint) the queued multi-term entries.
+// SINGLES: the queue holds no diagonal entry (the walk's own queue).
+template <int MODE, bool SINGLES>
 __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
 {
     const int lane = threadIdx.x & 63;
     if (qn == 0) return;
+    if (SINGLES && R.Z + R.NN - 1 + R.B->kinetic <= 64) {
+        flush_singles<MODE>(R, L, qn);
+        return;
+    }
     // first term of each queued entry
     int tot = 0;
     for (int base = 0; base < qn; base += 64) {
@@ -449,6 +608,54 @@ __device__ void flush_queue(const RowView& R, WaveLds& L, int qn)
     wave_sync();
 }
 
+// The row's diagonal entry: fill, its value, the single-particle sum plus every
+// occupied pair V_{ab,ab} (pp, nn, pn), one lane per pair, summed in FP64 in a
+// fixed order and rounded once; adjoint, G of the entry added to every
+// occupied pair's table position.  Lane u < Z(Z-1)/2 takes proton pair u in
+// colex order (u = y(y-1)/2 + x, x < y), the next N(N-1)/2 lanes the neutron
+// pairs, the last Z*N lanes the proton-neutron pairs.
+template <int MODE>
+__device__ void row_diagonal(const RowView& R, const WaveLds& L, int64_t p)
+{
+    const int lane = threadIdx.x & 63;
+    const BasisDev& B = *R.B;
+    const int Z = R.Z, NN = R.NN;
+    const int npp = Z * (Z - 1) / 2, nnn = NN * (NN - 1) / 2, tot = npp + nnn + Z * NN;
+    const float g = (MODE == kAdjoint && p < R.cap) ? glb(R.gval)[p] : 0.0f;
+    double acc = 0.0;
+    for (int u0 = 0; u0 < tot; u0 += 64) {
+        const int u = u0 + lane;
+        if (u < tot) {
+            int cls, a, b;
+            if (u < npp + nnn) {
+                const bool pp = u < npp;
+                const int t = pp ? u : u - npp;
+                int y = (int)(0.5f * (1.0f + sqrtf(1.0f + 8.0f * (float)t)));
+                while (y * (y - 1) / 2 > t) y--;
+                while ((y + 1) * y / 2 <= t) y++;
+                const int x = t - y * (y - 1) / 2;
+                const uint8_t* o = pp ? L.occ : L.occ + Z;
+                a = o[x];
+                b = o[y];
+                cls = pp ? 0 : 2;
+            } else {
+                const int t = u - npp - nnn;
+                const int ia = t / NN;
+                a = L.occ[ia];
+                b = L.occ[Z + (t - ia * NN)];
+                cls = 1;
+            }
+            const int k = tb_pos(B, cls, a, b, a, b);
+            if (MODE == kFill && k >= 0) acc += (double)glb(R.tbme)[k];
+            if (MODE == kAdjoint && k >= 0 && p < R.cap) adj_add(R, k, g);
+        }
+    }
+    if (MODE == kFill) {
+        acc = wave_sum_f64(acc);
+        if (lane == 0 && p < R.cap) glbw(R.val)[p] = (float)(acc + R.spe_sum);
+    }
+}
+
 // Occupied orbits of row (gP, gN) into L.occ, for the multi-term entries:
 // lane j < 2W holds determinant word j (protons, then neutrons), a wave scan
 // gives each word's first slot in occ, and (spe: for the fill's values) the
@@ -507,6 +714,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
 
     int64_t pos = 0;  // entries of the row so far
     int qn = 0;       // queued multi-term entries
+    int diag_at = -1; // position of the diagonal entry in the row
     for (int w0 = R.full ? 0 : bi; w0 < B.nblk; w0 += 64) {
         // 1. lane t: target block w0 + t of the window: proton partners of P,
         //    the row's neutron partners, column base
@@ -551,10 +759,12 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
         const int bincl = wave_incl_scan(np);
         const int bstart = bincl - np;  // first segment of the lane's block
         const int S = lane63(bincl);
+        int bcarry = -1;
         for (int s0 = 0; s0 < S; s0 += 64) {
             // 2. lane j: segment s0 + j = (target block, P'): its entry count
             const int s = s0 + lane;
-            const int t = lane_search64(bstart, s < S ? s : S - 1);
+            clear_marks(L);
+            const int t = owner_of(L, bstart, np, s0, &bcarry);
             const int t_bp = lane_read(bp, t), t_start = lane_read(bstart, t);
             const int t_col = lane_read(bcol, t), t_str = lane_read(bstr, t);
             const int t_n1 = lane_read(bn1, t), t_l1 = lane_read(bl1, t);
@@ -587,9 +797,11 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             }
             const int estart = eincl - len;  // first entry of the lane's segment
             // 3. the entries of the chunk, 64 consecutive ones per round
+            clear_marks(L);
+            int ecarry = -1;
             for (int e0 = 0; e0 < T; e0 += 64) {
                 const int e = e0 + lane;
-                const int j = lane_search64(estart, e < T ? e : T - 1);
+                const int j = owner_of(L, estart, len, e0, &ecarry);
                 const uint64_t prj = lane_read64(pr, j);
                 const int so2 = lane_read(so, j), sc2 = lane_read(sc, j), k = e - lane_read(estart, j);
                 bool special = false;
@@ -636,6 +848,13 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                         glbw(R.keys)[p] = special ? (kKeySpecial | qr)
                                                   : (key >= 0 ? ((uint32_t)key | (neg ? kKeyNeg : 0u)) : kKeyNone);
                 }
+                if (MODE != kCount) {
+                    // the diagonal entry (nothing moved) is treated on its own
+                    const bool diag = special && q_kind(qr) == 0;
+                    const uint64_t md = __ballot(diag);
+                    if (md) diag_at = __builtin_amdgcn_readlane((int)(pos + e), __ffsll((long long)md) - 1);
+                    special = special && !diag;
+                }
                 const uint64_t m = __ballot(special);
                 if (m) {
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -647,7 +866,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                     qn += __popcll(m);
                     wave_sync();
                     if (qn > kQueue - 64) {  // room for one more round
-                        flush_queue<MODE>(R, L, qn);
+                        flush_queue<MODE, true>(R, L, qn);
                         qn = 0;
                     }
                 }
@@ -655,7 +874,8 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             pos += T;
         }
     }
-    if (MODE != kCount) flush_queue<MODE>(R, L, qn);
+    if (MODE != kCount) flush_queue<MODE, true>(R, L, qn);
+    if (MODE != kCount && diag_at >= 0) row_diagonal<MODE>(R, L, R.pos0 + diag_at);
     return pos;
 }
 
@@ -701,12 +921,12 @@ __device__ void do_row_keys(const BasisDev& B, WaveLds& L, int bi, int r, RowVie
             qn += __popcll(m);
             wave_sync();
             if (qn > kQueue - 64) {  // room for one more round
-                flush_queue<kAdjoint>(R, L, qn);
+                flush_queue<kAdjoint, false>(R, L, qn);
                 qn = 0;
             }
         }
     }
-    flush_queue<kAdjoint>(R, L, qn);
+    flush_queue<kAdjoint, false>(R, L, qn);
 }
 
 template <int MODE>
@@ -1050,22 +1270,28 @@ __global__ void __launch_bounds__(64 * WAVES)
     }
 }
 
-// Sum of the adjoint's tile records: one workgroup per bucket of a basis'
-// table; hist holds, per tile, the absolute record position where each bucket
-// of the tile starts (and where the last ends).  The bucket's 2^bits positions are summed 8192 at a time in an FP64
-// shared-memory array (one pass over the bucket's record segments of every
-// tile of the basis per 8192 positions), plus the direct contributions in gacc,
-// and written once as FP32.
-constexpr int kReduceThreads = 1024;
-constexpr int kReduceWindow = 1 << kAdjBucketMinBits;
+// Sum of the adjoint's tile records.  hist holds, per tile, the absolute
+// record position where each bucket of the tile starts (and where the last
+// ends).  Workgroup (bucket, c) sums the bucket's records of the c-th of
+// `chunks` equal slices of the basis' tiles: each wavefront takes 64 tiles at a
+// time (lane l: tile t0 + l, its segment of the bucket) and every lane walks
+// its own segment, four records per step; the sums meet in an FP64
+// shared-memory array of up to 2^kAdjReduceBits positions (a larger bucket is
+// summed window by window).  With one chunk the workgroup adds the direct
+// contributions in gacc and writes each position once as FP32; with several it
+// writes its FP64 partial sums to part[c] and adjoint_combine adds the chunks.
+constexpr int kReduceThreads = 256;
+constexpr int kReduceWindow = 1 << kAdjReduceBits;
 
 __global__ void __launch_bounds__(kReduceThreads)
     adjoint_reduce(const BasisDev* __restrict__ bases, const AdjBasis* __restrict__ adjb, int nbases,
                    const uint64_t* __restrict__ recs, const int64_t* __restrict__ hist,
-                   const double* __restrict__ gacc, float* __restrict__ gtbme)
+                   const double* __restrict__ gacc, float* __restrict__ gtbme, int chunks,
+                   double* __restrict__ part, int64_t ntbme_all)
 {
     __shared__ double acc[kReduceWindow];
-    const int64_t bucket = blockIdx.x;
+    const int64_t bucket = blockIdx.x / chunks;
+    const int c = (int)(blockIdx.x - bucket * chunks);
     // basis of the bucket: largest x with bucket0 <= bucket
     int lo = 0, hi = nbases;
     while (hi - lo > 1) {
@@ -1079,25 +1305,59 @@ __global__ void __launch_bounds__(kReduceThreads)
     const int j = (int)(bucket - A.bucket0);
     const int64_t klo = (int64_t)j << A.bits;
     const int64_t khi = (klo + ((int64_t)1 << A.bits)) < ntbme ? klo + ((int64_t)1 << A.bits) : ntbme;
+    const int64_t ta = A.ntiles * c / chunks, tb = A.ntiles * (c + 1) / chunks;  // this chunk's tiles
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int kWaves = kReduceThreads / 64;
     for (int64_t w0 = klo; w0 < khi; w0 += kReduceWindow) {
         const int64_t w1 = (w0 + kReduceWindow) < khi ? w0 + kReduceWindow : khi;
-        for (int i = threadIdx.x; i < kReduceWindow; i += kReduceThreads) acc[i] = 0.0;
+        const int wn = (int)(w1 - w0);
+        for (int i = threadIdx.x; i < wn; i += kReduceThreads) acc[i] = 0.0;
         __syncthreads();
-        for (int64_t t = wid; t < A.ntiles; t += kWaves) {
-            const cptr<int64_t> hr = cst(hist) + A.hist0 + t * (A.nb + 1);
-            const int64_t s0 = uniform64(hr[j]), s1 = uniform64(hr[j + 1]);
-            for (int64_t p = s0 + lane; p < s1; p += 64) {
+        const int64_t kb = tbme0 + w0;  // global table position of acc[0]
+        for (int64_t t0 = ta + (int64_t)wid * 64; t0 < tb; t0 += (int64_t)kWaves * 64) {
+            const int64_t t = t0 + lane;
+            int64_t p = 0, e = 0;
+            if (t < tb) {
+                const cptr<int64_t> hr = cst(hist) + A.hist0 + t * (A.nb + 1);
+                p = hr[j];
+                e = hr[j + 1];
+            }
+            for (; p + 4 <= e; p += 4) {
+                uint64_t r[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) r[u] = glb(recs)[p + u];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int64_t k = (int64_t)(uint32_t)r[u] - kb;
+                    if (k >= 0 && k < wn) atomicAdd(&acc[k], (double)__uint_as_float((uint32_t)(r[u] >> 32)));
+                }
+            }
+            for (; p < e; p++) {
                 const uint64_t r = glb(recs)[p];
-                const int64_t k = (int64_t)(uint32_t)r - tbme0;
-                if (k >= w0 && k < w1) atomicAdd(&acc[k - w0], (double)__uint_as_float((uint32_t)(r >> 32)));
+                const int64_t k = (int64_t)(uint32_t)r - kb;
+                if (k >= 0 && k < wn) atomicAdd(&acc[k], (double)__uint_as_float((uint32_t)(r >> 32)));
             }
         }
         __syncthreads();
-        for (int64_t k = w0 + threadIdx.x; k < w1; k += kReduceThreads)
-            gtbme[tbme0 + k] = (float)(acc[k - w0] + gacc[tbme0 + k]);
+        if (chunks == 1) {
+            for (int i = threadIdx.x; i < wn; i += kReduceThreads)
+                gtbme[kb + i] = (float)(acc[i] + gacc[kb + i]);
+        } else {
+            for (int i = threadIdx.x; i < wn; i += kReduceThreads) part[(int64_t)c * ntbme_all + kb + i] = acc[i];
+        }
         __syncthreads();
+    }
+}
+
+// gtbme = gacc + the chunks' partial sums, in chunk order
+__global__ void __launch_bounds__(256) adjoint_combine(const double* __restrict__ gacc,
+                                                       const double* __restrict__ part, int chunks, int64_t n,
+                                                       float* __restrict__ gtbme)
+{
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        double v = gacc[k];
+        for (int c = 0; c < chunks; c++) v += part[(int64_t)c * n + k];
+        gtbme[k] = (float)v;
     }
 }
 
@@ -1307,7 +1567,8 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
 }
 
 hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
-                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets,
+                      int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets, int chunks,
+                      double* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
                       int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
@@ -1320,17 +1581,18 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
         const int rows = keys ? t.adjk_rows : t.adj_rows, tile_n = keys ? t.adjk_tile_n : t.adj_tile_n;
         hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, rows, tile_n,
                            tile_off, nbases, adjb);
-        const void* kern = keys ? (const void*)adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>
+        const bool wide = keys || t.adj_wide;  // 16 wavefronts, 16384-slot table
+        const void* kern = wide ? (const void*)adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>
                                 : (const void*)adjoint_kernel<kAdjWaves, kAdjSlotBits>;
-        const int threads = 64 * (keys ? kAdjKeysWaves : kAdjWaves);
+        const int threads = 64 * (wide ? kAdjKeysWaves : kAdjWaves);
         unsigned grid = (unsigned)ntiles;
         if (recs) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, rec_count);
         if (t.adj_persistent) {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, queue);
-            const unsigned res = resident_blocks(kern, threads, keys ? 7 : 6);
+            const unsigned res = resident_blocks(kern, threads, wide ? 7 : 6);
             grid = res < grid ? res : grid;
         }
-        if (keys)
+        if (wide)
             hipLaunchKernelGGL((adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>), dim3(grid), dim3(threads), 0, s,
                                bases, blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys,
                                gacc, use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count,
@@ -1342,16 +1604,18 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                                t.row_xcd);
     }
     if (ntbme > 0) {
-        if (use_table && walked && recs && nbuckets > 0)
-            hipLaunchKernelGGL(adjoint_reduce, dim3((unsigned)nbuckets), dim3(kReduceThreads), 0, s, bases, adjb,
-                               nbases, recs, hist, gacc, gtbme);
-        else
+        if (use_table && walked && recs && nbuckets > 0) {
+            const int ch = (chunks > 1 && part) ? chunks : 1;
+            hipLaunchKernelGGL(adjoint_reduce, dim3((unsigned)(nbuckets * ch)), dim3(kReduceThreads), 0, s, bases,
+                               adjb, nbases, recs, hist, gacc, gtbme, ch, part, ntbme);
+            if (ch > 1) hipLaunchKernelGGL(adjoint_combine, dim3(gz), dim3(256), 0, s, gacc, part, ch, ntbme, gtbme);
+        } else
             hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
     }
     return hipGetLastError();
 }
 
 // Slots of the shared-memory table of each adjoint (the records a tile can write).
-int adjoint_slots(bool stored) { return stored ? (1 << kAdjKeysSlotBits) : (1 << kAdjSlotBits); }
+int adjoint_slots(bool wide) { return wide ? (1 << kAdjKeysSlotBits) : (1 << kAdjSlotBits); }
 
 }  // namespace ci

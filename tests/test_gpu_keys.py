@@ -118,8 +118,8 @@ def test_vjp_keys_workload_sampled_rows(ci, name, nrows):
 
 
 # tiles of the stored-word adjoint (its own fields of the launch shape)
-ADJ_SHAPES = [dict(adjk_rows=r, adjk_tile_n=n, adj_persistent=q) for r, n in ((1, 1), (17, 5), (64, 8), (128, 16))
-              for q in (0, 1)]
+ADJ_SHAPES = [dict(adjk_rows=r, adjk_tile_n=n, adjk_persistent=q, adj_flush=f)
+              for r, n in ((1, 1), (17, 5), (64, 8), (128, 16)) for q in (0, 1) for f in (0, 1)]
 
 
 def test_vjp_keys_agrees_with_vjp_across_shapes(ci):

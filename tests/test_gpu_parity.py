@@ -365,9 +365,10 @@ def test_autograd_function(ci):
 
 SHAPES = [dict(row_waves=w, row_grab=g, row_xcd=0) for w in (4, 8) for g in (0, 1, 7)] + \
     [dict(row_waves=w, row_grab=0, row_xcd=1) for w in (4, 8)]
-ADJ_SHAPES = [dict(adj_rows=r, adj_tile_n=n, adj_persistent=q, row_xcd=0) for r, n in ((1, 1), (17, 5), (64, 16),
-                                                                                     (32, 64)) for q in (0, 1)] + \
-    [dict(adj_rows=r, adj_tile_n=n, adj_persistent=0, row_xcd=1) for r, n in ((17, 5), (128, 8))]
+ADJ_SHAPES = [dict(adj_rows=r, adj_tile_n=n, adj_persistent=q, row_xcd=0, adj_wide=w, adj_flush=f)
+              for r, n in ((1, 1), (17, 5), (64, 16), (32, 64)) for q in (0, 1) for w in (0, 1) for f in (0, 1)] + \
+    [dict(adj_rows=r, adj_tile_n=n, adj_persistent=0, row_xcd=1, adj_wide=w) for r, n in ((17, 5), (128, 8))
+     for w in (0, 1)] + [dict(adj_rows=512, adj_tile_n=32, adj_persistent=q, row_xcd=0, adj_wide=1) for q in (0, 1)]
 
 
 def test_launch_shapes_give_the_same_result(ci):
@@ -407,7 +408,7 @@ def test_tuning_validation_and_tuner(ci):
     seeds = [300 + k for k in range(len(probs))]
     b, rp, col, val, tb = run_forward(ci, probs, seeds)
     for bad in (dict(row_waves=6), dict(row_grab=-1), dict(adj_rows=0), dict(adj_tile_n=0), dict(adj_persistent=2),
-                dict(adjk_rows=0), dict(adjk_tile_n=4097), dict(row_xcd=2), dict(adjk_persistent=3)):
+                dict(adjk_rows=0), dict(adjk_tile_n=4097), dict(row_xcd=2), dict(adjk_persistent=3), dict(adj_wide=2), dict(adj_flush=2)):
         with pytest.raises(ci.CIError):
             b.tuning = bad
     rp_t = torch.from_numpy(rp).cuda()
@@ -420,7 +421,8 @@ def test_tuning_validation_and_tuner(ci):
     t = ci.ci_hamiltonian_tune(b, tbme, rp_t, c, v, G, reps=1, keys=kw)
     say("tuned", t)
     assert t["row_waves"] in (4, 8) and t["row_grab"] in (0, 1, 4, 16)
-    assert (t["adj_rows"], t["adj_tile_n"]) in ((32, 4), (32, 8), (64, 8), (64, 16), (128, 8), (128, 16))
+    assert (t["adj_rows"], t["adj_tile_n"], t["adj_wide"]) in (
+        (32, 8, 0), (64, 8, 0), (64, 16, 0), (128, 16, 0), (128, 16, 1), (256, 16, 1), (256, 32, 1), (512, 32, 1))
     assert (t["adjk_rows"], t["adjk_tile_n"]) in ((64, 8), (96, 8), (128, 8), (96, 16), (192, 8), (256, 16))
     assert t["adj_persistent"] in (0, 1) and t["adjk_persistent"] in (0, 1)
     torch.cuda.synchronize()
