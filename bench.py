@@ -268,10 +268,14 @@ def run_threebody(ci, torch, with_oracle, n1max=6, n3max=6):
     # algorithmic bytes of one launch of 1e6 requests: the block elements
     # (4 B each), the request (24 B) and the result (4 B)
     alg = 10 * (4 * int(elems.sum()) + 28 * len(req))
+    c = measured_counters("decouple_kernel_shells6_n3max6.md")
     res = {"workload": "three-body decoupling, shells 0..%d, triples inside %d, random requests (1e5 distinct)"
            % (n1max, n3max), "n_coupled": t.n_coupled, "requests_per_s_by_chunk": rates,
            "block_elements_per_request": float(elems.mean()),
-           "ms_per_launch_1e6": best, "alg_GBps_1e6": alg / (best * 1e-3) / 1e9}
+           "ms_per_launch_1e6": best, "alg_GBps_1e6": alg / (best * 1e-3) / 1e9,
+           "roofline": {"bound": "hbm", "achieved": alg / (best * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": alg,
+                        "traffic": c.get("traffic_bytes_per_launch") if c else None}}
     if with_oracle:
         # the oracle (plain Python sums) on a sample of the same requests, one core
         from oracle.threebody import ThreeBody as OracleTB
@@ -312,10 +316,12 @@ def run_three_body_term(ci, torch, prob, tbme_seed, with_oracle, reps=3):
     torch.cuda.synchronize()
     fill_ms = ev_f.mean_ms()
     alg = 8 * nnz + 8 * (D + 1)  # col + val per entry, row_ptr per row
+    c = measured_counters("h3_rows_fill_li6_nmax6.md")
     res = {"workload": "%s with a three-body term (d <= 3)" % "Z=%d N=%d Nmax=%d 2M=%d" % tuple(prob[:4]),
            "nnz": nnz, "count_ms_incl_sync": ev_c.mean_ms(), "fill_ms": fill_ms,
            "fill_nnz_per_s": nnz / (fill_ms * 1e-3), "fill_alg_GBps": alg / (fill_ms * 1e-3) / 1e9,
-           "fill_frac_of_hbm_peak": alg / (fill_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+           "fill_frac_of_hbm_peak": alg / (fill_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "fill_traffic": c.get("traffic_bytes_per_launch") if c else None}
     del col, val
     torch.cuda.empty_cache()
     # the full symmetric matrix with the term, and its lowest eigenpair (Lanczos)

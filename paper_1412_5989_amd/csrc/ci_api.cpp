@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <future>
 #include <map>
@@ -30,7 +31,7 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                       double* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
-                      int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+                      int32_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
 int adjoint_slots(bool wide);
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** p);
@@ -1224,8 +1225,8 @@ static int64_t count_tiles_of(const HostBasis& hb, const ci_tuning& t, bool stor
 
 // Work buffer of one adjoint launch: FP64 accumulators of the contributions
 // that find no table slot (or no room in the record buffer) [n_tbme], the
-// tile records (uint64: table position | FP32 bits << 32), the per-tile bucket
-// histograms (int64 positions).  The record buffer holds at most as many
+// tile records (uint64: table position | FP32 bits << 32), the bucket-major
+// histograms (int32 record positions, one per tile and bucket).  The record buffer holds at most as many
 // records as the tiles have slots, and no more than half the stored entries
 // (a tile writes one record per distinct table position it touched: about a
 // quarter to a third of the entries at the tuned shapes; a tile that finds
@@ -1268,7 +1269,8 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
     if (v.records) {
         v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored || t.adj_wide);
         if (b->nnz_total >= 0) v.rec_cap = std::min<int64_t>(v.rec_cap, b->nnz_total / 2 + 1);
-        v.hist = L.take<int64_t>((size_t)std::max<int64_t>(hist, 1));
+        v.rec_cap = std::min<int64_t>(v.rec_cap, INT32_MAX);  // record positions are int32 in the histograms
+        v.hist = L.take<int32_t>((size_t)std::max<int64_t>(hist, 1));
         v.chunks = reduce_chunks(v.nbuckets, b->n_tbme);
         if (limit && L.bytes() + (size_t)v.chunks * b->n_tbme * sizeof(double) + 4096 > limit) v.chunks = 1;
         if (v.chunks > 1) v.part = L.take<double>((size_t)v.chunks * b->n_tbme);
@@ -1331,7 +1333,7 @@ static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const fl
                       b->d_tile_off, b->d_adjb, v.nbuckets, v.chunks, v.chunks > 1 ? (double*)(w + v.part) : nullptr,
                       b->nrows, row_ptr, b->n_rowptr, grad_val, keys,
                       grad_tbme, (double*)w, v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap,
-                      b->d_rec_count, v.records ? (int64_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, s);
+                      b->d_rec_count, v.records ? (int32_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, s);
 }
 
 size_t ci_vjp_work_bytes(const ci_basis* b) { return (b && b->ready) ? work_bytes_for(b) : 0; }

@@ -74,6 +74,20 @@ __device__ __forceinline__ gmut<T> glbw(T* p)
 template <typename T>
 using lptr = __attribute__((address_space(3))) T*;
 
+// Element i of an array whose base is uniform (scalar registers), addressed
+// by a 32-bit byte offset: the load or store then takes the base + offset
+// form, with no 64-bit address arithmetic per lane (i * sizeof(T) < 2^32).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t i)
+{
+    return *(gptr<T>)((const __attribute__((address_space(1))) char*)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t i, T v)
+{
+    *(gmut<T>)((__attribute__((address_space(1))) char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 typedef int i32x4 __attribute__((ext_vector_type(4)));  // a BlockInfo record
 
 // The index tables and row_ptr do not change while a row kernel runs, so the
@@ -197,9 +211,11 @@ __device__ __forceinline__ int seg_search(const int32_t* a, int n, int x)
 // c protons and b, d neutrons for pn).  -1 if a pair is outside the table.
 __device__ __forceinline__ int tb_pos(const BasisDev& B, int cls, int a, int b, int c, int d)
 {
-    const int n = B.nsps;
-    const gptr<uint64_t> P = glb(B.pair) + cls * n * n;
-    const uint64_t e1 = P[a * n + b], e2 = P[c * n + d];
+    // 32-bit unsigned offsets from the table's base (an SGPR pair): the loads
+    // take their address as base + offset with no 64-bit arithmetic per lane
+    const uint32_t n = (uint32_t)B.nsps, o = (uint32_t)cls * n * n;
+    const uint64_t e1 = ld32(B.pair, o + (uint32_t)a * n + (uint32_t)b);
+    const uint64_t e2 = ld32(B.pair, o + (uint32_t)c * n + (uint32_t)d);
     const uint32_t l1 = (uint32_t)e1, l2 = (uint32_t)e2;
     if (e1 == kNoPair64 || e2 == kNoPair64 || (l1 >> 16) != (l2 >> 16)) return -1;
     const bool first = (l1 & 0xffff) <= (l2 & 0xffff);
@@ -774,7 +790,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             int so = 0, sc = 0;
             if (s < S) {
                 const int q = (t_bp & 0x7fffffff) + s - t_start;
-                pr = t_bp < 0 ? P12[q] : P1[q];
+                pr = t_bp < 0 ? P12[(uint32_t)q] : P1[(uint32_t)q];
                 const int dp = rec_d(pr), ipp = rec_local(pr);
                 sc = t_col + ipp * t_str;
                 if (w0 + t == bi && ipp < ip && !R.full) {
@@ -799,6 +815,10 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
             // 3. the entries of the chunk, 64 consecutive ones per round
             clear_marks(L);
             int ecarry = -1;
+            // entries of this chunk of segments start at row position pos:
+            // per-lane offsets from uniform bases stay 32-bit
+            const int64_t base = R.pos0 + pos;
+            const int room = (int)max((int64_t)0, min(R.cap - base, (int64_t)0x7fffffff));
             for (int e0 = 0; e0 < T; e0 += 64) {
                 const int e = e0 + lane;
                 const int j = owner_of(L, estart, len, e0, &ecarry);
@@ -810,7 +830,7 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                     const int dp = rec_d(prj);
                     uint64_t nr = 0;
                     if (dp != 2) {
-                        const int idx = (so2 & 0x7fffffff) + k;
+                        const uint32_t idx = (uint32_t)((so2 & 0x7fffffff) + k);
                         nr = so2 < 0 ? N12[idx] : N1[idx];
                     }
                     const int dn = rec_d(nr);
@@ -822,16 +842,17 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                     const int c = dp == 0 ? rec_h1(nr) : rec_h1(prj);
                     const int d = dp == 2 ? rec_h2(prj) : (dp == 1 ? rec_h1(nr) : rec_h2(nr));
                     const bool neg = rec_neg(prj) ^ rec_neg(nr);
-                    const int64_t p = R.pos0 + pos + e;
+                    const bool inb = e < room;
+                    const uint32_t ue = (uint32_t)e;
                     // upstream value first: its load overlaps the table lookup
-                    const float gv = (MODE == kAdjoint && !special && p < R.cap) ? glb(R.gval)[p] : 0.0f;
+                    const float gv = (MODE == kAdjoint && !special && inb) ? ld32(R.gval + base, ue) : 0.0f;
                     const int key = special ? -1 : tb_pos(B, cls, a, b, c, d);
-                    if (p < R.cap) {
+                    if (inb) {
                         if (MODE == kFill) {
-                            glbw(R.col)[p] = sc2 + (dp == 2 ? in : rec_local(nr));
+                            st32(R.col + base, ue, (int32_t)(sc2 + (dp == 2 ? in : rec_local(nr))));
                             if (!special) {
-                                const float x = key >= 0 ? glb(R.tbme)[key] : 0.0f;
-                                glbw(R.val)[p] = neg ? -x : x;
+                                const float x = key >= 0 ? ld32(R.tbme, (uint32_t)key) : 0.0f;
+                                st32(R.val + base, ue, neg ? -x : x);
                             }
                         } else if (key >= 0) {
                             adj_add(R, key, neg ? -gv : gv);
@@ -844,9 +865,9 @@ __device__ int64_t do_row(const BasisDev& B, WaveLds& L, int bi, int r, RowView&
                         qr = kind | ((uint32_t)rec_h1(mr) << 8) | ((uint32_t)rec_p1(mr) << 16) |
                              ((uint32_t)rec_neg(mr) << 24);
                     }
-                    if (MODE == kFill && R.keys && p < R.cap)
-                        glbw(R.keys)[p] = special ? (kKeySpecial | qr)
-                                                  : (key >= 0 ? ((uint32_t)key | (neg ? kKeyNeg : 0u)) : kKeyNone);
+                    if (MODE == kFill && R.keys && inb)
+                        st32(R.keys + base, ue, special ? (kKeySpecial | qr)
+                                                        : (key >= 0 ? ((uint32_t)key | (neg ? kKeyNeg : 0u)) : kKeyNone));
                 }
                 if (MODE != kCount) {
                     // the diagonal entry (nothing moved) is treated on its own
@@ -1133,7 +1154,7 @@ __global__ void __launch_bounds__(64 * WAVES)
                    const float* __restrict__ gval, const uint32_t* __restrict__ keys, double* __restrict__ gacc,
                    int use_table, int persistent, unsigned long long* __restrict__ queue,
                    const AdjBasis* __restrict__ adjb, uint64_t* __restrict__ recs, int64_t rec_cap,
-                   unsigned long long* __restrict__ rec_count, int64_t* __restrict__ hist, int xcd)
+                   unsigned long long* __restrict__ rec_count, int32_t* __restrict__ hist, int xcd)
 {
     constexpr int kSlots = 1 << SLOT_BITS;
     constexpr int kThreads = 64 * WAVES;
@@ -1240,8 +1261,11 @@ __global__ void __launch_bounds__(64 * WAVES)
                 }
                 __syncthreads();
                 const int64_t at = t_base;
-                const gmut<int64_t> hrow = glbw(hist) + A.hist0 + (g - A.tile0) * (A.nb + 1);
-                for (int c = threadIdx.x; c <= A.nb; c += kThreads) hrow[c] = at >= 0 ? at + bcur[c] : 0;
+                // column g - tile0 of the basis' histogram, bucket-major (the
+                // reduction reads one bucket's row of every tile contiguously)
+                const gmut<int32_t> hcol = glbw(hist) + A.hist0 + (g - A.tile0);
+                for (int c = threadIdx.x; c <= A.nb; c += kThreads)
+                    hcol[(int64_t)c * A.ntiles] = at >= 0 ? (int32_t)(at + bcur[c]) : 0;
                 __syncthreads();
                 if (at >= 0) {
                     const gmut<uint64_t> out = glbw(recs) + at;
@@ -1270,9 +1294,9 @@ __global__ void __launch_bounds__(64 * WAVES)
     }
 }
 
-// Sum of the adjoint's tile records.  hist holds, per tile, the absolute
-// record position where each bucket of the tile starts (and where the last
-// ends).  Workgroup (bucket, c) sums the bucket's records of the c-th of
+// Sum of the adjoint's tile records.  hist holds, per basis, nb + 1 rows of
+// one int32 per tile: row j, the absolute record position where the tile's
+// records of bucket j start (row nb: where its last bucket ends).  Workgroup (bucket, c) sums the bucket's records of the c-th of
 // `chunks` equal slices of the basis' tiles: each wavefront takes 64 tiles at a
 // time (lane l: tile t0 + l, its segment of the bucket) and every lane walks
 // its own segment, four records per step; the sums meet in an FP64
@@ -1285,7 +1309,7 @@ constexpr int kReduceWindow = 1 << kAdjReduceBits;
 
 __global__ void __launch_bounds__(kReduceThreads)
     adjoint_reduce(const BasisDev* __restrict__ bases, const AdjBasis* __restrict__ adjb, int nbases,
-                   const uint64_t* __restrict__ recs, const int64_t* __restrict__ hist,
+                   const uint64_t* __restrict__ recs, const int32_t* __restrict__ hist,
                    const double* __restrict__ gacc, float* __restrict__ gtbme, int chunks,
                    double* __restrict__ part, int64_t ntbme_all)
 {
@@ -1318,9 +1342,9 @@ __global__ void __launch_bounds__(kReduceThreads)
             const int64_t t = t0 + lane;
             int64_t p = 0, e = 0;
             if (t < tb) {
-                const cptr<int64_t> hr = cst(hist) + A.hist0 + t * (A.nb + 1);
-                p = hr[j];
-                e = hr[j + 1];
+                const gptr<int32_t> hr = glb(hist) + A.hist0 + t;
+                p = hr[(int64_t)j * A.ntiles];
+                e = hr[(int64_t)(j + 1) * A.ntiles];
             }
             for (; p + 4 <= e; p += 4) {
                 uint64_t r[4];
@@ -1571,7 +1595,7 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                       double* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
-                      int64_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+                      int32_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
