@@ -431,11 +431,14 @@ def run_batched(ci, torch, steps, warmup, stored, tuning_text=None):
     # adjoint (4 B per entry + 8 B per row + 4 B per table element) of every basis
     alg = 12 * tot + 16 * (dim_total + len(probs)) + 4 * b.n_tbme
     achieved = alg / (ms * 1e-3) / 1e9
+    # traffic of one replay: the committed counter summaries of its two kernels
+    cf, ca = measured_counters("row_kernel_fill_batch64.md"), measured_counters("adjoint_kernel_batch64.md")
+    traffic = (cf["traffic_bytes_per_launch"] + ca["traffic_bytes_per_launch"]) if (cf and ca and not stored) else None
     out = {"bases": len(probs), "dim_total": dim_total, "nnz_total": tot, "n_tbme_total": b.n_tbme,
            "ms_per_replay": ms, "nnz_per_s": tot / (ms * 1e-3), "setup_s": t_setup,
            "graph": "fill + vjp of all bases, one capture", "adjoint": "stored" if stored else "walk",
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_replay": alg},
+                        "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_replay": alg, "traffic": traffic},
            "tuning": dict(tuning, tune_s=t_tune, source="fixed" if tuning_text else "autotuner")}
     b.free()
     return out
