@@ -334,6 +334,25 @@ struct RowView {
     double spe_sum;
 };
 
+// FP32 add to an LDS word by a compare-and-swap loop on its bits.  The LDS
+// of this device executes ds_add_f32 far below its other atomics (measured on
+// random addresses of a 4096-word table: 0.33 lane-operations per CU cycle,
+// against 4.9 for a 32-bit compare-and-swap and 2.7 for this loop, which
+// usually takes one read and one compare-and-swap).
+__device__ __forceinline__ void lds_add_f32(lptr<float> p, float g)
+{
+    const lptr<uint32_t> q = (lptr<uint32_t>)p;
+    uint32_t old = *q;
+    for (;;) {
+        uint32_t exp = old;
+        const uint32_t nw = __float_as_uint(__uint_as_float(old) + g);
+        if (__hip_atomic_compare_exchange_strong(q, &exp, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        old = exp;
+    }
+}
+
 // Adjoint contribution g to table position k of the row's basis.
 __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
 {
@@ -346,7 +365,7 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
             const bool won = __hip_atomic_compare_exchange_strong(R.hkey + s, &cur, gk, __ATOMIC_RELAXED,
                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (won || cur == gk) {
-                __hip_atomic_fetch_add(R.hval + s, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                lds_add_f32(R.hval + s, g);
                 return;
             }
             s = (s + 1) & ((1u << R.hbits) - 1);
