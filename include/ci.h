@@ -123,7 +123,7 @@ typedef struct ci_basis ci_basis; /* opaque */
  * workgroup a tile of rows of one block -- tn = min(adj_tile_n, |Kn|) neutron
  * determinants times tp = max(1, adj_rows / tn) proton determinants -- whose
  * contributions are summed in one shared-memory table before they reach the
- * FP64 accumulators; the adjoint from stored words (ci_hamiltonian_vjp_keys)
+ * int64 fixed-point accumulators; the adjoint from stored words (ci_hamiltonian_vjp_keys)
  * has its own tile fields, adjk_rows, adjk_tile_n and adjk_persistent, which
  * ci_hamiltonian_tune tunes when it is given room for the words. */
 typedef struct {
@@ -140,7 +140,7 @@ typedef struct {
     int32_t adj_wide;       /* walking adjoint: 0 8 wavefronts sharing a 4096-slot table (three workgroups */
                             /* per CU); 1 16 wavefronts sharing a 16384-slot table (one per CU)            */
     int32_t adj_flush;      /* both adjoints: 0 each tile writes its table as records, summed per bucket by */
-                            /* a second kernel; 1 each tile adds its table to FP64 accumulators (device    */
+                            /* a second kernel; 1 each tile adds its table to int64 accumulators (device   */
                             /* atomics), then one conversion to FP32                                        */
 } ci_tuning;
 
@@ -199,8 +199,17 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
 
 /* Adjoint of the fill with respect to the two-body table: for L = sum_e
  * grad_val[e] * val[e], writes grad_tbme = dL/dtbme (device FP32, overwritten).
- * The pair / phase structure is recomputed, not stored.  work: device scratch
- * of at least ci_vjp_work_bytes(b) bytes (FP64 accumulators).  Asynchronous. */
+ * The pair / phase structure is recomputed, not stored.  The sums are in
+ * fixed point: each contribution g becomes the integer rint(g * 2^s), with s
+ * per basis from max |grad_val| over its entries and the rows of an adjoint
+ * tile (so that no sum can overflow), the integers are added exactly (in LDS,
+ * then in int64), and each total is scaled back and rounded once to FP32.
+ * Integer sums have no order, so the result is the same bit for bit on every
+ * run and for every adj_flush, adj_persistent, adj_wide and row_xcd at one
+ * tile shape (adj_rows, adj_tile_n); other tile shapes round the contributions
+ * on another grid and agree to ~1e-6 of max |grad_val|.  grad_val must be
+ * finite.  work: device scratch of at least ci_vjp_work_bytes(b) bytes (int64
+ * accumulators, tile records).  Asynchronous. */
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val,
                        float* grad_tbme, void* work, size_t work_bytes, ci_stream stream);
 
@@ -224,12 +233,12 @@ int ci_hamiltonian_vjp_keys(const ci_basis* b, const int64_t* row_ptr, const uin
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
- * adjoint as ci_hamiltonian_vjp (same arguments without the work buffer, same
- * result to rounding), with its scratch (FP64 accumulators, tile records and
+ * adjoint as ci_hamiltonian_vjp (same arguments without the work buffer, the
+ * same bits at the same launch shapes), with its scratch (int64 accumulators, tile records and
  * histograms) in a fixed device array of the library, 64 MiB per GPU
  * (ci_vjp_noalloc_scratch_bytes), held from the first call on a GPU until the
  * process ends.  Calls nothing that allocates.  The table of the handle must
- * fit the scratch as FP64 accumulators (n_tbme * 8 bytes, with room to spare;
+ * fit the scratch as int64 accumulators (n_tbme * 8 bytes, with room to spare;
  * else CI_ESPACE before any launch); the tile records get the rest (a tile
  * that finds no room adds its sums to the accumulators).  Every call on one
  * GPU shares the array: calls that overlap on one GPU (other streams, other

@@ -28,10 +28,11 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
                        uint32_t* keys, const ci_tuning& t, unsigned long long* queue, int full, hipStream_t s);
 hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
                       int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets, int chunks,
-                      double* part,
+                      unsigned long long* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
-                      float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
-                      int32_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s);
+                      float* gtbme, unsigned long long* gacc, uint64_t* recs, int64_t rec_cap,
+                      unsigned long long* rec_count, int32_t* hist, int64_t ntbme, const ci_tuning& t,
+                      unsigned long long* queue, unsigned long long* gscale, hipStream_t s);
 int adjoint_slots(bool wide);
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** p);
@@ -400,6 +401,7 @@ struct ci_basis {
     int64_t* d_tile_off = nullptr;          // adjoint tiles per block (inclusive scan), [nblocks + 1]
     AdjBasis* d_adjb = nullptr;             // per-basis layout of the adjoint's tile records
     unsigned long long* d_rec_count = nullptr;  // records written by the adjoint's tiles
+    unsigned long long* d_gscale = nullptr;     // per basis: the adjoint's fixed-point scale (max |G|, then the shift)
     mutable int64_t nnz_total = -1;         // stored entries of all bases (after the upper-triangle count)
     int nblocks = 0;
     ci_tuning tune{};
@@ -431,7 +433,7 @@ struct BuildPlan {
     std::vector<UOff> uo;
     size_t pair_start = 0, host_bytes = 0;
     size_t o_row0 = 0, o_first = 0, o_last = 0, o_blk_basis = 0, o_blk_local = 0;
-    size_t o_bases = 0, o_scan = 0, o_nnz = 0, o_queue = 0, o_rec_count = 0, o_tile_off = 0, o_adjb = 0;
+    size_t o_bases = 0, o_scan = 0, o_nnz = 0, o_queue = 0, o_rec_count = 0, o_gscale = 0, o_tile_off = 0, o_adjb = 0;
     size_t bytes = 0;
     int nblocks = 0;
 };
@@ -565,6 +567,7 @@ int plan_build(const ci_problem* probs, int32_t n_probs, BuildPlan& P, std::stri
     P.o_nnz = L.take<int64_t>(n_probs);
     P.o_queue = L.take<unsigned long long>(1);
     P.o_rec_count = L.take<unsigned long long>(1);
+    P.o_gscale = L.take<unsigned long long>(n_probs);
     P.o_tile_off = L.take<int64_t>(P.nblocks + 1);
     P.o_adjb = L.take<AdjBasis>(n_probs);
     P.bytes = L.bytes();
@@ -871,6 +874,7 @@ int ci_basis_build(const ci_problem* probs, int32_t n_probs, ci_basis_info* info
     h->d_nnz = (int64_t*)D(P->o_nnz);
     h->d_queue = (unsigned long long*)D(P->o_queue);
     h->d_rec_count = (unsigned long long*)D(P->o_rec_count);
+    h->d_gscale = (unsigned long long*)D(P->o_gscale);
     h->d_blk_basis = (int32_t*)D(P->o_blk_basis);
     h->d_blk_local = (int32_t*)D(P->o_blk_local);
     h->d_tile_off = (int64_t*)D(P->o_tile_off);
@@ -1223,9 +1227,10 @@ static int64_t count_tiles_of(const HostBasis& hb, const ci_tuning& t, bool stor
     return n;
 }
 
-// Work buffer of one adjoint launch: FP64 accumulators of the contributions
-// that find no table slot (or no room in the record buffer) [n_tbme], the
-// tile records (uint64: table position | FP32 bits << 32), the bucket-major
+// Work buffer of one adjoint launch: int64 fixed-point accumulators of the
+// contributions that find no table slot (or no room in the record buffer)
+// [n_tbme], the tile records (uint64: table position | int32 fixed-point tile
+// sum << 32), the bucket-major
 // histograms (int32 record positions, one per tile and bucket).  The record buffer holds at most as many
 // records as the tiles have slots, and no more than half the stored entries
 // (a tile writes one record per distinct table position it touched: about a
@@ -1237,18 +1242,18 @@ constexpr int64_t kHistCap = (int64_t)1 << 25;
 
 struct VjpLayout {
     int64_t ntiles = 0, nbuckets = 0, rec_cap = 0;
-    int chunks = 1;  // tile chunks per bucket in the reduction (> 1: FP64 partial sums at part)
+    int chunks = 1;  // tile chunks per bucket in the reduction (> 1: int64 partial sums at part)
     bool records = false;
     size_t recs = 0, hist = 0, part = 0, bytes = 0;
 };
 
 // The reduction runs one workgroup per (bucket, chunk of tiles); with few
 // buckets the tiles are cut into chunks so that about 512 workgroups share the
-// work, each chunk's FP64 partial sums taking n_tbme doubles (at most 256 MiB).
+// work, each chunk's int64 partial sums taking n_tbme words (at most 256 MiB).
 static int reduce_chunks(int64_t nbuckets, int64_t n_tbme)
 {
     int c = (int)std::min<int64_t>(kAdjMaxChunks, std::max<int64_t>(1, 512 / std::max<int64_t>(nbuckets, 1)));
-    while (c > 1 && (int64_t)c * n_tbme * (int64_t)sizeof(double) > ((int64_t)256 << 20)) c--;
+    while (c > 1 && (int64_t)c * n_tbme * (int64_t)sizeof(int64_t) > ((int64_t)256 << 20)) c--;
     return c;
 }
 
@@ -1265,15 +1270,15 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
     }
     v.records = t.adj_flush == 0 && hist <= kHistCap && b->n_tbme < 0xffffffffLL;
     Layout L;
-    (void)L.take<double>((size_t)b->n_tbme);
+    (void)L.take<int64_t>((size_t)b->n_tbme);
     if (v.records) {
         v.rec_cap = v.ntiles * (int64_t)adjoint_slots(stored || t.adj_wide);
         if (b->nnz_total >= 0) v.rec_cap = std::min<int64_t>(v.rec_cap, b->nnz_total / 2 + 1);
         v.rec_cap = std::min<int64_t>(v.rec_cap, INT32_MAX);  // record positions are int32 in the histograms
         v.hist = L.take<int32_t>((size_t)std::max<int64_t>(hist, 1));
         v.chunks = reduce_chunks(v.nbuckets, b->n_tbme);
-        if (limit && L.bytes() + (size_t)v.chunks * b->n_tbme * sizeof(double) + 4096 > limit) v.chunks = 1;
-        if (v.chunks > 1) v.part = L.take<double>((size_t)v.chunks * b->n_tbme);
+        if (limit && L.bytes() + (size_t)v.chunks * b->n_tbme * sizeof(int64_t) + 4096 > limit) v.chunks = 1;
+        if (v.chunks > 1) v.part = L.take<int64_t>((size_t)v.chunks * b->n_tbme);
         if (limit) {  // a fixed buffer: the records get what is left of it
             const size_t left = limit > L.bytes() + 256 ? limit - L.bytes() - 256 : 0;
             v.rec_cap = std::min<int64_t>(v.rec_cap, (int64_t)(left / sizeof(uint64_t)));
@@ -1286,7 +1291,7 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
         v.chunks = 1;
         v.recs = v.hist = v.part = 0;
         L = Layout();
-        (void)L.take<double>((size_t)b->n_tbme);
+        (void)L.take<int64_t>((size_t)b->n_tbme);
     }
     v.bytes = L.bytes();
     return v;
@@ -1330,10 +1335,11 @@ static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const fl
     ci_tuning tt = t;
     if (stored) tt.adj_persistent = t.adjk_persistent;
     return launch_vjp(b->d_bases, (int)b->info.size(), b->d_blk_basis, b->d_blk_local, b->nblocks, v.ntiles,
-                      b->d_tile_off, b->d_adjb, v.nbuckets, v.chunks, v.chunks > 1 ? (double*)(w + v.part) : nullptr,
-                      b->nrows, row_ptr, b->n_rowptr, grad_val, keys,
-                      grad_tbme, (double*)w, v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap,
-                      b->d_rec_count, v.records ? (int32_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, s);
+                      b->d_tile_off, b->d_adjb, v.nbuckets, v.chunks,
+                      v.chunks > 1 ? (unsigned long long*)(w + v.part) : nullptr, b->nrows, row_ptr, b->n_rowptr,
+                      grad_val, keys, grad_tbme, (unsigned long long*)w,
+                      v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap, b->d_rec_count,
+                      v.records ? (int32_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, b->d_gscale, s);
 }
 
 size_t ci_vjp_work_bytes(const ci_basis* b) { return (b && b->ready) ? work_bytes_for(b) : 0; }
@@ -1376,8 +1382,8 @@ int ci_hamiltonian_vjp_noalloc(const ci_basis* b, const int64_t* row_ptr, const 
     if (!grad_val && b->nrows > 0) return fail(CI_EINVAL, "null pointer");
     if (b->n_tbme > 0 && !grad_tbme) return fail(CI_EINVAL, "null pointer");
     const size_t cap = noalloc_scratch_bytes();
-    // the FP64 accumulators must fit; the tile records take what is left
-    if ((size_t)b->n_tbme * sizeof(double) + 256 > cap)
+    // the int64 accumulators must fit; the tile records take what is left
+    if ((size_t)b->n_tbme * sizeof(int64_t) + 256 > cap)
         return fail(CI_ESPACE, "the two-body tables of this handle (" + std::to_string(b->n_tbme) +
                                    " elements) exceed the fixed scratch of " + std::to_string(cap) + " bytes");
     void* scr = nullptr;

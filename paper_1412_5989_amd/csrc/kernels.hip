@@ -61,10 +61,10 @@ __device__ __forceinline__ gptr<T> glb(const T* p)
 }
 template <typename T>
 using gmut = __attribute__((address_space(1))) T*;
-// relaxed device-scope FP64 add in L2 (hardware atomic with -munsafe-fp-atomics)
-__device__ __forceinline__ void atomic_add_f64(gmut<double> p, double v)
+// relaxed device-scope add of a signed 64-bit integer (two's complement) in L2
+__device__ __forceinline__ void atomic_add_i64(gmut<unsigned long long> p, int64_t v)
 {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
 __device__ __forceinline__ gmut<T> glbw(T* p)
@@ -315,14 +315,15 @@ constexpr uint32_t kKeyNone = 0x3fffffffu;
 struct RowView {
     const BasisDev* B;
     const float* tbme;  // this basis' table (fill)
-    double* gacc;       // this basis' accumulators (adjoint)
+    unsigned long long* gacc;  // this basis' int64 fixed-point accumulators (adjoint)
     int64_t tbme0;      // this basis' first table position in the batch
     // LDS accumulator table of the workgroup (adjoint); used only when
     // use_table is set (an LDS address can be 0, so no null test on it)
     lptr<uint32_t> hkey;
-    lptr<float> hval;
+    lptr<int32_t> hval;
     bool use_table;
     int hbits;  // the table has 1 << hbits slots
+    int qshift; // adjoint contribution g counts as the integer rint(g * 2^qshift)
     const float* gval;  // upstream values (adjoint)
     int32_t* col;
     float* val;
@@ -334,28 +335,20 @@ struct RowView {
     double spe_sum;
 };
 
-// FP32 add to an LDS word by a compare-and-swap loop on its bits.  The LDS
-// of this device executes ds_add_f32 far below its other atomics (measured on
-// random addresses of a 4096-word table: 0.33 lane-operations per CU cycle,
-// against 4.9 for a 32-bit compare-and-swap and 2.7 for this loop, which
-// usually takes one read and one compare-and-swap).
-__device__ __forceinline__ void lds_add_f32(lptr<float> p, float g)
-{
-    const lptr<uint32_t> q = (lptr<uint32_t>)p;
-    uint32_t old = *q;
-    for (;;) {
-        uint32_t exp = old;
-        const uint32_t nw = __float_as_uint(__uint_as_float(old) + g);
-        if (__hip_atomic_compare_exchange_strong(q, &exp, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
-            return;
-        old = exp;
-    }
-}
-
-// Adjoint contribution g to table position k of the row's basis.
+// Adjoint contribution g to table position k of the row's basis, in fixed
+// point: q = rint(g * 2^qshift), an exact power-of-two scaling and one
+// rounding.  Integer sums do not depend on their order, so the gradient is the
+// same bit for bit whatever the tile shape, the flush and the order in which
+// wavefronts and atomics meet.  The shift is chosen from max |G| and the rows
+// of a tile so that a tile's sum in an int32 LDS slot cannot overflow: a row
+// adds at most one contribution to any table position (its moves are distinct
+// and a move and its reverse cannot both start from one determinant), so a slot
+// receives at most one per row of the tile.  LDS sums use the native integer
+// add (this device runs ds_add_f32 at 0.33 lane-operations per CU cycle on
+// random addresses of a 4096-word table, far below its integer atomics).
 __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
 {
+    const int32_t q = (int32_t)__float2int_rn(ldexpf(g, R.qshift));
     if (R.use_table) {
         const uint32_t gk = (uint32_t)(R.tbme0 + k);
         uint32_t s = (gk * 2654435761u) >> (32 - R.hbits);
@@ -365,13 +358,19 @@ __device__ __forceinline__ void adj_add(const RowView& R, int k, float g)
             const bool won = __hip_atomic_compare_exchange_strong(R.hkey + s, &cur, gk, __ATOMIC_RELAXED,
                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (won || cur == gk) {
-                lds_add_f32(R.hval + s, g);
+                __hip_atomic_fetch_add(R.hval + s, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return;
             }
             s = (s + 1) & ((1u << R.hbits) - 1);
         }
     }
-    atomic_add_f64(glbw(R.gacc) + k, (double)g);
+    atomic_add_i64(glbw(R.gacc) + k, (int64_t)q);
+}
+
+// An int64 fixed-point sum (two's complement in the word) as FP32.
+__device__ __forceinline__ float fixed_to_f32(unsigned long long v, int qshift)
+{
+    return (float)ldexp((double)(int64_t)v, -qshift);
 }
 
 // number of terms of a queued entry: two-body terms, plus the one-body
@@ -973,8 +972,9 @@ template <int MODE>
 __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int r, const float* __restrict__ tbme,
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
-                                           double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, int hbits, bool full, uint32_t* keys, WaveLds& L);
+                                           unsigned long long* __restrict__ gacc, lptr<uint32_t> hkey,
+                                           lptr<int32_t> hval, bool use_table, int hbits, int qshift, bool full,
+                                           uint32_t* keys, WaveLds& L);
 
 // Row grow of the batch (rows of all bases are numbered consecutively) on the
 // calling wavefront.
@@ -983,8 +983,8 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
                                         const int64_t* __restrict__ basis_row0, int64_t grow,
                                         const float* __restrict__ tbme, int64_t* __restrict__ row_ptr,
                                         int64_t nrp, int32_t* __restrict__ col, float* __restrict__ val,
-                                        const float* __restrict__ gval, double* __restrict__ gacc,
-                                        lptr<uint32_t> hkey, lptr<float> hval, bool use_table, bool full,
+                                        const float* __restrict__ gval, unsigned long long* __restrict__ gacc,
+                                        lptr<uint32_t> hkey, lptr<int32_t> hval, bool use_table, bool full,
                                         uint32_t* keys, WaveLds& L)
 {
     // basis of the row (few bases: linear search)
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ void run_row(const BasisDev* __restrict__ bases, int 
     }
     const int bi = uniform(lo);
     run_row_at<MODE>(B, bi, i, i - (int)blk_off[bi], tbme, row_ptr, nrp, col, val, gval, gacc, hkey, hval, use_table,
-                     0, full, keys, L);
+                     0, 0, full, keys, L);
 }
 
 // Row i of basis B, row r of its block bi.
@@ -1011,8 +1011,9 @@ template <int MODE>
 __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int r, const float* __restrict__ tbme,
                                            int64_t* __restrict__ row_ptr, int64_t nrp, int32_t* __restrict__ col,
                                            float* __restrict__ val, const float* __restrict__ gval,
-                                           double* __restrict__ gacc, lptr<uint32_t> hkey, lptr<float> hval,
-                                           bool use_table, int hbits, bool full, uint32_t* keys, WaveLds& L)
+                                           unsigned long long* __restrict__ gacc, lptr<uint32_t> hkey,
+                                           lptr<int32_t> hval, bool use_table, int hbits, int qshift, bool full,
+                                           uint32_t* keys, WaveLds& L)
 {
     RowView R;
     R.B = &B;
@@ -1023,6 +1024,7 @@ __device__ __forceinline__ void run_row_at(const BasisDev& B, int bi, int i, int
     R.hval = hval;
     R.use_table = use_table;
     R.hbits = hbits;
+    R.qshift = qshift;
     R.gval = gval;
     R.col = col;
     R.val = val;
@@ -1173,23 +1175,24 @@ __global__ void __launch_bounds__(64 * WAVES)
     adjoint_kernel(const BasisDev* __restrict__ bases, const int32_t* __restrict__ blk_basis,
                    const int32_t* __restrict__ blk_local, int nblocks, const int64_t* __restrict__ tile_off,
                    int rows, int tile_n, const int64_t* __restrict__ row_ptr, int64_t nrp,
-                   const float* __restrict__ gval, const uint32_t* __restrict__ keys, double* __restrict__ gacc,
-                   int use_table, int persistent, unsigned long long* __restrict__ queue,
-                   const AdjBasis* __restrict__ adjb, uint64_t* __restrict__ recs, int64_t rec_cap,
-                   unsigned long long* __restrict__ rec_count, int32_t* __restrict__ hist, int xcd)
+                   const float* __restrict__ gval, const uint32_t* __restrict__ keys,
+                   unsigned long long* __restrict__ gacc, int use_table, int persistent,
+                   unsigned long long* __restrict__ queue, const AdjBasis* __restrict__ adjb,
+                   uint64_t* __restrict__ recs, int64_t rec_cap, unsigned long long* __restrict__ rec_count,
+                   int32_t* __restrict__ hist, const unsigned long long* __restrict__ gscale, int xcd)
 {
     constexpr int kSlots = 1 << SLOT_BITS;
     constexpr int kThreads = 64 * WAVES;
     __shared__ WaveLds lds[WAVES];
     __shared__ uint32_t hkey[kSlots];
-    __shared__ float hval[kSlots];
+    __shared__ int32_t hval[kSlots];  // fixed-point tile sums
     __shared__ int32_t bcur[kAdjMaxBuckets + 1];  // bucket counts, then cursors
     __shared__ int next_row;
     __shared__ int t_gb, t_ip0, t_in0, t_tp, t_tn, t_nKn, t_valid;
     __shared__ int64_t t_g, t_base;
     for (int s = threadIdx.x; s < kSlots; s += kThreads) {
         hkey[s] = kAdjEmpty;
-        hval[s] = 0.0f;
+        hval[s] = 0;
     }
     const int wid = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -1236,6 +1239,7 @@ __global__ void __launch_bounds__(64 * WAVES)
         const BasisDev& B = bases[xb];
         const int bi = uniform(cst(blk_local)[gb]);
         const int cnt = tp * tn;
+        const int qshift = uniform((int)(int64_t)cst(gscale)[xb]);
         for (;;) {
             int t = 0;
             if (lane == 0) t = atomicAdd(&next_row, 1);
@@ -1244,8 +1248,8 @@ __global__ void __launch_bounds__(64 * WAVES)
             const int u = t / tn, v = t - u * tn;
             const int r = (ip0 + u) * nKn + in0 + v;
             run_row_at<kAdjoint>(B, bi, uniform((int)cst(B.blk_off)[bi] + r), r, nullptr, const_cast<int64_t*>(row_ptr), nrp,
-                                 nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<float>)hval,
-                                 use_table != 0, SLOT_BITS, false, const_cast<uint32_t*>(keys), lds[wid]);
+                                 nullptr, nullptr, gval, gacc, (lptr<uint32_t>)hkey, (lptr<int32_t>)hval,
+                                 use_table != 0, SLOT_BITS, qshift, false, const_cast<uint32_t*>(keys), lds[wid]);
         }
         __syncthreads();
         if (use_table) {
@@ -1253,7 +1257,7 @@ __global__ void __launch_bounds__(64 * WAVES)
             // the record buffer (one device-scope atomic per tile), scan (one
             // wavefront; the histogram row of absolute positions goes to
             // global memory), scatter.  Without room (or without a record
-            // buffer) the slots go to the FP64 accumulators instead.
+            // buffer) the slots go to the int64 accumulators instead.
             const AdjBasis A = adjb ? adjb[xb] : AdjBasis{};
             const uint32_t base = (uint32_t)B.tbme0;
             if (recs) {
@@ -1295,9 +1299,9 @@ __global__ void __launch_bounds__(64 * WAVES)
                         const uint32_t k = hkey[s];
                         if (k != kAdjEmpty) {
                             const int p = atomicAdd(&bcur[(k - base) >> A.bits], 1);
-                            out[p] = (uint64_t)k | ((uint64_t)__float_as_uint(hval[s]) << 32);
+                            out[p] = (uint64_t)k | ((uint64_t)(uint32_t)hval[s] << 32);
                             hkey[s] = kAdjEmpty;
-                            hval[s] = 0.0f;
+                            hval[s] = 0;
                         }
                     }
                 }
@@ -1305,9 +1309,9 @@ __global__ void __launch_bounds__(64 * WAVES)
             for (int s = threadIdx.x; s < kSlots; s += kThreads) {
                 const uint32_t k = hkey[s];
                 if (k != kAdjEmpty) {  // no record buffer, or no room in it
-                    atomic_add_f64(glbw(gacc) + k, (double)hval[s]);
+                    atomic_add_i64(glbw(gacc) + k, (int64_t)hval[s]);
                     hkey[s] = kAdjEmpty;
-                    hval[s] = 0.0f;
+                    hval[s] = 0;
                 }
             }
         }
@@ -1321,21 +1325,22 @@ __global__ void __launch_bounds__(64 * WAVES)
 // records of bucket j start (row nb: where its last bucket ends).  Workgroup (bucket, c) sums the bucket's records of the c-th of
 // `chunks` equal slices of the basis' tiles: each wavefront takes 64 tiles at a
 // time (lane l: tile t0 + l, its segment of the bucket) and every lane walks
-// its own segment, four records per step; the sums meet in an FP64
+// its own segment, four records per step; the sums meet in an int64
 // shared-memory array of up to 2^kAdjReduceBits positions (a larger bucket is
 // summed window by window).  With one chunk the workgroup adds the direct
 // contributions in gacc and writes each position once as FP32; with several it
-// writes its FP64 partial sums to part[c] and adjoint_combine adds the chunks.
+// writes its int64 partial sums to part[c] and adjoint_combine adds the chunks.
 constexpr int kReduceThreads = 256;
 constexpr int kReduceWindow = 1 << kAdjReduceBits;
 
 __global__ void __launch_bounds__(kReduceThreads)
     adjoint_reduce(const BasisDev* __restrict__ bases, const AdjBasis* __restrict__ adjb, int nbases,
                    const uint64_t* __restrict__ recs, const int32_t* __restrict__ hist,
-                   const double* __restrict__ gacc, float* __restrict__ gtbme, int chunks,
-                   double* __restrict__ part, int64_t ntbme_all)
+                   const unsigned long long* __restrict__ gacc, float* __restrict__ gtbme, int chunks,
+                   unsigned long long* __restrict__ part, int64_t ntbme_all,
+                   const unsigned long long* __restrict__ gscale)
 {
-    __shared__ double acc[kReduceWindow];
+    __shared__ unsigned long long acc[kReduceWindow];
     const int64_t bucket = blockIdx.x / chunks;
     const int c = (int)(blockIdx.x - bucket * chunks);
     // basis of the bucket: largest x with bucket0 <= bucket
@@ -1346,6 +1351,7 @@ __global__ void __launch_bounds__(kReduceThreads)
         else hi = mid;
     }
     const int x = uniform(lo);
+    const int qshift = (int)(int64_t)gscale[x];
     const AdjBasis A = adjb[x];
     const int64_t tbme0 = bases[x].tbme0, ntbme = bases[x].ntbme;
     const int j = (int)(bucket - A.bucket0);
@@ -1357,7 +1363,7 @@ __global__ void __launch_bounds__(kReduceThreads)
     for (int64_t w0 = klo; w0 < khi; w0 += kReduceWindow) {
         const int64_t w1 = (w0 + kReduceWindow) < khi ? w0 + kReduceWindow : khi;
         const int wn = (int)(w1 - w0);
-        for (int i = threadIdx.x; i < wn; i += kReduceThreads) acc[i] = 0.0;
+        for (int i = threadIdx.x; i < wn; i += kReduceThreads) acc[i] = 0;
         __syncthreads();
         const int64_t kb = tbme0 + w0;  // global table position of acc[0]
         for (int64_t t0 = ta + (int64_t)wid * 64; t0 < tb; t0 += (int64_t)kWaves * 64) {
@@ -1375,19 +1381,19 @@ __global__ void __launch_bounds__(kReduceThreads)
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const int64_t k = (int64_t)(uint32_t)r[u] - kb;
-                    if (k >= 0 && k < wn) atomicAdd(&acc[k], (double)__uint_as_float((uint32_t)(r[u] >> 32)));
+                    if (k >= 0 && k < wn) atomicAdd(&acc[k], (unsigned long long)(int64_t)(int32_t)(r[u] >> 32));
                 }
             }
             for (; p < e; p++) {
                 const uint64_t r = glb(recs)[p];
                 const int64_t k = (int64_t)(uint32_t)r - kb;
-                if (k >= 0 && k < wn) atomicAdd(&acc[k], (double)__uint_as_float((uint32_t)(r >> 32)));
+                if (k >= 0 && k < wn) atomicAdd(&acc[k], (unsigned long long)(int64_t)(int32_t)(r >> 32));
             }
         }
         __syncthreads();
         if (chunks == 1) {
             for (int i = threadIdx.x; i < wn; i += kReduceThreads)
-                gtbme[kb + i] = (float)(acc[i] + gacc[kb + i]);
+                gtbme[kb + i] = fixed_to_f32(acc[i] + gacc[kb + i], qshift);
         } else {
             for (int i = threadIdx.x; i < wn; i += kReduceThreads) part[(int64_t)c * ntbme_all + kb + i] = acc[i];
         }
@@ -1395,15 +1401,30 @@ __global__ void __launch_bounds__(kReduceThreads)
     }
 }
 
-// gtbme = gacc + the chunks' partial sums, in chunk order
-__global__ void __launch_bounds__(256) adjoint_combine(const double* __restrict__ gacc,
-                                                       const double* __restrict__ part, int chunks, int64_t n,
-                                                       float* __restrict__ gtbme)
+// fixed-point shift of table position k of the batch (bases in table order)
+__device__ __forceinline__ int shift_of(const BasisDev* __restrict__ bases, int nbases,
+                                        const unsigned long long* __restrict__ gscale, int64_t k)
+{
+    int lo = 0, hi = nbases;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bases[mid].tbme0 <= k) lo = mid;
+        else hi = mid;
+    }
+    return (int)(int64_t)gscale[lo];
+}
+
+// gtbme = gacc + the chunks' partial sums
+__global__ void __launch_bounds__(256) adjoint_combine(const unsigned long long* __restrict__ gacc,
+                                                       const unsigned long long* __restrict__ part, int chunks,
+                                                       int64_t n, float* __restrict__ gtbme,
+                                                       const BasisDev* __restrict__ bases, int nbases,
+                                                       const unsigned long long* __restrict__ gscale)
 {
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
-        double v = gacc[k];
+        unsigned long long v = gacc[k];
         for (int c = 0; c < chunks; c++) v += part[(int64_t)c * n + k];
-        gtbme[k] = (float)v;
+        gtbme[k] = fixed_to_f32(v, shift_of(bases, nbases, gscale, k));
     }
 }
 
@@ -1493,11 +1514,57 @@ __global__ void fill_f64(double* __restrict__ x, int64_t n, double v)
         x[t] = v;
 }
 
-__global__ void f64_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n)
+__global__ void fixed_to_f32_n(const unsigned long long* __restrict__ x, float* __restrict__ y, int64_t n,
+                               const BasisDev* __restrict__ bases, int nbases,
+                               const unsigned long long* __restrict__ gscale)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x)
-        y[t] = (float)x[t];
+        y[t] = fixed_to_f32(x[t], shift_of(bases, nbases, gscale, t));
+}
+
+// max |G| over the stored entries of basis blockIdx.y, as the bits of a
+// non-negative FP32 (ordered like the values), into gscale[basis] (zero before)
+__global__ void __launch_bounds__(256) grad_absmax(const float* __restrict__ g, const int64_t* __restrict__ row_ptr,
+                                                   const BasisDev* __restrict__ bases,
+                                                   unsigned long long* __restrict__ gscale)
+{
+    const BasisDev& B = bases[blockIdx.y];
+    const int64_t n0 = row_ptr[B.row0], n1 = row_ptr[B.row0 + B.dim];
+    // 16-byte loads over the 16-byte aligned middle [a0, a1) of the range
+    const int64_t a0 = n0 + (int64_t)(((16 - ((uintptr_t)(g + n0) & 15)) & 15) / 4);
+    const int64_t a1 = a0 < n1 ? a0 + ((n1 - a0) & ~(int64_t)3) : a0;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    uint32_t m = 0;
+    if (a0 < a1) {
+        const float4* v = (const float4*)(g + a0);
+        for (int64_t t = tid; t < (a1 - a0) / 4; t += nt) {
+            const float4 x = v[t];
+            m = max(m, max(max(__float_as_uint(x.x) & 0x7fffffffu, __float_as_uint(x.y) & 0x7fffffffu),
+                           max(__float_as_uint(x.z) & 0x7fffffffu, __float_as_uint(x.w) & 0x7fffffffu)));
+        }
+        for (int64_t t = n0 + tid; t < a0; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+        for (int64_t t = a1 + tid; t < n1; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+    } else {
+        for (int64_t t = n0 + tid; t < n1; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(gscale + blockIdx.y, (unsigned long long)m);
+}
+
+// max |G| of each basis -> its fixed-point shift: with max |G| < 2^e and tiles
+// of at most 2^rows_log2 rows, a contribution rounds to an integer of
+// magnitude at most 2^(30 - rows_log2) and a tile's sum in one LDS slot stays
+// below 2^30.  A zero (or non-finite) maximum gives shift 0.
+__global__ void __launch_bounds__(256) adj_scale(unsigned long long* __restrict__ gscale, int nbases, int rows_log2)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbases) return;
+    const float m = __uint_as_float((uint32_t)gscale[b]);
+    int e = 0;
+    (void)frexpf(m, &e);  // m = f * 2^e, 0.5 <= f < 1
+    const int shift = (m > 0.0f && isfinite(m)) ? 30 - rows_log2 - e : 0;
+    gscale[b] = (unsigned long long)(int64_t)shift;
 }
 
 __global__ void nnz_of_bases(const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ first,
@@ -1614,17 +1681,27 @@ hipError_t launch_fill(const BasisDev* bases, int nb, const int64_t* basis_row0,
 
 hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basis, const int32_t* blk_local,
                       int nblocks, int64_t ntiles, int64_t* tile_off, AdjBasis* adjb, int64_t nbuckets, int chunks,
-                      double* part,
+                      unsigned long long* part,
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
-                      float* gtbme, double* gacc, uint64_t* recs, int64_t rec_cap, unsigned long long* rec_count,
-                      int32_t* hist, int64_t ntbme, const ci_tuning& t, unsigned long long* queue, hipStream_t s)
+                      float* gtbme, unsigned long long* gacc, uint64_t* recs, int64_t rec_cap,
+                      unsigned long long* rec_count, int32_t* hist, int64_t ntbme, const ci_tuning& t,
+                      unsigned long long* queue, unsigned long long* gscale, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
-    if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, gacc, ntbme, 0.0);
+    if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, (double*)gacc, ntbme, 0.0);  // int64 zeros
     const int use_table = ntbme < (int64_t)kAdjEmpty ? 1 : 0;
     const bool walked = nrows > 0 && ntiles > 0;
+    const int rows = keys ? t.adjk_rows : t.adj_rows, tile_n = keys ? t.adjk_tile_n : t.adj_tile_n;
+    // fixed-point shift from max |G| and the rows of a tile (at most max(rows, tile_n))
+    int rows_log2 = 0;
+    while ((1 << rows_log2) < (rows > tile_n ? rows : tile_n)) rows_log2++;
+    if (nbases <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64, dim3(1), dim3(256), 0, s, (double*)gscale, (int64_t)nbases, 0.0);  // zeros
+    if (nrows > 0)
+        hipLaunchKernelGGL(grad_absmax, dim3(nbases > 16 ? 64 : 1024 / nbases, nbases), dim3(256), 0, s, gval,
+                           row_ptr, bases, gscale);
+    hipLaunchKernelGGL(adj_scale, dim3(grid_for(nbases, 256)), dim3(256), 0, s, gscale, nbases, rows_log2);
     if (walked) {
-        const int rows = keys ? t.adjk_rows : t.adj_rows, tile_n = keys ? t.adjk_tile_n : t.adj_tile_n;
         hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, rows, tile_n,
                            tile_off, nbases, adjb);
         const bool wide = keys || t.adj_wide;  // 16 wavefronts, 16384-slot table
@@ -1642,21 +1719,23 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
             hipLaunchKernelGGL((adjoint_kernel<kAdjKeysWaves, kAdjKeysSlotBits>), dim3(grid), dim3(threads), 0, s,
                                bases, blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys,
                                gacc, use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count,
-                               hist, t.row_xcd);
+                               hist, gscale, t.row_xcd);
         else
             hipLaunchKernelGGL((adjoint_kernel<kAdjWaves, kAdjSlotBits>), dim3(grid), dim3(threads), 0, s, bases,
                                blk_basis, blk_local, nblocks, tile_off, rows, tile_n, row_ptr, nrp, gval, keys, gacc,
                                use_table, t.adj_persistent ? 1 : 0, queue, adjb, recs, rec_cap, rec_count, hist,
-                               t.row_xcd);
+                               gscale, t.row_xcd);
     }
     if (ntbme > 0) {
         if (use_table && walked && recs && nbuckets > 0) {
             const int ch = (chunks > 1 && part) ? chunks : 1;
             hipLaunchKernelGGL(adjoint_reduce, dim3((unsigned)(nbuckets * ch)), dim3(kReduceThreads), 0, s, bases,
-                               adjb, nbases, recs, hist, gacc, gtbme, ch, part, ntbme);
-            if (ch > 1) hipLaunchKernelGGL(adjoint_combine, dim3(gz), dim3(256), 0, s, gacc, part, ch, ntbme, gtbme);
+                               adjb, nbases, recs, hist, gacc, gtbme, ch, part, ntbme, gscale);
+            if (ch > 1)
+                hipLaunchKernelGGL(adjoint_combine, dim3(gz), dim3(256), 0, s, gacc, part, ch, ntbme, gtbme, bases,
+                                   nbases, gscale);
         } else
-            hipLaunchKernelGGL(f64_to_f32, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme);
+            hipLaunchKernelGGL(fixed_to_f32_n, dim3(gz), dim3(256), 0, s, gacc, gtbme, ntbme, bases, nbases, gscale);
     }
     return hipGetLastError();
 }
