@@ -32,7 +32,7 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, unsigned long long* gacc, uint64_t* recs, int64_t rec_cap,
                       unsigned long long* rec_count, int32_t* hist, int64_t ntbme, const ci_tuning& t,
-                      unsigned long long* queue, unsigned long long* gscale, hipStream_t s);
+                      unsigned long long* queue, unsigned long long* gscale, int64_t nnz_total, hipStream_t s);
 int adjoint_slots(bool wide);
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** p);
@@ -1339,7 +1339,8 @@ static hipError_t vjp_launch(const ci_basis* b, const int64_t* row_ptr, const fl
                       v.chunks > 1 ? (unsigned long long*)(w + v.part) : nullptr, b->nrows, row_ptr, b->n_rowptr,
                       grad_val, keys, grad_tbme, (unsigned long long*)w,
                       v.records ? (uint64_t*)(w + v.recs) : nullptr, v.rec_cap, b->d_rec_count,
-                      v.records ? (int32_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, b->d_gscale, s);
+                      v.records ? (int32_t*)(w + v.hist) : nullptr, b->n_tbme, tt, b->d_queue, b->d_gscale,
+                      b->nnz_total, s);
 }
 
 size_t ci_vjp_work_bytes(const ci_basis* b) { return (b && b->ready) ? work_bytes_for(b) : 0; }

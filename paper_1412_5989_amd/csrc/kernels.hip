@@ -1523,33 +1523,64 @@ __global__ void fixed_to_f32_n(const unsigned long long* __restrict__ x, float* 
         y[t] = fixed_to_f32(x[t], shift_of(bases, nbases, gscale, t));
 }
 
-// max |G| over the stored entries of basis blockIdx.y, as the bits of a
-// non-negative FP32 (ordered like the values), into gscale[basis] (zero before)
-__global__ void __launch_bounds__(256) grad_absmax(const float* __restrict__ g, const int64_t* __restrict__ row_ptr,
-                                                   const BasisDev* __restrict__ bases,
-                                                   unsigned long long* __restrict__ gscale)
+// max |G| of each basis over its stored entries, as the bits of a
+// non-negative FP32 (ordered like the values), into gscale[basis] (zero
+// before).  The entries of the batch (bases in row order hold consecutive
+// entry ranges) are cut into chunks of kAbsChunk; workgroup c takes chunks c,
+// c + gridDim.x, ... and reduces each basis a chunk overlaps (nearly always
+// one), so large and small bases get workgroups in proportion to their entries.
+constexpr int kAbsThreads = 256;
+constexpr int64_t kAbsChunk = 16384;
+
+__device__ __forceinline__ uint32_t absmax_range(const float* __restrict__ g, int64_t n0, int64_t n1)
 {
-    const BasisDev& B = bases[blockIdx.y];
-    const int64_t n0 = row_ptr[B.row0], n1 = row_ptr[B.row0 + B.dim];
     // 16-byte loads over the 16-byte aligned middle [a0, a1) of the range
-    const int64_t a0 = n0 + (int64_t)(((16 - ((uintptr_t)(g + n0) & 15)) & 15) / 4);
-    const int64_t a1 = a0 < n1 ? a0 + ((n1 - a0) & ~(int64_t)3) : a0;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t a0 = min(n1, n0 + (int64_t)(((16 - ((uintptr_t)(g + n0) & 15)) & 15) / 4));
+    const int64_t a1 = a0 + ((n1 - a0) & ~(int64_t)3);
     uint32_t m = 0;
-    if (a0 < a1) {
-        const float4* v = (const float4*)(g + a0);
-        for (int64_t t = tid; t < (a1 - a0) / 4; t += nt) {
-            const float4 x = v[t];
-            m = max(m, max(max(__float_as_uint(x.x) & 0x7fffffffu, __float_as_uint(x.y) & 0x7fffffffu),
-                           max(__float_as_uint(x.z) & 0x7fffffffu, __float_as_uint(x.w) & 0x7fffffffu)));
-        }
-        for (int64_t t = n0 + tid; t < a0; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
-        for (int64_t t = a1 + tid; t < n1; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
-    } else {
-        for (int64_t t = n0 + tid; t < n1; t += nt) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+    const float4* v = (const float4*)(g + a0);
+    for (int64_t t = threadIdx.x; t < (a1 - a0) / 4; t += kAbsThreads) {
+        const float4 x = v[t];
+        m = max(m, max(max(__float_as_uint(x.x) & 0x7fffffffu, __float_as_uint(x.y) & 0x7fffffffu),
+                       max(__float_as_uint(x.z) & 0x7fffffffu, __float_as_uint(x.w) & 0x7fffffffu)));
     }
-    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(gscale + blockIdx.y, (unsigned long long)m);
+    for (int64_t t = n0 + threadIdx.x; t < a0; t += kAbsThreads) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+    for (int64_t t = a1 + threadIdx.x; t < n1; t += kAbsThreads) m = max(m, __float_as_uint(g[t]) & 0x7fffffffu);
+    return m;
+}
+
+__global__ void __launch_bounds__(kAbsThreads) grad_absmax(const float* __restrict__ g,
+                                                           const int64_t* __restrict__ row_ptr,
+                                                           const BasisDev* __restrict__ bases, int nbases,
+                                                           unsigned long long* __restrict__ gscale)
+{
+    __shared__ uint32_t wmax[kAbsThreads / 64];
+    const int64_t n = row_ptr[bases[nbases - 1].row0 + bases[nbases - 1].dim];  // entries of all bases
+    for (int64_t c0 = (int64_t)blockIdx.x * kAbsChunk; c0 < n; c0 += (int64_t)gridDim.x * kAbsChunk) {
+        const int64_t c1 = min(c0 + kAbsChunk, n);
+        // the basis whose entries hold c0
+        int lo = 0, hi = nbases;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (row_ptr[bases[mid].row0] <= c0) lo = mid;
+            else hi = mid;
+        }
+        for (int b = lo; b < nbases; b++) {
+            const int64_t s0 = max(c0, row_ptr[bases[b].row0]);
+            const int64_t s1 = min(c1, row_ptr[bases[b].row0 + bases[b].dim]);
+            if (s0 >= c1) break;
+            uint32_t m = s0 < s1 ? absmax_range(g, s0, s1) : 0u;
+            for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+            if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t w = 0;
+                for (int k = 0; k < kAbsThreads / 64; k++) w = max(w, wmax[k]);
+                if (w) atomicMax(gscale + b, (unsigned long long)w);
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // max |G| of each basis -> its fixed-point shift: with max |G| < 2^e and tiles
@@ -1685,7 +1716,7 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
                       int64_t nrows, const int64_t* row_ptr, int64_t nrp, const float* gval, const uint32_t* keys,
                       float* gtbme, unsigned long long* gacc, uint64_t* recs, int64_t rec_cap,
                       unsigned long long* rec_count, int32_t* hist, int64_t ntbme, const ci_tuning& t,
-                      unsigned long long* queue, unsigned long long* gscale, hipStream_t s)
+                      unsigned long long* queue, unsigned long long* gscale, int64_t nnz_total, hipStream_t s)
 {
     const unsigned gz = grid_for(ntbme, 256) < 4096 ? grid_for(ntbme, 256) : 4096;
     if (ntbme > 0) hipLaunchKernelGGL(fill_f64, dim3(gz), dim3(256), 0, s, (double*)gacc, ntbme, 0.0);  // int64 zeros
@@ -1697,9 +1728,12 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
     while ((1 << rows_log2) < (rows > tile_n ? rows : tile_n)) rows_log2++;
     if (nbases <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_f64, dim3(1), dim3(256), 0, s, (double*)gscale, (int64_t)nbases, 0.0);  // zeros
-    if (nrows > 0)
-        hipLaunchKernelGGL(grad_absmax, dim3(nbases > 16 ? 64 : 1024 / nbases, nbases), dim3(256), 0, s, gval,
-                           row_ptr, bases, gscale);
+    if (nrows > 0) {
+        // one workgroup per kAbsChunk entries (known on the host after the count), at most 2^20
+        const int64_t ch = nnz_total >= 0 ? (nnz_total + kAbsChunk - 1) / kAbsChunk : 4096;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ch, (int64_t)1 << 20));
+        hipLaunchKernelGGL(grad_absmax, dim3(grid), dim3(kAbsThreads), 0, s, gval, row_ptr, bases, nbases, gscale);
+    }
     hipLaunchKernelGGL(adj_scale, dim3(grid_for(nbases, 256)), dim3(256), 0, s, gscale, nbases, rows_log2);
     if (walked) {
         hipLaunchKernelGGL(tile_offsets, dim3(1), dim3(256), 0, s, bases, blk_basis, blk_local, nblocks, rows, tile_n,
