@@ -663,7 +663,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32+f32 (f64 accumulation)",
+        "dtype": "int32+f32 (f64 sums in the fill, int64 fixed-point sums in the adjoint)",
         "data": "synthetic: seeded N(0,1) MeV two-body table, seeded psi for the upstream gradient",
         "config": {"workload": args.workload, "Z": prob[0], "N": prob[1], "nmax": prob[2],
                    "two_m": prob[3], "parity": prob[4], "dim": D, "nnz": nnz, "n_tbme": m["n_tbme"],
