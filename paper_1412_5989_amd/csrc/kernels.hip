@@ -103,8 +103,9 @@ __device__ __forceinline__ cptr<T> cst(const T* p)
 }
 
 // Adjoint: the rows of a workgroup scatter into a shared LDS table first
-// (open addressing on the global table position, FP32 partial sums), and each
-// occupied slot is added to the FP64 accumulator once at the end.  Table keys
+// (open addressing on the global table position, int32 fixed-point partial
+// sums), and each occupied slot is added to the int64 accumulator once at the
+// end.  Table keys
 // repeat across consecutive rows (the same proton move for every row of one
 // proton determinant, and overlapping neutron moves), so the number of
 // device-scope atomics drops by that reuse factor.  A key that finds no slot
@@ -1161,11 +1162,11 @@ __global__ void __launch_bounds__(256) tile_offsets(const BasisDev* __restrict__
 // Adjoint: a workgroup takes one tile of rows (above), its wavefronts take
 // the tile's rows one at a time from a shared counter, and the contributions
 // meet in the LDS accumulator table.  When the tile is done its occupied slots
-// are written out as (table position, FP32 partial sum) records, grouped by
+// are written out as (table position, int32 fixed-point partial sum) records, grouped by
 // bucket of the basis' table (a histogram row per tile gives each bucket's
 // segment), with plain stores; adjoint_reduce sums them.  No device-scope
 // atomic is issued except for a contribution that finds no slot within
-// kAdjProbes probes (it goes to the FP64 accumulator gacc directly).
+// kAdjProbes probes (it goes to the int64 accumulator gacc directly).
 // persistent == 0: tile = workgroup index; persistent == 1: a persistent grid
 // takes tiles from the work counter *queue (zero at launch).  use_table == 0
 // (global table positions do not fit 32 bits): every contribution goes to
