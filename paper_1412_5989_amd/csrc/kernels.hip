@@ -1527,11 +1527,11 @@ __global__ void fixed_to_f32_n(const unsigned long long* __restrict__ x, float* 
 // max |G| of each basis over its stored entries, as the bits of a
 // non-negative FP32 (ordered like the values), into gscale[basis] (zero
 // before).  The entries of the batch (bases in row order hold consecutive
-// entry ranges) are cut into chunks of kAbsChunk; workgroup c takes chunks c,
-// c + gridDim.x, ... and reduces each basis a chunk overlaps (nearly always
-// one), so large and small bases get workgroups in proportion to their entries.
+// entry ranges) are cut into chunks of `chunk` entries (a multiple of 4);
+// workgroup c takes chunks c, c + gridDim.x, ... and reduces each basis a chunk
+// overlaps (nearly always one), so large and small bases get workgroups in
+// proportion to their entries.
 constexpr int kAbsThreads = 256;
-constexpr int64_t kAbsChunk = 16384;
 
 __device__ __forceinline__ uint32_t absmax_range(const float* __restrict__ g, int64_t n0, int64_t n1)
 {
@@ -1553,12 +1553,12 @@ __device__ __forceinline__ uint32_t absmax_range(const float* __restrict__ g, in
 __global__ void __launch_bounds__(kAbsThreads) grad_absmax(const float* __restrict__ g,
                                                            const int64_t* __restrict__ row_ptr,
                                                            const BasisDev* __restrict__ bases, int nbases,
-                                                           unsigned long long* __restrict__ gscale)
+                                                           int64_t chunk, unsigned long long* __restrict__ gscale)
 {
     __shared__ uint32_t wmax[kAbsThreads / 64];
     const int64_t n = row_ptr[bases[nbases - 1].row0 + bases[nbases - 1].dim];  // entries of all bases
-    for (int64_t c0 = (int64_t)blockIdx.x * kAbsChunk; c0 < n; c0 += (int64_t)gridDim.x * kAbsChunk) {
-        const int64_t c1 = min(c0 + kAbsChunk, n);
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n; c0 += (int64_t)gridDim.x * chunk) {
+        const int64_t c1 = min(c0 + chunk, n);
         // the basis whose entries hold c0
         int lo = 0, hi = nbases;
         while (hi - lo > 1) {
@@ -1730,10 +1730,15 @@ hipError_t launch_vjp(const BasisDev* bases, int nbases, const int32_t* blk_basi
     if (nbases <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_f64, dim3(1), dim3(256), 0, s, (double*)gscale, (int64_t)nbases, 0.0);  // zeros
     if (nrows > 0) {
-        // one workgroup per kAbsChunk entries (known on the host after the count), at most 2^20
-        const int64_t ch = nnz_total >= 0 ? (nnz_total + kAbsChunk - 1) / kAbsChunk : 4096;
+        // about 2048 workgroups (a few per CU, each streaming a long chunk) once
+        // the host knows the entries (after the count); chunks of 16Ki..1Mi entries
+        const int64_t chunk =
+            nnz_total >= 0 ? std::min<int64_t>((int64_t)1 << 20, std::max<int64_t>(16384, (nnz_total / 2048 + 3) & ~(int64_t)3))
+                           : 16384;
+        const int64_t ch = nnz_total >= 0 ? (nnz_total + chunk - 1) / chunk : 4096;
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ch, (int64_t)1 << 20));
-        hipLaunchKernelGGL(grad_absmax, dim3(grid), dim3(kAbsThreads), 0, s, gval, row_ptr, bases, nbases, gscale);
+        hipLaunchKernelGGL(grad_absmax, dim3(grid), dim3(kAbsThreads), 0, s, gval, row_ptr, bases, nbases, chunk,
+                           gscale);
     }
     hipLaunchKernelGGL(adj_scale, dim3(grid_for(nbases, 256)), dim3(256), 0, s, gscale, nbases, rows_log2);
     if (walked) {
