@@ -1299,8 +1299,9 @@ static VjpLayout vjp_layout(const ci_basis* b, const ci_tuning& t, bool stored, 
 
 // Launch shapes the autotuner tries for the adjoint (tile rows, neutron width).
 // walking adjoint: (rows, neutron width, wide table)
-static const int kWalkTiles[][3] = {{32, 8, 0}, {64, 8, 0}, {64, 16, 0}, {128, 16, 0},
-                                    {128, 16, 1}, {256, 16, 1}, {256, 32, 1}, {512, 32, 1}};
+static const int kWalkTiles[][3] = {{32, 8, 0},   {64, 8, 0},   {64, 16, 0},  {128, 16, 0}, {64, 16, 1},
+                                    {96, 16, 1},  {128, 16, 1}, {192, 16, 1}, {256, 16, 1}, {256, 32, 1},
+                                    {512, 32, 1}};
 static const int kStoredTiles[][2] = {{64, 8}, {96, 8}, {128, 8}, {96, 16}, {192, 8}, {256, 16}};
 
 static size_t work_bytes_for(const ci_basis* b)

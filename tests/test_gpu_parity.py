@@ -434,7 +434,8 @@ def test_tuning_validation_and_tuner(ci):
     say("tuned", t)
     assert t["row_waves"] in (4, 8) and t["row_grab"] in (0, 1, 4, 16)
     assert (t["adj_rows"], t["adj_tile_n"], t["adj_wide"]) in (
-        (32, 8, 0), (64, 8, 0), (64, 16, 0), (128, 16, 0), (128, 16, 1), (256, 16, 1), (256, 32, 1), (512, 32, 1))
+        (32, 8, 0), (64, 8, 0), (64, 16, 0), (128, 16, 0), (64, 16, 1), (96, 16, 1), (128, 16, 1), (192, 16, 1),
+        (256, 16, 1), (256, 32, 1), (512, 32, 1))
     assert (t["adjk_rows"], t["adjk_tile_n"]) in ((64, 8), (96, 8), (128, 8), (96, 16), (192, 8), (256, 16))
     assert t["adj_persistent"] in (0, 1) and t["adjk_persistent"] in (0, 1)
     torch.cuda.synchronize()
