@@ -207,8 +207,9 @@ int ci_hamiltonian_fill(const ci_basis* b, const float* tbme, const int64_t* row
  * Integer sums have no order, so the result is the same bit for bit on every
  * run and for every adj_flush, adj_persistent, adj_wide and row_xcd at one
  * tile shape (adj_rows, adj_tile_n); other tile shapes round the contributions
- * on another grid and agree to ~1e-6 of max |grad_val|.  grad_val must be
- * finite.  work: device scratch of at least ci_vjp_work_bytes(b) bytes (int64
+ * on another grid (spacing at most 2^-(29 - ceil(log2 rows)) of max |grad_val|
+ * per basis, rows = max(adj_rows, adj_tile_n)) and agree to that rounding.
+ * grad_val must be finite.  work: device scratch of at least ci_vjp_work_bytes(b) bytes (int64
  * accumulators, tile records).  Asynchronous. */
 int ci_hamiltonian_vjp(const ci_basis* b, const int64_t* row_ptr, const float* grad_val,
                        float* grad_tbme, void* work, size_t work_bytes, ci_stream stream);
